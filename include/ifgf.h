@@ -1,0 +1,180 @@
+/*
+ * ifgf.h -- C ABI of the MI355X (gfx950) IFGF operator library.
+ *
+ * The library evaluates the discrete operator of Bauinger and Bruno, "IFGF:
+ * Interpolated Factored Green Function method" (arXiv 2010.02857), Sec. 2,
+ * eq. (field1) with the Helmholtz kernel of eq. (greensfunction):
+ *
+ *     I_r(x_l) = sum_{m != l} a_r(x_m) e^{i k |x_l - x_m|} / (4 pi |x_l - x_m|),
+ *
+ * for N points x_1..x_N that serve as both sources and targets, by the
+ * O(N log N) IFGF algorithm of Sec. 3.3 (Algorithm 1): octree of boxes, cone
+ * segments per box, leaf-level direct evaluation at the cone interpolation
+ * points, child-to-parent Chebyshev interpolation with re-centring by the
+ * centred factor, direct near-field sums, and interpolation at the cousin
+ * targets of every level.
+ *
+ * Conventions common to every call:
+ *   - Every call returns an ifgf_status; no C++ exception crosses the ABI.
+ *     On failure ifgf_last_error() returns a message for the calling thread.
+ *   - "device" pointers are HIP device allocations on the GPU that was
+ *     current when the plan was created; "host" pointers are ordinary memory.
+ *   - Complex arrays are interleaved (re, im).  With precision IFGF_FP64 they
+ *     are complex128 (two doubles); with IFGF_MIXED complex64 (two floats).
+ *   - A batch of nrhs vectors is laid out [nrhs][n]: vector r occupies
+ *     elements r*n .. r*n + n - 1, in the order the points were given.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).  The
+ *     apply calls are asynchronous on it; argument errors are reported
+ *     synchronously, kernel launch failures as IFGF_E_HIP.
+ *   - A plan owns all device memory it allocates (tree, cone tables, cone
+ *     value buffers).  It may be used by one stream at a time: its
+ *     workspaces are shared, and concurrent calls on one plan race.
+ */
+#ifndef IFGF_H
+#define IFGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifgf_plan* ifgf_plan_t;
+
+typedef enum {
+    IFGF_OK = 0,
+    IFGF_E_INVALID_ARG = 1,   /* bad argument (pointer, size, duplicate points) */
+    IFGF_E_OUT_OF_MEMORY = 2, /* host or device allocation failed, or the
+                                 workspace limit is too small                 */
+    IFGF_E_HIP = 3,           /* a HIP runtime call or kernel launch failed   */
+    IFGF_E_UNSUPPORTED = 4,   /* valid request this build cannot serve        */
+    IFGF_E_INTERNAL = 5
+} ifgf_status;
+
+typedef enum {
+    IFGF_FP64 = 0,  /* all arithmetic in FP64; complex128 input and output    */
+    IFGF_MIXED = 1  /* FP64 for distances, the phase k r and its reduction
+                       modulo 2 pi, box centres and the cone-coordinate map
+                       (s, theta, phi); FP32 for interpolation, kernel values
+                       and accumulation; complex64 input and output           */
+} ifgf_precision;
+
+#define IFGF_MAX_LEVELS 24
+
+/* Plan options.  Zero-initialised fields take the defaults noted. */
+typedef struct {
+    int32_t leaf_ns;         /* radial cone intervals per leaf box, n_{s,D}
+                                (0: 1, the paper's choice, Sec. 4)            */
+    int32_t leaf_nc;         /* polar cone intervals per leaf box, n_{C,D};
+                                there are 2 n_{C,D} azimuthal ones (0: 2)    */
+    int32_t precision;       /* ifgf_precision (0: IFGF_FP64)                 */
+    int32_t max_nrhs;        /* largest nrhs an apply call may pass; sizes
+                                the workspaces (0: 16)                        */
+    int32_t store_levels;    /* cone values of every level kept after an
+                                apply for ifgf_grad_targets: 1 keep, 0
+                                recompute, -1 (or 0 from zero-init): decided
+                                by memory                                     */
+    int32_t host_only;       /* 1: build the hierarchy on the host only (no
+                                GPU use); apply calls return
+                                IFGF_E_UNSUPPORTED but ifgf_plan_stats works */
+    int32_t no_dilate;       /* 1: mark only the cone a query point falls in;
+                                0: also mark the neighbouring cone when the
+                                point lies within 1e-10 (local coordinates)
+                                of a cone face, so that the GPU's own
+                                evaluation of the point's cone always finds
+                                computed data                                 */
+    int32_t reserved0;
+    size_t workspace_limit;  /* device bytes the plan may allocate, 0: none  */
+} ifgf_options;
+
+/* Per-level counts of a plan; entry d is level d (1-based). */
+typedef struct {
+    int32_t D;                               /* levels                          */
+    int32_t n_points;
+    double H1;                               /* root box side                   */
+    double x1[3];                            /* root box centre                 */
+    double kappa;
+    int32_t ps, pang;                        /* node counts per cone direction  */
+    int32_t ns[IFGF_MAX_LEVELS + 1];         /* radial intervals n_{s,d}        */
+    int32_t nc[IFGF_MAX_LEVELS + 1];         /* polar intervals n_{C,d}         */
+    int64_t n_boxes[IFGF_MAX_LEVELS + 1];    /* relevant boxes |R_B^d|          */
+    int64_t n_cones[IFGF_MAX_LEVELS + 1];    /* relevant cone segments |R_C^d|  */
+    int64_t n_cousin_boxes[IFGF_MAX_LEVELS + 1];  /* sum over boxes of |M B|    */
+    int64_t max_cousin_boxes[IFGF_MAX_LEVELS + 1];
+    int64_t n_cousin_evals[IFGF_MAX_LEVELS + 1];  /* (target, cousin box) pairs */
+    int64_t n_parent_evals[IFGF_MAX_LEVELS + 1];  /* (parent node, child) pairs
+                                                     interpolated at level d   */
+    int64_t n_leaf_pairs;                    /* (cone node, source) pairs, d=D */
+    int64_t n_near_pairs;                    /* directly summed pairs           */
+    int64_t n_dilated;                       /* cones marked only by dilation   */
+    int64_t device_bytes;                    /* device memory held by the plan  */
+    double t_plan_s;                         /* host seconds to build the plan  */
+} ifgf_stats;
+
+/* Create a plan for the points (Sec. 3.3.2: box octree, relevant boxes,
+ * neighbours and cousins, cone segments per level and the relevant ones).
+ *   points   host, n x 3 row-major FP64; copied, the caller keeps ownership.
+ *            Points must be pairwise different (Sec. 2); two equal points
+ *            give IFGF_E_INVALID_ARG.
+ *   n        number of points, >= 2.
+ *   k        wavenumber kappa >= 0 (0: the Laplace limit 1/(4 pi r)).
+ *   levels   number of levels D >= 2, or 0: D = 1 + round(log2(4 H_1 k /
+ *            (2 pi))) so that the leaf boxes are about a quarter wavelength
+ *            wide (Sec. 4); for k = 0 the smallest D with at most 8 points
+ *            per relevant leaf box.
+ *   degrees  {P_s, P_ang}: Chebyshev nodes per cone in s and in each angle
+ *            (Sec. 3.2); NULL: {3, 5}.  Supported: {3,5}, {4,6}, {2,3}.
+ *   opt      NULL for defaults.
+ *   plan     receives the new plan.                                        */
+ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t levels,
+                             const int32_t* degrees, const ifgf_options* opt, ifgf_plan_t* plan);
+
+/* out = IFGF approximation of the operator applied to the densities
+ * (Algorithm 1).
+ *   densities  device, [nrhs][n] complex (dtype by precision); read only.
+ *   nrhs       1 .. max_nrhs.
+ *   out        device, [nrhs][n] complex, overwritten; must not alias the
+ *              densities.                                                  */
+ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, int32_t nrhs, void* out, void* stream);
+
+/* out = adjoint operator applied to v:
+ *   out_r(x_m) = sum_{l != m} conj(G(x_l, x_m)) v_r(x_l),
+ * evaluated by the same hierarchy with the conjugated kernel (k -> -k, which
+ * conjugates every factor e^{i k .} while the real interpolation weights are
+ * unchanged).  Same layouts and rules as ifgf_apply.                       */
+ifgf_status ifgf_apply_adjoint(ifgf_plan_t plan, const void* v, int32_t nrhs, void* out, void* stream);
+
+/* Gradient of a real loss L(I) with respect to the target coordinates, the
+ * sources held fixed:
+ *   grad_xyz[l][c] = sum_r Re( conj(g_r(x_l)) * dI_r(x_l)/dx_{l,c} ),
+ * where g = dL/dRe(I) + i dL/dIm(I) (PyTorch's convention for complex
+ * gradients) and dI/dx differentiates the IFGF approximation: the near-field
+ * kernels and, at every level, the centred factor times the Chebyshev
+ * interpolant in (s, theta, phi).
+ *   densities  device [nrhs][n] complex, the forward input.
+ *   grad_out   device [nrhs][n] complex, g.
+ *   grad_xyz   device [n][3] FP64, overwritten.
+ * If the plan keeps the cone values of every level (store_levels) and the
+ * last ifgf_apply used the same densities, they are reused; otherwise they
+ * are recomputed.                                                           */
+ifgf_status ifgf_grad_targets(ifgf_plan_t plan, const void* densities, const void* grad_out,
+                              int32_t nrhs, double* grad_xyz, void* stream);
+
+/* Per-level counts of the hierarchy (host, no GPU work). */
+ifgf_status ifgf_plan_stats(ifgf_plan_t plan, ifgf_stats* out);
+
+/* Synchronises the plan's last stream and reports how many interpolation
+ * queries found no computed cone since the plan was created (must be 0). */
+ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses);
+
+/* Releases the plan and all memory it owns.  NULL is accepted. */
+ifgf_status ifgf_plan_destroy(ifgf_plan_t plan);
+
+const char* ifgf_status_string(ifgf_status s);
+const char* ifgf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFGF_H */

@@ -25,8 +25,11 @@
  *       n_{.,d-1} = a_d n_{.,d} with a_d = 2 iff 2 kappa H_d > 1 (Sec. 3.3.1).
  *   R6  Root box: centre = bounding-box midpoint, side = largest extent; box
  *       indices are clamped to the last box on the upper faces.
- *   R7  Cone index = floor of coordinate / interval, clamped to the last
- *       interval; phi = atan2(y, x) shifted into [0, 2 pi).
+ *   R7  Cone index = the half-open interval of eq. (defconedomain) holding
+ *       the coordinate: floor(coordinate / interval length), where a value
+ *       within 1e-10 (in interval units) below a boundary counts as on it
+ *       and so falls in the interval above; clamped to the last interval;
+ *       phi = atan2(y, x) shifted into [0, 2 pi) and wrapped at 2 pi.
  *   R8  Relevance rule (ii) marks the child cones containing the nodes of the
  *       parent's relevant cones (the node-based narrative of Sec. 3.3.2).
  *   R9  The self term is skipped by index.
@@ -268,7 +271,17 @@ void oracle_cone_coords(const double* c, double H, int32_t ns, int32_t nc, const
     double phi = atan2(v[1], v[0]);
     if (phi < 0.0) phi += 2.0 * PI;
     double ds = eta_const() / ns, dth = PI / nc, dph = PI / nc;
-    int32_t is = (int32_t)floor(s / ds), it = (int32_t)floor(theta / dth), ip = (int32_t)floor(phi / dph);
+    /* Interval index of coordinate / interval length q.  The intervals of
+     * eq. (defconedomain) are half-open, so a point on a boundary belongs to
+     * the interval above it; q within 1e-10 below an integer counts as on
+     * that boundary (reading R7).  phi wraps around at 2 pi. */
+    const double tie = 1e-10;
+    double qs = s / ds, qt = theta / dth, qp = phi / dph;
+    int32_t is = (int32_t)floor(qs + tie), it = (int32_t)floor(qt + tie), ip = (int32_t)floor(qp + tie);
+    if (ip >= 2 * nc) {
+        ip -= 2 * nc;
+        qp -= 2 * nc;
+    }
     if (is > ns - 1) is = ns - 1;
     if (it > nc - 1) it = nc - 1;
     if (ip > 2 * nc - 1) ip = 2 * nc - 1;
@@ -278,9 +291,9 @@ void oracle_cone_coords(const double* c, double H, int32_t ns, int32_t nc, const
     idx[0] = is;
     idx[1] = it;
     idx[2] = ip;
-    loc[0] = 2.0 * (s - is * ds) / ds - 1.0;
-    loc[1] = 2.0 * (theta - it * dth) / dth - 1.0;
-    loc[2] = 2.0 * (phi - ip * dph) / dph - 1.0;
+    loc[0] = 2.0 * (qs - is) - 1.0;
+    loc[1] = 2.0 * (qt - it) - 1.0;
+    loc[2] = 2.0 * (qp - ip) - 1.0;
     if (sth) {
         sth[0] = s;
         sth[1] = theta;

@@ -1,0 +1,308 @@
+// C ABI of the IFGF library (declared in include/ifgf.h).
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ifgf_internal.hpp"
+
+struct ifgf_plan {
+    ifgf::DevicePlan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ifgf_status fail(ifgf_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+ifgf_status hip_fail(hipError_t e, const char* where)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(IFGF_E_OUT_OF_MEMORY, std::string(where) + ": " + hipGetErrorString(e));
+    return fail(IFGF_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t upload(ifgf::DevicePlan& p, const std::vector<T>& v, const T** out)
+{
+    *out = nullptr;
+    if (v.empty()) return hipSuccess;
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    p.allocs.push_back(d);
+    p.tree_bytes += v.size() * sizeof(T);
+    e = hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    *out = (const T*)d;
+    return e;
+}
+
+void release(ifgf::DevicePlan& p)
+{
+    if (p.device >= 0) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p.device);
+        (void)hipDeviceSynchronize();
+        for (void* q : p.ws_allocs) (void)hipFree(q);
+        for (void* q : p.allocs) (void)hipFree(q);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
+    p.ws_allocs.clear();
+    p.allocs.clear();
+}
+
+hipError_t upload_plan(ifgf::DevicePlan& p)
+{
+    using namespace ifgf;
+    HostPlan& hp = p.hp;
+    hipError_t e;
+    const double* dp = nullptr;
+    const int32_t* ip = nullptr;
+    if ((e = upload(p, hp.pts, &dp)) != hipSuccess) return e;
+    p.pts = const_cast<double*>(dp);
+    if ((e = upload(p, hp.perm, &ip)) != hipSuccess) return e;
+    p.perm = const_cast<int32_t*>(ip);
+    std::vector<int32_t> iperm(hp.n);
+    for (int64_t i = 0; i < hp.n; ++i) iperm[hp.perm[i]] = (int32_t)i;
+    if ((e = upload(p, iperm, &ip)) != hipSuccess) return e;
+    p.iperm = const_cast<int32_t*>(ip);
+    void* m = nullptr;
+    if ((e = hipMalloc(&m, sizeof(unsigned long long))) != hipSuccess) return e;
+    p.allocs.push_back(m);
+    p.miss = (unsigned long long*)m;
+    if ((e = hipMemset(m, 0, sizeof(unsigned long long))) != hipSuccess) return e;
+    p.L.assign(hp.D + 1, LevelDev{});
+    for (int d = 1; d <= hp.D; ++d) {
+        HostLevel& H = hp.L[d];
+        LevelDev& L = p.L[d];
+        L.nbox = (int)H.nbox;
+        L.ns = H.ns;
+        L.nc = H.nc;
+        L.ncell = H.ncell;
+        L.W = H.W;
+        L.nslots = (int)H.nslots;
+        L.H = H.H;
+        L.h = H.h;
+        L.ds = H.ds;
+        L.dang = H.dang;
+        bool interp_level = d >= 3;
+        bool parent_of_interp = d >= 3 && d < hp.D;
+        if (d == hp.D || interp_level) {
+            if ((e = upload(p, H.box_start, &L.box_start)) != hipSuccess) return e;
+            if ((e = upload(p, H.box_ctr, &L.box_ctr)) != hipSuccess) return e;
+            if ((e = upload(p, H.pt_box, &L.pt_box)) != hipSuccess) return e;
+        }
+        if (d == hp.D)
+            if ((e = upload(p, H.nbr_start, &L.nbr_start)) != hipSuccess || (e = upload(p, H.nbr, &L.nbr)) != hipSuccess)
+                return e;
+        if (interp_level) {
+            if ((e = upload(p, H.box_oct, &L.box_oct)) != hipSuccess) return e;
+            if ((e = upload(p, H.cou_start, &L.cou_start)) != hipSuccess) return e;
+            if ((e = upload(p, H.cou, &L.cou)) != hipSuccess) return e;
+            if ((e = upload(p, H.cell_base, &L.cell_base)) != hipSuccess) return e;
+            const uint64_t* mk = nullptr;
+            if ((e = upload(p, H.cell_mask, &mk)) != hipSuccess) return e;
+            L.cell_mask = (const unsigned long long*)mk;
+            if ((e = upload(p, H.slot_box, &L.slot_box)) != hipSuccess) return e;
+            if ((e = upload(p, H.slot_cone, &L.slot_cone)) != hipSuccess) return e;
+            if ((e = upload(p, H.node_r, &L.node_r)) != hipSuccess) return e;
+            if ((e = upload(p, H.node_dir, &L.node_dir)) != hipSuccess) return e;
+        }
+        if (parent_of_interp) {
+            if ((e = upload(p, H.chl_start, &L.chl_start)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+ifgf_status check_apply_args(ifgf_plan_t plan, const void* a, const void* out, int32_t nrhs)
+{
+    if (!plan) return fail(IFGF_E_INVALID_ARG, "plan is NULL");
+    if (plan->p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
+    if (!a || !out) return fail(IFGF_E_INVALID_ARG, "NULL device pointer");
+    if (a == out) return fail(IFGF_E_INVALID_ARG, "input and output must not alias");
+    if (nrhs < 1 || nrhs > plan->p.max_nrhs)
+        return fail(IFGF_E_INVALID_ARG, "nrhs must be in [1, max_nrhs=" + std::to_string(plan->p.max_nrhs) + "]");
+    return IFGF_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (dev >= 0 && dev != prev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t levels, const int32_t* degrees,
+                             const ifgf_options* opt, ifgf_plan_t* plan)
+{
+    if (!plan) return fail(IFGF_E_INVALID_ARG, "plan output pointer is NULL");
+    *plan = nullptr;
+    ifgf_options o{};
+    if (opt) o = *opt;
+    int ps = degrees ? degrees[0] : 3, pa = degrees ? degrees[1] : 5;
+    if (!((ps == 3 && pa == 5) || (ps == 4 && pa == 6) || (ps == 2 && pa == 3)))
+        return fail(IFGF_E_UNSUPPORTED, "degrees must be {3,5}, {4,6} or {2,3}");
+    int leaf_ns = o.leaf_ns ? o.leaf_ns : 1, leaf_nc = o.leaf_nc ? o.leaf_nc : 2;
+    if (o.precision != IFGF_FP64 && o.precision != IFGF_MIXED) return fail(IFGF_E_INVALID_ARG, "unknown precision");
+    int max_nrhs = o.max_nrhs ? o.max_nrhs : 16;
+    if (max_nrhs < 1 || max_nrhs > 4096) return fail(IFGF_E_INVALID_ARG, "max_nrhs must be in [1, 4096]");
+    ifgf_plan* pl = new (std::nothrow) ifgf_plan();
+    if (!pl) return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed");
+    ifgf::DevicePlan& p = pl->p;
+    p.precision = o.precision;
+    p.max_nrhs = max_nrhs;
+    p.store_levels = o.store_levels;
+    p.host_only = o.host_only != 0;
+    p.ws_limit = o.workspace_limit;
+    ifgf_status code = IFGF_OK;
+    std::string msg;
+    try {
+        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, p.hp, code);
+    } catch (const std::bad_alloc&) {
+        delete pl;
+        return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed while building the plan");
+    } catch (const std::exception& ex) {
+        delete pl;
+        return fail(IFGF_E_INTERNAL, ex.what());
+    }
+    if (code != IFGF_OK) {
+        delete pl;
+        return fail(code, msg);
+    }
+    if (!p.host_only) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) {
+            delete pl;
+            return hip_fail(e, "hipGetDevice");
+        }
+        p.device = dev;
+        e = upload_plan(p);
+        if (e != hipSuccess) {
+            release(p);
+            delete pl;
+            return hip_fail(e, "uploading the plan");
+        }
+        if (p.ws_limit && p.tree_bytes > p.ws_limit) {
+            release(p);
+            delete pl;
+            return fail(IFGF_E_OUT_OF_MEMORY, "workspace_limit is smaller than the hierarchy");
+        }
+        // keep every level's cone values when asked, or when they fit in a
+        // quarter of the free device memory
+        size_t total = 0;
+        int rb = max_nrhs >= 5 ? 16 : (max_nrhs >= 2 ? 4 : 1);
+        size_t ce = p.precision == IFGF_MIXED ? 8 : 16;
+        for (int d = 3; d <= p.hp.D; ++d) total += (size_t)p.hp.L[d].nslots * p.hp.P * rb * ce;
+        if (p.store_levels == 1) p.ws_store_pref = true;
+        else if (p.store_levels == 0) p.ws_store_pref = false;
+        else {
+            size_t fr = 0, tot = 0;
+            (void)hipMemGetInfo(&fr, &tot);
+            p.ws_store_pref = total <= fr / 4 && (!p.ws_limit || p.tree_bytes + 2 * total <= p.ws_limit);
+        }
+    }
+    p.hp.stats.device_bytes = (int64_t)p.tree_bytes;
+    *plan = pl;
+    return IFGF_OK;
+}
+
+static ifgf_status apply_common(ifgf_plan_t plan, const void* a, int32_t nrhs, void* out, void* stream, bool adj)
+{
+    ifgf_status s = check_apply_args(plan, a, out, nrhs);
+    if (s != IFGF_OK) return s;
+    ifgf::DevicePlan& p = plan->p;
+    DeviceGuard g(p.device);
+    double kappa = adj ? -p.hp.kappa : p.hp.kappa;
+    hipError_t e = ifgf::run_apply(p, a, nrhs, out, kappa, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, adj ? "ifgf_apply_adjoint" : "ifgf_apply");
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, int32_t nrhs, void* out, void* stream)
+{
+    return apply_common(plan, densities, nrhs, out, stream, false);
+}
+
+ifgf_status ifgf_apply_adjoint(ifgf_plan_t plan, const void* v, int32_t nrhs, void* out, void* stream)
+{
+    return apply_common(plan, v, nrhs, out, stream, true);
+}
+
+ifgf_status ifgf_grad_targets(ifgf_plan_t plan, const void* densities, const void* grad_out, int32_t nrhs,
+                              double* grad_xyz, void* stream)
+{
+    ifgf_status s = check_apply_args(plan, densities, grad_xyz, nrhs);
+    if (s != IFGF_OK) return s;
+    if (!grad_out) return fail(IFGF_E_INVALID_ARG, "grad_out is NULL");
+    if (nrhs > ifgf::kMaxRhsPass) return fail(IFGF_E_UNSUPPORTED, "ifgf_grad_targets takes at most 16 right-hand sides");
+    ifgf::DevicePlan& p = plan->p;
+    DeviceGuard g(p.device);
+    hipError_t e = ifgf::run_grad(p, densities, grad_out, nrhs, grad_xyz, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ifgf_grad_targets");
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_stats(ifgf_plan_t plan, ifgf_stats* out)
+{
+    if (!plan || !out) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    *out = plan->p.hp.stats;
+    out->device_bytes = (int64_t)(plan->p.tree_bytes + plan->p.ws_bytes);
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses)
+{
+    if (!plan || !misses) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    *misses = 0;
+    if (plan->p.host_only) return IFGF_OK;
+    DeviceGuard g(plan->p.device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "ifgf_plan_check");
+    unsigned long long m = 0;
+    e = hipMemcpy(&m, plan->p.miss, sizeof(m), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ifgf_plan_check");
+    *misses = (int64_t)m;
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_destroy(ifgf_plan_t plan)
+{
+    if (!plan) return IFGF_OK;
+    release(plan->p);
+    delete plan;
+    return IFGF_OK;
+}
+
+const char* ifgf_status_string(ifgf_status s)
+{
+    switch (s) {
+    case IFGF_OK: return "IFGF_OK";
+    case IFGF_E_INVALID_ARG: return "IFGF_E_INVALID_ARG";
+    case IFGF_E_OUT_OF_MEMORY: return "IFGF_E_OUT_OF_MEMORY";
+    case IFGF_E_HIP: return "IFGF_E_HIP";
+    case IFGF_E_UNSUPPORTED: return "IFGF_E_UNSUPPORTED";
+    case IFGF_E_INTERNAL: return "IFGF_E_INTERNAL";
+    }
+    return "unknown ifgf_status";
+}
+
+const char* ifgf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

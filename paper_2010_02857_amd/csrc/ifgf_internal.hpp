@@ -1,0 +1,221 @@
+// Internal types of the IFGF library: host-built hierarchy, its device
+// mirror, and the cone-coordinate map shared by the plan builder (host) and
+// the kernels (device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ifgf.h"
+
+namespace ifgf {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxNodes = 8;       // Chebyshev nodes per direction, upper bound
+constexpr int kMaxRhsPass = 16;    // right-hand sides handled by one kernel pass
+constexpr double kDilateTol = 1e-9;
+
+// Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
+// denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).
+struct ChebNodes {
+    double t[kMaxNodes];
+    double inv[kMaxNodes];
+};
+
+inline ChebNodes make_cheb_nodes(int n)
+{
+    ChebNodes c{};
+    for (int k = 0; k < n; ++k) c.t[k] = std::cos((2.0 * k + 1.0) * kPi / (2.0 * n));
+    for (int k = 0; k < n; ++k) {
+        double p = 1.0;
+        for (int j = 0; j < n; ++j)
+            if (j != k) p *= (c.t[k] - c.t[j]);
+        c.inv[k] = 1.0 / p;
+    }
+    return c;
+}
+
+// Cone segment of a point: cell = i_theta * (2 n_C) + i_phi, radial index
+// i_s, local coordinates (ts, tt, tp) in [-1, 1], and r = |v|.
+struct ConeLoc {
+    int cell, is, it, ip;
+    double ts, tt, tp;
+    double r, s, th, ph;
+};
+
+// Cone-coordinate map of v = x - x_k (Sec. 3.1-3.2): s = h / |v| with h the
+// box circumradius, theta = atan2(sqrt(vx^2 + vy^2), vz) in [0, pi],
+// phi = atan2(vy, vx) moved into [0, 2 pi).  The cone intervals are
+// half-open (eq. defconedomain), so a point on a face belongs to the interval
+// above it: with q = coordinate / interval length the index is
+// floor(q + 1e-10), which also keeps points that lie exactly on a face (for
+// instance on the planes x = +-y of a symmetric point set) from moving between
+// cones with last-bit differences of atan2; phi wraps at 2 pi, s and theta are
+// clamped to their last interval.  Contraction into FMAs is switched off so
+// that the host (plan) and the device (kernels) form every intermediate with
+// the same roundings.
+__host__ __device__ inline void cone_locate(double vx, double vy, double vz, double h, double ds,
+                                            double dang, int ns, int nc, ConeLoc& c)
+{
+#pragma clang fp contract(off)
+    const double tie = 1e-10;
+    double rho2 = vx * vx + vy * vy;
+    double r = sqrt(rho2 + vz * vz);
+    double s = h / r;
+    double th = atan2(sqrt(rho2), vz);
+    double ph = atan2(vy, vx);
+    if (ph < 0.0) ph += 2.0 * kPi;
+    double qs = s / ds, qt = th / dang, qp = ph / dang;
+    int is = (int)floor(qs + tie);
+    int it = (int)floor(qt + tie);
+    int ip = (int)floor(qp + tie);
+    if (ip >= 2 * nc) {
+        ip -= 2 * nc;
+        qp -= 2 * nc;
+    }
+    is = is < 0 ? 0 : (is > ns - 1 ? ns - 1 : is);
+    it = it < 0 ? 0 : (it > nc - 1 ? nc - 1 : it);
+    ip = ip < 0 ? 0 : (ip > 2 * nc - 1 ? 2 * nc - 1 : ip);
+    c.is = is;
+    c.it = it;
+    c.ip = ip;
+    c.cell = it * (2 * nc) + ip;
+    c.ts = 2.0 * (qs - is) - 1.0;
+    c.tt = 2.0 * (qt - it) - 1.0;
+    c.tp = 2.0 * (qp - ip) - 1.0;
+    c.r = r;
+    c.s = s;
+    c.th = th;
+    c.ph = ph;
+}
+
+// Position of an interpolation point relative to a child box centre:
+// v = r * dir - o, where r * dir is the point relative to the parent centre
+// and o the child centre relative to the parent centre.  Formed without
+// contraction so that host and device agree bit for bit.
+__host__ __device__ inline void node_minus(double rr, const double* dir, const double* o, double* v)
+{
+#pragma clang fp contract(off)
+    v[0] = rr * dir[0] - o[0];
+    v[1] = rr * dir[1] - o[1];
+    v[2] = rr * dir[2] - o[2];
+}
+
+// ------------------------------------------------------------ host plan
+
+struct HostLevel {
+    double H = 0, h = 0, ds = 0, dang = 0;
+    int ns = 0, nc = 0, ncell = 0, W = 0;     // W: 64-bit mask words per cell
+    int64_t nbox = 0;
+    std::vector<uint64_t> prefix;             // Morton prefix of each box (sorted)
+    std::vector<int32_t> box_start;           // [nbox+1] Morton point ranges
+    std::vector<double> box_ctr;              // [nbox][3]
+    std::vector<uint8_t> box_oct;             // [nbox] parity bits of the index
+    std::vector<int32_t> pt_box;              // [n] box of each Morton point
+    std::vector<int32_t> parent;              // [nbox] index at level d-1
+    std::vector<int32_t> chl_start, chl;      // children (level d+1)
+    std::vector<int32_t> nbr_start, nbr;      // neighbours incl. self
+    std::vector<int32_t> cou_start, cou;      // cousins
+    // relevant cones
+    std::vector<int32_t> cell_base;           // [nbox][ncell] first slot
+    std::vector<uint64_t> cell_mask;          // [nbox][ncell][W]
+    std::vector<int32_t> slot_start;          // [nbox+1]
+    std::vector<int32_t> slot_box;            // [nslots]
+    std::vector<int32_t> slot_cone;           // [nslots] cell * ns + is
+    int64_t nslots = 0;
+    std::vector<double> node_r;               // [ns][PS] h / s at radial nodes
+    std::vector<double> node_dir;             // [ncell][PA][PA][3] unit directions
+};
+
+struct HostPlan {
+    int64_t n = 0;
+    double kappa = 0;
+    int D = 0, ps = 3, pang = 5, P = 75;
+    double H1 = 0, x1[3] = {0, 0, 0}, corner[3] = {0, 0, 0};
+    std::vector<int32_t> perm;                // Morton position -> input index
+    std::vector<double> pts;                  // [n][3] Morton order
+    std::vector<HostLevel> L;                 // levels 0..D (0 unused)
+    ifgf_stats stats{};
+};
+
+// Builds the hierarchy; returns an empty string on success, else a message.
+// `code` receives the ifgf_status on failure.
+std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
+                            int leaf_ns, int leaf_nc, bool dilate, HostPlan& hp, ifgf_status& code);
+
+// ---------------------------------------------------------- device mirror
+
+struct LevelDev {
+    int nbox, ns, nc, ncell, W, nslots;
+    double H, h, ds, dang;                    // box side, circumradius, intervals
+    const int32_t* box_start;
+    const double* box_ctr;
+    const uint8_t* box_oct;
+    const int32_t* pt_box;
+    const int32_t* chl_start;
+    const int32_t* chl;
+    const int32_t* nbr_start;
+    const int32_t* nbr;
+    const int32_t* cou_start;
+    const int32_t* cou;
+    const int32_t* cell_base;
+    const unsigned long long* cell_mask;
+    const int32_t* slot_box;
+    const int32_t* slot_cone;
+    const double* node_r;
+    const double* node_dir;
+};
+
+struct KernelConsts {
+    ChebNodes cs, ca;        // radial and angular node sets
+    double kappa;            // signed wavenumber (negative for the adjoint)
+    int n;                   // points
+    unsigned long long* miss;  // device counter of interpolation misses
+};
+
+// A plan: the host hierarchy, its device copy and the workspaces.
+struct DevicePlan {
+    HostPlan hp;
+    int device = -1;
+    int precision = IFGF_FP64;
+    int max_nrhs = 16;
+    int store_levels = -1;
+    bool host_only = false;
+    size_t ws_limit = 0;
+    // device hierarchy
+    double* pts = nullptr;
+    int32_t* perm = nullptr;    // Morton position -> input index
+    int32_t* iperm = nullptr;   // input index -> Morton position
+    std::vector<LevelDev> L;
+    unsigned long long* miss = nullptr;
+    std::vector<void*> allocs;
+    size_t tree_bytes = 0;
+    // workspaces, sized for `ws_rb` right-hand sides per pass
+    int ws_rb = 0;
+    bool ws_store = false;
+    void* dens_m = nullptr;     // [n][rb] complex, Morton order
+    void* out_m = nullptr;      // [n][rb] complex, Morton order
+    void* gout_m = nullptr;     // [n][rb] complex, Morton order (gradient input)
+    double* grad_m = nullptr;   // [n][3] FP64, Morton order (gradient output)
+    bool ws_store_pref = false; // keep the cone values of every level
+    void* F[IFGF_MAX_LEVELS + 1] = {};  // cone values per level [nslots][P][rb]
+    std::vector<void*> ws_allocs;
+    size_t ws_bytes = 0;
+    // what the stored cone values hold (for gradient reuse)
+    const void* stored_dens = nullptr;
+    int stored_nrhs = 0;
+    bool stored_valid = false;
+};
+
+// Kernel pipeline entry points (kernels.hip).  `kappa` is signed: -k for
+// the adjoint.  Each enqueues on `stream` and returns hipSuccess or the
+// first launch error.
+hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t stream);
+hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
+                    hipStream_t stream);
+
+}  // namespace ifgf

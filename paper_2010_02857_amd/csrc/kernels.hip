@@ -1,0 +1,692 @@
+// HIP kernels of the IFGF operator for gfx950 (Algorithm 1, Sec. 3.3.3).
+//
+// Every kernel gathers: each output element (a target, or an interpolation
+// point of a parent cone) is owned by one thread, which loops over the
+// sources that reach it.  No output is written by two threads, so results
+// are deterministic and no atomics are needed.  Points are in Morton order,
+// so the threads of a wavefront share boxes, cousin lists and cone data.
+//
+// Precision: T = double gives the FP64 path; T = float the mixed path, in
+// which distances, the phase k r and its reduction modulo 2 pi, box centres
+// and the cone map (s, theta, phi) stay FP64 while kernel values,
+// interpolation weights and accumulation are FP32.
+#include "ifgf_internal.hpp"
+
+namespace ifgf {
+namespace {
+
+constexpr double k2Pi = 2.0 * kPi;
+constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
+constexpr double kInv4Pi = 1.0 / (4.0 * kPi);
+constexpr int kBlock = 256;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+
+// e^{i ph}: FP64 sincos, or for float an FP64 reduction of ph to [-pi, pi]
+// followed by FP32 sincos.
+template <typename T>
+__device__ inline void expi(double ph, T& c, T& s);
+template <>
+__device__ inline void expi<double>(double ph, double& c, double& s)
+{
+    sincos(ph, &s, &c);
+}
+template <>
+__device__ inline void expi<float>(double ph, float& c, float& s)
+{
+    double q = rint(ph * kInv2Pi);
+    float red = (float)(ph - q * k2Pi);
+    sincosf(red, &s, &c);
+}
+
+// Lagrange basis of the N first-kind Chebyshev nodes at t:
+// L_k(t) = prod_{j != k} (t - t_j) / (t_k - t_j).  Interpolating the node
+// values with it gives the same polynomial as the Chebyshev expansion whose
+// coefficients the discrete transform would produce.
+template <typename T, int N>
+__device__ inline void lagrange(double t, const ChebNodes& cn, T* L)
+{
+    T tt = (T)t;
+    T d[N], suf[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = tt - (T)cn.t[k];
+    suf[N - 1] = (T)1;
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) suf[k] = suf[k + 1] * d[k + 1];
+    T pre = (T)1;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        L[k] = pre * suf[k] * (T)cn.inv[k];
+        pre *= d[k];
+    }
+}
+
+// Basis and its derivative d/dt.
+template <typename T, int N>
+__device__ inline void lagrange_d(double t, const ChebNodes& cn, T* L, T* dL)
+{
+    T tt = (T)t;
+    T d[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = tt - (T)cn.t[k];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        T p = (T)1, dp = (T)0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j == k) continue;
+            dp = dp * d[j] + p;
+            p *= d[j];
+        }
+        L[k] = p * (T)cn.inv[k];
+        dL[k] = dp * (T)cn.inv[k];
+    }
+}
+
+// Slot of cone (cell, i_s) of `box`, or -1 if it was not marked relevant.
+__device__ inline int lookup(const LevelDev& L, int box, int cell, int is)
+{
+    size_t c = (size_t)box * L.ncell + cell;
+    const unsigned long long* M = L.cell_mask + c * L.W;
+    int w = is >> 6, bit = is & 63;
+    unsigned long long m = M[w];
+    if (!((m >> bit) & 1ull)) return -1;
+    int cnt = __popcll(m & ((1ull << bit) - 1ull));
+    for (int i = 0; i < w; ++i) cnt += __popcll(M[i]);
+    return L.cell_base[c] + cnt;
+}
+
+// sum_{a,b,c} F[a][b][c][r] Ls[a] Lt[b] Lp[c] for the RB right-hand sides.
+template <typename T, int PS, int PA, int RB>
+__device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T* Lt, const T* Lp, cpx<T>* v)
+{
+#pragma unroll
+    for (int r = 0; r < RB; ++r) v[r].x = v[r].y = (T)0;
+#pragma unroll
+    for (int a = 0; a < PS; ++a)
+#pragma unroll
+        for (int b = 0; b < PA; ++b) {
+            T wab = Ls[a] * Lt[b];
+#pragma unroll
+            for (int c = 0; c < PA; ++c) {
+                T w = wab * Lp[c];
+                const cpx<T>* f = F + ((a * PA + b) * PA + c) * RB;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    cpx<T> q = f[r];
+                    v[r].x += w * q.x;
+                    v[r].y += w * q.y;
+                }
+            }
+        }
+}
+
+// ------------------------------------------------------------------ kernels
+
+// densities [nrhs][n] (input order) -> [n][RB] (Morton order), zero padded.
+template <typename T, int RB>
+__global__ void __launch_bounds__(kBlock) k_permute_in(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                                       const int32_t* __restrict__ perm, int n, int nrhs, int r0)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int src = perm[i];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        int rr = r0 + r;
+        cpx<T> v;
+        v.x = v.y = (T)0;
+        if (rr < nrhs) v = in[(size_t)rr * n + src];
+        out[(size_t)i * RB + r] = v;
+    }
+}
+
+// [n][RB] (Morton order) -> out [nrhs][n] (input order).
+template <typename T, int RB>
+__global__ void __launch_bounds__(kBlock) k_permute_out(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                                        const int32_t* __restrict__ iperm, int n, int nrhs, int r0)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int i = iperm[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        int rr = r0 + r;
+        if (rr < nrhs) out[(size_t)rr * n + j] = in[(size_t)i * RB + r];
+    }
+}
+
+// Near field at the leaf level (Algorithm 1, direct evaluations onto the
+// neighbourhood U B): I(x_i) = sum over the neighbour boxes of x_i's leaf box
+// of a_j G(x_i, x_j), j != i.  Writes (initialises) the output.
+template <typename T, int RB>
+__global__ void __launch_bounds__(kBlock) k_nearfield(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
+                                                      const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int b = L.pt_box[i];
+    const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int qi = L.nbr_start[b]; qi < L.nbr_start[b + 1]; ++qi) {
+        const int q = L.nbr[qi];
+        for (int j = L.box_start[q]; j < L.box_start[q + 1]; ++j) {
+            if (j == i) continue;
+            double dx = x0 - pts[3 * j], dy = x1 - pts[3 * j + 1], dz = x2 - pts[3 * j + 2];
+            double rr = sqrt(dx * dx + dy * dy + dz * dz);
+            T c, s;
+            expi<T>(kc.kappa * rr, c, s);
+            T inv = (T)(kInv4Pi / rr);
+            T gr = c * inv, gi = s * inv;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                cpx<T> a = dens[(size_t)j * RB + r];
+                acc[r].x += a.x * gr - a.y * gi;
+                acc[r].y += a.x * gi + a.y * gr;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) out[(size_t)i * RB + r] = acc[r];
+}
+
+// Leaf level: F_k^D at every interpolation point of every relevant leaf cone
+// (eq. I_k): F(x) = sum_{m in B_k} a_m |x - c| / |x - x_m| e^{i k (|x - x_m| - |x - c|)},
+// the difference of radii formed as (|w|^2 - 2 y.w) / (|y - w| + |y|) with
+// y = x - c, w = x_m - c.
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_leaf_nodes(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
+                                                       const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ F)
+{
+    constexpr int P = PS * PA * PA;
+    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int slot = (int)(gid / P);
+    int nu = (int)(gid - (size_t)slot * P);
+    if (slot >= L.nslots) return;
+    const int b = L.slot_box[slot];
+    const int cone = L.slot_cone[slot];
+    const int cell = cone / L.ns, is = cone - cell * L.ns;
+    const int a = nu / (PA * PA), bc = nu - a * PA * PA;
+    const double rr = L.node_r[is * PS + a];
+    const double* dir = &L.node_dir[((size_t)cell * PA * PA + bc) * 3];
+    const double y0 = rr * dir[0], y1 = rr * dir[1], y2 = rr * dir[2];
+    const double ry = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+    const double c0 = L.box_ctr[3 * b], c1 = L.box_ctr[3 * b + 1], c2 = L.box_ctr[3 * b + 2];
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int j = L.box_start[b]; j < L.box_start[b + 1]; ++j) {
+        double w0 = pts[3 * j] - c0, w1 = pts[3 * j + 1] - c1, w2 = pts[3 * j + 2] - c2;
+        double e0 = y0 - w0, e1 = y1 - w1, e2 = y2 - w2;
+        double rxy = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        double num = (w0 * w0 + w1 * w1 + w2 * w2) - 2.0 * (y0 * w0 + y1 * w1 + y2 * w2);
+        double diff = num / (rxy + ry);
+        T c, s;
+        expi<T>(kc.kappa * diff, c, s);
+        T mag = (T)(ry / rxy);
+        T gr = mag * c, gi = mag * s;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            cpx<T> q = dens[(size_t)j * RB + r];
+            acc[r].x += q.x * gr - q.y * gi;
+            acc[r].y += q.x * gi + q.y * gr;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) F[((size_t)slot * P + nu) * RB + r] = acc[r];
+}
+
+// Interpolation at cousin targets, level d (Algorithm 1, first inner loop):
+// for target x and every cousin box k of x's box,
+//   I(x) += G(x, x_k) P_{k, gamma(x)}(s, theta, phi).
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_eval(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
+                                                        const cpx<T>* __restrict__ F, cpx<T>* __restrict__ out)
+{
+    constexpr int P = PS * PA * PA;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int t = L.pt_box[i];
+    const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int ci = L.cou_start[t]; ci < L.cou_start[t + 1]; ++ci) {
+        const int k = L.cou[ci];
+        ConeLoc cl;
+        cone_locate(x0 - L.box_ctr[3 * k], x1 - L.box_ctr[3 * k + 1], x2 - L.box_ctr[3 * k + 2], L.h, L.ds, L.dang,
+                    L.ns, L.nc, cl);
+        const int slot = lookup(L, k, cl.cell, cl.is);
+        if (slot < 0) {
+            atomicAdd(kc.miss, 1ull);
+            continue;
+        }
+        T Ls[PS], Lt[PA], Lp[PA];
+        lagrange<T, PS>(cl.ts, kc.cs, Ls);
+        lagrange<T, PA>(cl.tt, kc.ca, Lt);
+        lagrange<T, PA>(cl.tp, kc.ca, Lp);
+        cpx<T> v[RB];
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
+        T c, s;
+        expi<T>(kc.kappa * cl.r, c, s);
+        T inv = (T)(kInv4Pi / cl.r);
+        T gr = c * inv, gi = s * inv;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            acc[r].x += v[r].x * gr - v[r].y * gi;
+            acc[r].y += v[r].x * gi + v[r].y * gr;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        cpx<T> o = out[(size_t)i * RB + r];
+        o.x += acc[r].x;
+        o.y += acc[r].y;
+        out[(size_t)i * RB + r] = o;
+    }
+}
+
+// Child-to-parent interpolation, children at level d (Algorithm 1, second
+// inner loop): for every interpolation point x of every relevant cone of a
+// level-(d-1) box j,
+//   F_j(x) = sum_{children k} P_{k, gamma(x)}(.) G(x, x_k) / G(x, x_j),
+// with G(x, x_k) / G(x, x_j) = |y| / |y - o| e^{i k (|y - o| - |y|)},
+// y = x - x_j, o = x_k - x_j, and |y - o| - |y| = (|o|^2 - 2 y.o) / (|y - o| + |y|).
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                            const cpx<T>* __restrict__ Fc, cpx<T>* __restrict__ Fp)
+{
+    constexpr int P = PS * PA * PA;
+    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int pslot = (int)(gid / P);
+    int nu = (int)(gid - (size_t)pslot * P);
+    if (pslot >= Lp.nslots) return;
+    const int j = Lp.slot_box[pslot];
+    const int pcone = Lp.slot_cone[pslot];
+    const int pcell = pcone / Lp.ns, pis = pcone - pcell * Lp.ns;
+    const int a = nu / (PA * PA), bc = nu - a * PA * PA;
+    const double rr = Lp.node_r[pis * PS + a];
+    const double* dir = &Lp.node_dir[((size_t)pcell * PA * PA + bc) * 3];
+    const double y0 = rr * dir[0], y1 = rr * dir[1], y2 = rr * dir[2];
+    const double ry = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+    const double half = 0.5 * Lc.H;
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int k = Lp.chl_start[j]; k < Lp.chl_start[j + 1]; ++k) {
+        const int oct = Lc.box_oct[k];
+        double o[3] = {(oct & 1) ? half : -half, (oct & 2) ? half : -half, (oct & 4) ? half : -half};
+        double v[3];
+        node_minus(rr, dir, o, v);
+        ConeLoc cl;
+        cone_locate(v[0], v[1], v[2], Lc.h, Lc.ds, Lc.dang, Lc.ns, Lc.nc, cl);
+        const int slot = lookup(Lc, k, cl.cell, cl.is);
+        if (slot < 0) {
+            atomicAdd(kc.miss, 1ull);
+            continue;
+        }
+        T Ls[PS], Lt[PA], Lpp[PA];
+        lagrange<T, PS>(cl.ts, kc.cs, Ls);
+        lagrange<T, PA>(cl.tt, kc.ca, Lt);
+        lagrange<T, PA>(cl.tp, kc.ca, Lpp);
+        cpx<T> val[RB];
+        interp<T, PS, PA, RB>(Fc + (size_t)slot * P * RB, Ls, Lt, Lpp, val);
+        double num = (o[0] * o[0] + o[1] * o[1] + o[2] * o[2]) - 2.0 * (y0 * o[0] + y1 * o[1] + y2 * o[2]);
+        double diff = num / (cl.r + ry);
+        T c, s;
+        expi<T>(kc.kappa * diff, c, s);
+        T mag = (T)(ry / cl.r);
+        T gr = mag * c, gi = mag * s;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            acc[r].x += val[r].x * gr - val[r].y * gi;
+            acc[r].y += val[r].x * gi + val[r].y * gr;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) Fp[((size_t)pslot * P + nu) * RB + r] = acc[r];
+}
+
+// ----------------------------------------------------------- gradients
+
+// d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
+// contracted with conj(g): grad[i][c] = sum_r Re(conj(g_r) dI_r/dx_c).
+template <typename T, int RB>
+__global__ void __launch_bounds__(kBlock) k_near_grad(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
+                                                      const cpx<T>* __restrict__ dens, const cpx<T>* __restrict__ gout,
+                                                      double* __restrict__ grad)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int b = L.pt_box[i];
+    const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
+    cpx<T> g[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) g[r] = gout[(size_t)i * RB + r];
+    double acc0 = 0, acc1 = 0, acc2 = 0;
+    for (int qi = L.nbr_start[b]; qi < L.nbr_start[b + 1]; ++qi) {
+        const int q = L.nbr[qi];
+        for (int j = L.box_start[q]; j < L.box_start[q + 1]; ++j) {
+            if (j == i) continue;
+            double dx = x0 - pts[3 * j], dy = x1 - pts[3 * j + 1], dz = x2 - pts[3 * j + 2];
+            double rr = sqrt(dx * dx + dy * dy + dz * dz);
+            T c, s;
+            expi<T>(kc.kappa * rr, c, s);
+            T inv = (T)(kInv4Pi / rr);
+            // G (i k - 1/r) / r
+            T gr = c * inv, gi = s * inv;
+            T fr = (T)(-1.0 / rr), fi = (T)kc.kappa;
+            T hr = (gr * fr - gi * fi) * (T)(1.0 / rr), hi = (gr * fi + gi * fr) * (T)(1.0 / rr);
+            // s = sum_r Re(conj(g_r) a_r h)
+            T sr = (T)0;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                cpx<T> a = dens[(size_t)j * RB + r];
+                T ar = a.x * hr - a.y * hi, ai = a.x * hi + a.y * hr;
+                sr += g[r].x * ar + g[r].y * ai;
+            }
+            acc0 += (double)sr * dx;
+            acc1 += (double)sr * dy;
+            acc2 += (double)sr * dz;
+        }
+    }
+    grad[3 * i] = acc0;
+    grad[3 * i + 1] = acc1;
+    grad[3 * i + 2] = acc2;
+}
+
+// d/dx of the cousin-target interpolation at level d:
+//   d/dx [G(x, x_k) P] = P grad G + G (dP/dts 2/ds grad s + dP/dtt 2/dang grad theta
+//                                      + dP/dtp 2/dang grad phi),
+// grad s = -s v / r^2, grad theta = (vx vz, vy vz, -rho^2) / (rho r^2),
+// grad phi = (-vy, vx, 0) / rho^2.
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
+                                                        const cpx<T>* __restrict__ F, const cpx<T>* __restrict__ gout,
+                                                        double* __restrict__ grad)
+{
+    constexpr int P = PS * PA * PA;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int t = L.pt_box[i];
+    const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
+    cpx<T> g[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) g[r] = gout[(size_t)i * RB + r];
+    double acc0 = 0, acc1 = 0, acc2 = 0;
+    for (int ci = L.cou_start[t]; ci < L.cou_start[t + 1]; ++ci) {
+        const int k = L.cou[ci];
+        const double v0 = x0 - L.box_ctr[3 * k], v1 = x1 - L.box_ctr[3 * k + 1], v2 = x2 - L.box_ctr[3 * k + 2];
+        ConeLoc cl;
+        cone_locate(v0, v1, v2, L.h, L.ds, L.dang, L.ns, L.nc, cl);
+        const int slot = lookup(L, k, cl.cell, cl.is);
+        if (slot < 0) {
+            atomicAdd(kc.miss, 1ull);
+            continue;
+        }
+        T Ls[PS], Lt[PA], Lp[PA], dLs[PS], dLt[PA], dLp[PA];
+        lagrange_d<T, PS>(cl.ts, kc.cs, Ls, dLs);
+        lagrange_d<T, PA>(cl.tt, kc.ca, Lt, dLt);
+        lagrange_d<T, PA>(cl.tp, kc.ca, Lp, dLp);
+        cpx<T> v[RB], vs[RB], vt[RB], vp[RB];
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, dLs, Lt, Lp, vs);
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, dLt, Lp, vt);
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, dLp, vp);
+        const double r = cl.r, r2 = r * r;
+        const double rho2 = v0 * v0 + v1 * v1, rho = sqrt(rho2);
+        const double cs_ = 2.0 / L.ds, ca_ = 2.0 / L.dang;
+        const double gs[3] = {-cl.s * v0 / r2 * cs_, -cl.s * v1 / r2 * cs_, -cl.s * v2 / r2 * cs_};
+        const double gt[3] = {v0 * v2 / (rho * r2) * ca_, v1 * v2 / (rho * r2) * ca_, -rho / r2 * ca_};
+        const double gp[3] = {-v1 / rho2 * ca_, v0 / rho2 * ca_, 0.0};
+        T c, s;
+        expi<T>(kc.kappa * r, c, s);
+        T inv = (T)(kInv4Pi / r);
+        T Gr = c * inv, Gi = s * inv;
+        // grad G = G (i k - 1/r) v / r
+        T fr = (T)(-1.0 / r), fi = (T)kc.kappa;
+        T Hr = (Gr * fr - Gi * fi) * (T)(1.0 / r), Hi = (Gr * fi + Gi * fr) * (T)(1.0 / r);
+        // per RHS: Re(conj(g) (P H v_c + G (Ps gs_c + Pt gt_c + Pp gp_c)))
+        double sP = 0, sS = 0, sT = 0, sPh = 0;
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            T pr = v[rr].x * Hr - v[rr].y * Hi, pi = v[rr].x * Hi + v[rr].y * Hr;           // P H
+            sP += (double)(g[rr].x * pr + g[rr].y * pi);
+            T qr = vs[rr].x * Gr - vs[rr].y * Gi, qi = vs[rr].x * Gi + vs[rr].y * Gr;       // Ps G
+            sS += (double)(g[rr].x * qr + g[rr].y * qi);
+            qr = vt[rr].x * Gr - vt[rr].y * Gi;
+            qi = vt[rr].x * Gi + vt[rr].y * Gr;
+            sT += (double)(g[rr].x * qr + g[rr].y * qi);
+            qr = vp[rr].x * Gr - vp[rr].y * Gi;
+            qi = vp[rr].x * Gi + vp[rr].y * Gr;
+            sPh += (double)(g[rr].x * qr + g[rr].y * qi);
+        }
+        acc0 += sP * v0 + sS * gs[0] + sT * gt[0] + sPh * gp[0];
+        acc1 += sP * v1 + sS * gs[1] + sT * gt[1] + sPh * gp[1];
+        acc2 += sP * v2 + sS * gs[2] + sT * gt[2] + sPh * gp[2];
+    }
+    grad[3 * i] += acc0;
+    grad[3 * i + 1] += acc1;
+    grad[3 * i + 2] += acc2;
+}
+
+// [n][3] (Morton order) -> grad [n][3] (input order).
+__global__ void __launch_bounds__(kBlock) k_permute_grad(const double* __restrict__ in, double* __restrict__ out,
+                                                         const int32_t* __restrict__ iperm, int n)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int i = iperm[j];
+    out[3 * j] = in[3 * i];
+    out[3 * j + 1] = in[3 * i + 1];
+    out[3 * j + 2] = in[3 * i + 2];
+}
+
+// ------------------------------------------------------------- host side
+
+inline unsigned grid_for(size_t items) { return (unsigned)((items + kBlock - 1) / kBlock); }
+
+inline int rb_for(int nrhs) { return nrhs >= 5 ? 16 : (nrhs >= 2 ? 4 : 1); }
+
+// Workspaces for `rb` right-hand sides per pass; cone values either for every
+// level (store) or in two buffers used alternately.  Sets *fresh when the
+// buffers were (re)allocated, which discards stored cone values.
+template <typename T>
+hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
+{
+    const HostPlan& hp = p.hp;
+    const int D = hp.D;
+    if (fresh) *fresh = false;
+    if (p.ws_rb >= rb && p.ws_store == store) return hipSuccess;
+    if (fresh) *fresh = true;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    for (void* q : p.ws_allocs) (void)hipFree(q);
+    p.ws_allocs.clear();
+    p.ws_bytes = 0;
+    p.ws_rb = 0;
+    p.dens_m = p.out_m = p.gout_m = nullptr;
+    p.grad_m = nullptr;
+    for (auto& f : p.F) f = nullptr;
+    p.stored_valid = false;
+    const size_t ce = sizeof(cpx<T>);
+    size_t need = 3 * (size_t)hp.n * rb * ce + (size_t)hp.n * 3 * sizeof(double);
+    size_t maxs = 0, tot = 0;
+    for (int d = 3; d <= D; ++d) {
+        maxs = std::max(maxs, (size_t)hp.L[d].nslots);
+        tot += (size_t)hp.L[d].nslots;
+    }
+    need += (store ? tot : 2 * maxs) * hp.P * rb * ce;
+    if (p.ws_limit && p.tree_bytes + need > p.ws_limit) return hipErrorOutOfMemory;
+    auto alloc = [&](size_t bytes, void** out) -> hipError_t {
+        if (bytes == 0) bytes = 16;
+        hipError_t err = hipMalloc(out, bytes);
+        if (err == hipSuccess) {
+            p.ws_allocs.push_back(*out);
+            p.ws_bytes += bytes;
+        }
+        return err;
+    };
+    if ((e = alloc((size_t)hp.n * rb * ce, &p.dens_m)) != hipSuccess) return e;
+    if ((e = alloc((size_t)hp.n * rb * ce, &p.out_m)) != hipSuccess) return e;
+    if ((e = alloc((size_t)hp.n * rb * ce, &p.gout_m)) != hipSuccess) return e;
+    void* gm = nullptr;
+    if ((e = alloc((size_t)hp.n * 3 * sizeof(double), &gm)) != hipSuccess) return e;
+    p.grad_m = (double*)gm;
+    if (store) {
+        for (int d = 3; d <= D; ++d)
+            if ((e = alloc((size_t)hp.L[d].nslots * hp.P * rb * ce, &p.F[d])) != hipSuccess) return e;
+    } else if (D >= 3) {
+        void* buf[2];
+        if ((e = alloc(maxs * hp.P * rb * ce, &buf[0])) != hipSuccess) return e;
+        if ((e = alloc(maxs * hp.P * rb * ce, &buf[1])) != hipSuccess) return e;
+        for (int d = 3; d <= D; ++d) p.F[d] = buf[d & 1];
+    }
+    p.ws_rb = rb;
+    p.ws_store = store;
+    return hipSuccess;
+}
+
+template <typename T, int PS, int PA, int RB>
+hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st, bool grad, bool reuse)
+{
+    const HostPlan& hp = p.hp;
+    const int D = hp.D;
+    const int n = (int)hp.n;
+    constexpr int P = PS * PA * PA;
+    using C = cpx<T>;
+    if (D < 3) return hipSuccess;
+    if (!reuse && hp.L[D].nslots > 0)
+        k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
+            kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
+    for (int d = D; d >= 3; --d) {
+        if (grad)
+            k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                         (const C*)p.gout_m, p.grad_m);
+        else
+            k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                         (C*)p.out_m);
+        if (d > 3 && !reuse && hp.L[d - 1].nslots > 0)
+            k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)hp.L[d - 1].nslots * P), kBlock, 0, st>>>(
+                kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int PS, int PA, int RB>
+hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* out, double kappa, hipStream_t st)
+{
+    const int n = (int)p.hp.n;
+    using C = cpx<T>;
+    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), kappa, n, p.miss};
+    k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, r0);
+    k_nearfield<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m, (C*)p.out_m);
+    hipError_t e = upward_and_eval<T, PS, PA, RB>(p, kc, st, false, false);
+    if (e != hipSuccess) return e;
+    k_permute_out<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)p.out_m, (C*)out, p.iperm, n, nrhs, r0);
+    return hipGetLastError();
+}
+
+template <typename T, int PS, int PA, int RB>
+hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
+                     hipStream_t st)
+{
+    const int n = (int)p.hp.n;
+    using C = cpx<T>;
+    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), p.hp.kappa, n, p.miss};
+    if (!reuse)
+        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, 0);
+    k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n, nrhs, 0);
+    k_near_grad<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m,
+                                                        (const C*)p.gout_m, p.grad_m);
+    hipError_t e = upward_and_eval<T, PS, PA, RB>(p, kc, st, true, reuse);
+    if (e != hipSuccess) return e;
+    k_permute_grad<<<grid_for(n), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, n);
+    return hipGetLastError();
+}
+
+template <typename T, int PS, int PA>
+hipError_t apply_t(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t st)
+{
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPass) {
+        int rb = rb_for(std::min(kMaxRhsPass, nrhs - r0));
+        bool store = p.ws_store_pref && nrhs <= kMaxRhsPass;
+        hipError_t e = ensure_workspace<T>(p, rb, store, nullptr);
+        if (e != hipSuccess) return e;
+        if (rb == 1) e = apply_pass<T, PS, PA, 1>(p, dens, nrhs, r0, out, kappa, st);
+        else if (rb == 4) e = apply_pass<T, PS, PA, 4>(p, dens, nrhs, r0, out, kappa, st);
+        else e = apply_pass<T, PS, PA, 16>(p, dens, nrhs, r0, out, kappa, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int PS, int PA>
+hipError_t grad_t(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
+                  hipStream_t st)
+{
+    const int rb = rb_for(nrhs);
+    bool fresh = false;
+    hipError_t e = ensure_workspace<T>(p, rb, p.ws_store_pref, &fresh);
+    if (e != hipSuccess) return e;
+    if (fresh) reuse = false;
+    if (rb == 1) return grad_pass<T, PS, PA, 1>(p, dens, gout, nrhs, grad, reuse, st);
+    if (rb == 4) return grad_pass<T, PS, PA, 4>(p, dens, gout, nrhs, grad, reuse, st);
+    return grad_pass<T, PS, PA, 16>(p, dens, gout, nrhs, grad, reuse, st);
+}
+
+}  // namespace
+
+hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t st)
+{
+    const int ps = p.hp.ps, pa = p.hp.pang;
+    hipError_t e;
+    bool mixed = p.precision == IFGF_MIXED;
+    if (ps == 3 && pa == 5)
+        e = mixed ? apply_t<float, 3, 5>(p, dens, nrhs, out, kappa, st) : apply_t<double, 3, 5>(p, dens, nrhs, out, kappa, st);
+    else if (ps == 4 && pa == 6)
+        e = mixed ? apply_t<float, 4, 6>(p, dens, nrhs, out, kappa, st) : apply_t<double, 4, 6>(p, dens, nrhs, out, kappa, st);
+    else if (ps == 2 && pa == 3)
+        e = mixed ? apply_t<float, 2, 3>(p, dens, nrhs, out, kappa, st) : apply_t<double, 2, 3>(p, dens, nrhs, out, kappa, st);
+    else
+        return hipErrorInvalidValue;
+    if (e == hipSuccess) {
+        p.stored_valid = p.ws_store && kappa == p.hp.kappa && nrhs <= kMaxRhsPass && p.ws_rb == rb_for(nrhs);
+        p.stored_dens = dens;
+        p.stored_nrhs = nrhs;
+    }
+    return e;
+}
+
+hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
+                    hipStream_t st)
+{
+    const int ps = p.hp.ps, pa = p.hp.pang;
+    bool mixed = p.precision == IFGF_MIXED;
+    if (nrhs > kMaxRhsPass) return hipErrorInvalidValue;
+    reuse = reuse && p.ws_store && p.stored_valid && p.stored_dens == dens && p.stored_nrhs == nrhs &&
+            p.ws_rb == rb_for(nrhs);
+    hipError_t e;
+    if (ps == 3 && pa == 5)
+        e = mixed ? grad_t<float, 3, 5>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 3, 5>(p, dens, gout, nrhs, grad, reuse, st);
+    else if (ps == 4 && pa == 6)
+        e = mixed ? grad_t<float, 4, 6>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 4, 6>(p, dens, gout, nrhs, grad, reuse, st);
+    else if (ps == 2 && pa == 3)
+        e = mixed ? grad_t<float, 2, 3>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 2, 3>(p, dens, gout, nrhs, grad, reuse, st);
+    else
+        return hipErrorInvalidValue;
+    if (e == hipSuccess && p.ws_store) {
+        // the stored cone values now hold these densities (reused or rebuilt)
+        p.stored_valid = true;
+        p.stored_dens = dens;
+        p.stored_nrhs = nrhs;
+    }
+    return e;
+}
+
+}  // namespace ifgf

@@ -1,0 +1,522 @@
+// Host construction of the IFGF hierarchy (Sec. 3.3.1-3.3.2): root box,
+// Morton-ordered points, relevant boxes of every level as contiguous Morton
+// ranges, parents/children, neighbours and cousins, cone intervals per
+// level, and the relevant cone segments of every box with their slot tables.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "ifgf_internal.hpp"
+
+namespace ifgf {
+namespace {
+
+int host_threads()
+{
+    const char* e = std::getenv("IFGF_HOST_THREADS");
+    int t = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+    if (t < 1) t = 1;
+    if (t > 16) t = 16;
+    return t;
+}
+
+// Runs f(i) for i in [0, n) on a small thread pool, `grain` indices at a time.
+template <class F>
+void parallel_for(int64_t n, F&& f, int64_t grain = 1)
+{
+    int nt = host_threads();
+    if (n <= grain || nt == 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            int64_t b = next.fetch_add(grain);
+            if (b >= n) break;
+            int64_t e = std::min(n, b + grain);
+            for (int64_t i = b; i < e; ++i) f(i);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
+}
+
+uint64_t interleave3(uint64_t x, uint64_t y, uint64_t z, int bits)
+{
+    uint64_t c = 0;
+    for (int b = 0; b < bits; ++b) {
+        c |= ((x >> b) & 1ull) << (3 * b + 2);
+        c |= ((y >> b) & 1ull) << (3 * b + 1);
+        c |= ((z >> b) & 1ull) << (3 * b);
+    }
+    return c;
+}
+
+void deinterleave3(uint64_t c, int bits, int64_t* k)
+{
+    k[0] = k[1] = k[2] = 0;
+    for (int b = 0; b < bits; ++b) {
+        k[0] |= (int64_t)((c >> (3 * b + 2)) & 1ull) << b;
+        k[1] |= (int64_t)((c >> (3 * b + 1)) & 1ull) << b;
+        k[2] |= (int64_t)((c >> (3 * b)) & 1ull) << b;
+    }
+}
+
+// Integer part of (x - corner) / H per axis, clamped into [0, nb - 1].
+void box_index(const double* x, const double* corner, double H, int64_t nb, int64_t* k)
+{
+    for (int a = 0; a < 3; ++a) {
+        double q = std::floor((x[a] - corner[a]) / H);
+        int64_t v = q < 0.0 ? 0 : (int64_t)q;
+        k[a] = v > nb - 1 ? nb - 1 : v;
+    }
+}
+
+int64_t find_prefix(const std::vector<uint64_t>& v, uint64_t key)
+{
+    auto it = std::lower_bound(v.begin(), v.end(), key);
+    if (it == v.end() || *it != key) return -1;
+    return (int64_t)(it - v.begin());
+}
+
+}  // namespace
+
+std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
+                            int leaf_ns, int leaf_nc, bool dilate, HostPlan& hp, ifgf_status& code)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    code = IFGF_E_INVALID_ARG;
+    if (!points) return "points is NULL";
+    if (n < 2) return "need at least two points";
+    if (n > (int64_t)INT32_MAX / 2) return "too many points for 32-bit indexing";
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return "wavenumber must be finite and >= 0";
+    if (levels < 0 || levels > 22) return "levels must be 0 (auto) or 2..22";
+    if (levels == 1) return "levels must be 0 (auto) or 2..22";
+    if (leaf_ns < 1 || leaf_nc < 1 || leaf_ns > 64 || leaf_nc > 64) return "leaf cone counts out of range";
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(points[i])) return "points must be finite";
+
+    hp = HostPlan();
+    hp.n = n;
+    hp.kappa = kappa;
+    hp.ps = ps;
+    hp.pang = pang;
+    hp.P = ps * pang * pang;
+
+    // Root box: centre at the bounding-box midpoint, side = largest extent.
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = points[a];
+    for (int64_t i = 1; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], points[3 * i + a]);
+            hi[a] = std::max(hi[a], points[3 * i + a]);
+        }
+    double H1 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        hp.x1[a] = 0.5 * (lo[a] + hi[a]);
+        H1 = std::max(H1, hi[a] - lo[a]);
+    }
+    if (!(H1 > 0.0)) return "all points coincide";
+    hp.H1 = H1;
+    for (int a = 0; a < 3; ++a) hp.corner[a] = hp.x1[a] - H1 / 2.0;
+
+    // Number of levels: leaf boxes about a quarter wavelength wide (Sec. 4).
+    int D = levels;
+    if (D == 0) {
+        if (kappa > 0.0) {
+            double lambda = 2.0 * kPi / kappa;
+            D = 1 + (int)std::floor(std::log2(4.0 * H1 / lambda) + 0.5);
+        } else {
+            for (D = 2; D < 22; ++D) {
+                double Hd = std::ldexp(H1, -(D - 1));
+                int64_t nb = (int64_t)1 << (D - 1);
+                std::vector<uint64_t> keys(n);
+                for (int64_t i = 0; i < n; ++i) {
+                    int64_t k[3];
+                    box_index(&points[3 * i], hp.corner, Hd, nb, k);
+                    keys[i] = ((uint64_t)k[0] << 42) | ((uint64_t)k[1] << 21) | (uint64_t)k[2];
+                }
+                std::sort(keys.begin(), keys.end());
+                int64_t nu = std::unique(keys.begin(), keys.end()) - keys.begin();
+                if ((double)n / (double)nu <= 8.0) break;
+            }
+        }
+        D = std::max(2, std::min(22, D));
+    }
+    hp.D = D;
+    const int bits = D - 1;
+    const double HD = std::ldexp(H1, -(D - 1));
+    const int64_t nbD = (int64_t)1 << (D - 1);
+
+    // Leaf multi-index and Morton code of every point; sort by code (ties by
+    // coordinates, so equal points become neighbours in the order).
+    std::vector<int64_t> kD(3 * n);
+    std::vector<uint64_t> mort(n);
+    parallel_for(n, [&](int64_t i) {
+        box_index(&points[3 * i], hp.corner, HD, nbD, &kD[3 * i]);
+        mort[i] = interleave3(kD[3 * i], kD[3 * i + 1], kD[3 * i + 2], bits);
+    }, 4096);
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (mort[a] != mort[b]) return mort[a] < mort[b];
+        for (int c = 0; c < 3; ++c)
+            if (points[3 * a + c] != points[3 * b + c]) return points[3 * a + c] < points[3 * b + c];
+        return a < b;
+    });
+    for (int64_t i = 1; i < n; ++i) {
+        int32_t a = order[i - 1], b = order[i];
+        if (mort[a] == mort[b] && points[3 * a] == points[3 * b] && points[3 * a + 1] == points[3 * b + 1] &&
+            points[3 * a + 2] == points[3 * b + 2])
+            return "points must be pairwise different (duplicates of input point " + std::to_string(a) + ")";
+    }
+    hp.perm = order;
+    hp.pts.resize(3 * n);
+    std::vector<uint64_t> mcode(n);
+    std::vector<int64_t> mk(3 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            hp.pts[3 * i + a] = points[3 * order[i] + a];
+            mk[3 * i + a] = kD[3 * order[i] + a];
+        }
+        mcode[i] = mort[order[i]];
+    }
+
+    // Relevant boxes of every level: unique Morton prefixes.
+    hp.L.assign(D + 1, HostLevel());
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        L.H = std::ldexp(H1, -(d - 1));
+        L.h = std::sqrt(3.0) * L.H / 2.0;
+        int shift = 3 * (D - d);
+        L.pt_box.resize(n);
+        for (int64_t i = 0; i < n; ++i) {
+            uint64_t p = mcode[i] >> shift;
+            if (i == 0 || p != L.prefix.back()) {
+                L.prefix.push_back(p);
+                L.box_start.push_back((int32_t)i);
+            }
+            L.pt_box[i] = (int32_t)L.prefix.size() - 1;
+        }
+        L.nbox = (int64_t)L.prefix.size();
+        L.box_start.push_back((int32_t)n);
+        L.box_ctr.resize(3 * L.nbox);
+        L.box_oct.resize(L.nbox);
+        for (int64_t b = 0; b < L.nbox; ++b) {
+            int64_t i = L.box_start[b];
+            int64_t k[3];
+            for (int a = 0; a < 3; ++a) k[a] = mk[3 * i + a] >> (D - d);
+            // x_k^d = x_1^1 - H_1/2 + H_d/2 (2k - 1), 1-based k (eq. defboxsizesandcenters)
+            for (int a = 0; a < 3; ++a) L.box_ctr[3 * b + a] = hp.x1[a] - H1 / 2.0 + L.H / 2.0 * (2.0 * k[a] + 1.0);
+            L.box_oct[b] = (uint8_t)((k[0] & 1) | ((k[1] & 1) << 1) | ((k[2] & 1) << 2));
+        }
+    }
+
+    // Parents and children.
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        L.parent.assign(L.nbox, -1);
+        if (d > 1) {
+            const HostLevel& Lp = hp.L[d - 1];
+            int64_t p = 0;
+            for (int64_t b = 0; b < L.nbox; ++b) {
+                uint64_t pk = L.prefix[b] >> 3;
+                while (Lp.prefix[p] != pk) ++p;
+                L.parent[b] = (int32_t)p;
+            }
+        }
+    }
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        L.chl_start.assign(L.nbox + 1, 0);
+        if (d < D) {
+            const HostLevel& Lc = hp.L[d + 1];
+            for (int64_t c = 0; c < Lc.nbox; ++c) L.chl_start[Lc.parent[c] + 1]++;
+            for (int64_t b = 0; b < L.nbox; ++b) L.chl_start[b + 1] += L.chl_start[b];
+            L.chl.resize(Lc.nbox);
+            for (int64_t c = 0; c < Lc.nbox; ++c) L.chl[c] = (int32_t)c;  // children are contiguous and ordered
+        }
+    }
+
+    // Neighbours (|a - k|_inf <= 1, self included) on every level.
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        int64_t nb = (int64_t)1 << (d - 1);
+        std::vector<int32_t> cnt(L.nbox), tmp(27 * L.nbox);
+        parallel_for(L.nbox, [&](int64_t b) {
+            int64_t k[3];
+            deinterleave3(L.prefix[b], d - 1, k);
+            int c = 0;
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        int64_t q[3] = {k[0] + dx, k[1] + dy, k[2] + dz};
+                        if (q[0] < 0 || q[1] < 0 || q[2] < 0 || q[0] >= nb || q[1] >= nb || q[2] >= nb) continue;
+                        int64_t j = find_prefix(L.prefix, interleave3(q[0], q[1], q[2], d - 1));
+                        if (j >= 0) tmp[27 * b + c++] = (int32_t)j;
+                    }
+            std::sort(&tmp[27 * b], &tmp[27 * b] + c);
+            cnt[b] = c;
+        }, 256);
+        L.nbr_start.assign(L.nbox + 1, 0);
+        for (int64_t b = 0; b < L.nbox; ++b) L.nbr_start[b + 1] = L.nbr_start[b] + cnt[b];
+        L.nbr.resize(L.nbr_start[L.nbox]);
+        for (int64_t b = 0; b < L.nbox; ++b)
+            std::copy(&tmp[27 * b], &tmp[27 * b] + cnt[b], &L.nbr[L.nbr_start[b]]);
+    }
+
+    // Cousins: relevant children of the parent's neighbours that are not
+    // neighbours themselves (eq. defcousinboxes).
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        L.cou_start.assign(L.nbox + 1, 0);
+        if (d < 3) continue;
+        const HostLevel& Lp = hp.L[d - 1];
+        std::vector<std::vector<int32_t>> lists(L.nbox);
+        parallel_for(L.nbox, [&](int64_t b) {
+            int64_t k[3];
+            deinterleave3(L.prefix[b], d - 1, k);
+            int32_t p = L.parent[b];
+            for (int32_t qi = Lp.nbr_start[p]; qi < Lp.nbr_start[p + 1]; ++qi) {
+                int32_t q = Lp.nbr[qi];
+                for (int32_t c = Lp.chl_start[q]; c < Lp.chl_start[q + 1]; ++c) {
+                    int64_t kc[3];
+                    deinterleave3(L.prefix[c], d - 1, kc);
+                    if (std::llabs(kc[0] - k[0]) <= 1 && std::llabs(kc[1] - k[1]) <= 1 && std::llabs(kc[2] - k[2]) <= 1)
+                        continue;
+                    lists[b].push_back(c);
+                }
+            }
+        }, 64);
+        for (int64_t b = 0; b < L.nbox; ++b) L.cou_start[b + 1] = L.cou_start[b] + (int32_t)lists[b].size();
+        L.cou.resize(L.cou_start[L.nbox]);
+        for (int64_t b = 0; b < L.nbox; ++b) std::copy(lists[b].begin(), lists[b].end(), &L.cou[L.cou_start[b]]);
+    }
+
+    // Cone intervals: leaf counts given; going up, a_d = 2 iff 2 kappa H_d > 1.
+    hp.L[D].ns = leaf_ns;
+    hp.L[D].nc = leaf_nc;
+    for (int d = D; d >= 2; --d) {
+        int ad = (2.0 * kappa * hp.L[d].H > 1.0) ? 2 : 1;
+        hp.L[d - 1].ns = ad * hp.L[d].ns;
+        hp.L[d - 1].nc = ad * hp.L[d].nc;
+    }
+    const ChebNodes cs = make_cheb_nodes(ps), ca = make_cheb_nodes(pang);
+    const double eta = std::sqrt(3.0) / 3.0;
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        if ((int64_t)L.ns * L.nc * 2 * L.nc > (int64_t)1 << 30) {
+            code = IFGF_E_UNSUPPORTED;
+            return "too many cone segments per box at level " + std::to_string(d);
+        }
+        L.ds = eta / L.ns;
+        L.dang = kPi / L.nc;
+        L.ncell = L.nc * 2 * L.nc;
+        L.W = (L.ns + 63) / 64;
+        if (d < 3) continue;
+        // interpolation points (eq. interp_pts): radii h / s and unit directions
+        L.node_r.resize((size_t)L.ns * ps);
+        for (int is = 0; is < L.ns; ++is)
+            for (int a = 0; a < ps; ++a) {
+                double s = L.ds * (is + 0.5 * (cs.t[a] + 1.0));
+                L.node_r[(size_t)is * ps + a] = L.h / s;
+            }
+        L.node_dir.resize((size_t)L.ncell * pang * pang * 3);
+        for (int it = 0; it < L.nc; ++it)
+            for (int ip = 0; ip < 2 * L.nc; ++ip)
+                for (int b = 0; b < pang; ++b)
+                    for (int c = 0; c < pang; ++c) {
+                        double th = L.dang * (it + 0.5 * (ca.t[b] + 1.0));
+                        double ph = L.dang * (ip + 0.5 * (ca.t[c] + 1.0));
+                        size_t o = ((((size_t)it * 2 * L.nc + ip) * pang + b) * pang + c) * 3;
+                        L.node_dir[o] = std::sin(th) * std::cos(ph);
+                        L.node_dir[o + 1] = std::sin(th) * std::sin(ph);
+                        L.node_dir[o + 2] = std::cos(th);
+                    }
+    }
+
+    // Relevant cone segments, sweeping d = 3..D (eq. defallrelevantconesegments):
+    // (i) the cone of every cousin point, (ii) for d >= 4 the cone of every
+    // interpolation point of the parent's relevant cones.
+    int64_t n_dilated = 0;
+    for (int d = 3; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        const int64_t ncone = (int64_t)L.ncell * L.ns;
+        const int64_t wpb = (ncone + 63) / 64;
+        std::vector<uint64_t> prim((size_t)L.nbox * wpb, 0), dil;
+        if (dilate) dil.assign((size_t)L.nbox * wpb, 0);
+        const double tol = kDilateTol;
+        auto mark = [&](int64_t b, const ConeLoc& c) {
+            uint64_t* P = &prim[(size_t)b * wpb];
+            int64_t bit = (int64_t)c.cell * L.ns + c.is;
+            P[bit >> 6] |= 1ull << (bit & 63);
+            if (!dilate) return;
+            int ls[3] = {c.is, c.is, c.is}, lt[3] = {c.it, c.it, c.it}, lp[3] = {c.ip, c.ip, c.ip};
+            int nsv = 1, ntv = 1, npv = 1;
+            if (c.ts > 1.0 - tol && c.is + 1 < L.ns) ls[nsv++] = c.is + 1;
+            if (c.ts < -1.0 + tol && c.is > 0) ls[nsv++] = c.is - 1;
+            if (c.tt > 1.0 - tol && c.it + 1 < L.nc) lt[ntv++] = c.it + 1;
+            if (c.tt < -1.0 + tol && c.it > 0) lt[ntv++] = c.it - 1;
+            if (c.tp > 1.0 - tol) lp[npv++] = (c.ip + 1) % (2 * L.nc);
+            if (c.tp < -1.0 + tol) lp[npv++] = (c.ip + 2 * L.nc - 1) % (2 * L.nc);
+            if (nsv * ntv * npv == 1) return;
+            uint64_t* Q = &dil[(size_t)b * wpb];
+            for (int i = 0; i < nsv; ++i)
+                for (int j = 0; j < ntv; ++j)
+                    for (int k = 0; k < npv; ++k) {
+                        int64_t cb = ((int64_t)lt[j] * 2 * L.nc + lp[k]) * L.ns + ls[i];
+                        Q[cb >> 6] |= 1ull << (cb & 63);
+                    }
+        };
+        const HostLevel* Lp = &hp.L[d - 1];
+        parallel_for(L.nbox, [&](int64_t b) {
+            const double* ctr = &L.box_ctr[3 * b];
+            for (int32_t ci = L.cou_start[b]; ci < L.cou_start[b + 1]; ++ci) {
+                int32_t c = L.cou[ci];
+                for (int32_t j = L.box_start[c]; j < L.box_start[c + 1]; ++j) {
+                    ConeLoc cl;
+                    cone_locate(hp.pts[3 * j] - ctr[0], hp.pts[3 * j + 1] - ctr[1], hp.pts[3 * j + 2] - ctr[2], L.h,
+                                L.ds, L.dang, L.ns, L.nc, cl);
+                    mark(b, cl);
+                }
+            }
+            if (d >= 4) {
+                int32_t p = L.parent[b];
+                double o[3];
+                for (int a = 0; a < 3; ++a) o[a] = ((L.box_oct[b] >> a) & 1) ? 0.5 * L.H : -0.5 * L.H;
+                for (int32_t sl = Lp->slot_start[p]; sl < Lp->slot_start[p + 1]; ++sl) {
+                    int32_t pc = Lp->slot_cone[sl];
+                    int pcell = pc / Lp->ns, pis = pc % Lp->ns;
+                    for (int a = 0; a < ps; ++a) {
+                        double rr = Lp->node_r[(size_t)pis * ps + a];
+                        for (int bb = 0; bb < pang; ++bb)
+                            for (int cc = 0; cc < pang; ++cc) {
+                                const double* dir = &Lp->node_dir[(((size_t)pcell * pang + bb) * pang + cc) * 3];
+                                double v[3];
+                                node_minus(rr, dir, o, v);
+                                ConeLoc cl;
+                                cone_locate(v[0], v[1], v[2], L.h, L.ds, L.dang, L.ns, L.nc, cl);
+                                mark(b, cl);
+                            }
+                    }
+                }
+            }
+        }, 1);
+        // Compact into per-cell masks and slots.
+        if (dilate) {
+            std::atomic<int64_t> nd{0};
+            parallel_for(L.nbox, [&](int64_t b) {
+                int64_t c = 0;
+                for (int64_t w = 0; w < wpb; ++w) {
+                    uint64_t extra = dil[(size_t)b * wpb + w] & ~prim[(size_t)b * wpb + w];
+                    c += __builtin_popcountll(extra);
+                    prim[(size_t)b * wpb + w] |= extra;
+                }
+                nd += c;
+            }, 16);
+            n_dilated += nd.load();
+        }
+        std::vector<int32_t> cnt(L.nbox);
+        parallel_for(L.nbox, [&](int64_t b) {
+            int64_t c = 0;
+            for (int64_t w = 0; w < wpb; ++w) c += __builtin_popcountll(prim[(size_t)b * wpb + w]);
+            cnt[b] = (int32_t)c;
+        }, 16);
+        L.slot_start.assign(L.nbox + 1, 0);
+        for (int64_t b = 0; b < L.nbox; ++b) {
+            if ((int64_t)L.slot_start[b] + cnt[b] > INT32_MAX) {
+                code = IFGF_E_UNSUPPORTED;
+                return "too many relevant cones at level " + std::to_string(d);
+            }
+            L.slot_start[b + 1] = L.slot_start[b] + cnt[b];
+        }
+        L.nslots = L.slot_start[L.nbox];
+        L.slot_box.resize(L.nslots);
+        L.slot_cone.resize(L.nslots);
+        L.cell_base.assign((size_t)L.nbox * L.ncell, 0);
+        L.cell_mask.assign((size_t)L.nbox * L.ncell * L.W, 0);
+        parallel_for(L.nbox, [&](int64_t b) {
+            const uint64_t* P = &prim[(size_t)b * wpb];
+            int32_t slot = L.slot_start[b];
+            for (int cell = 0; cell < L.ncell; ++cell) {
+                L.cell_base[(size_t)b * L.ncell + cell] = slot;
+                uint64_t* M = &L.cell_mask[((size_t)b * L.ncell + cell) * L.W];
+                int64_t base = (int64_t)cell * L.ns;
+                for (int is = 0; is < L.ns; ++is) {
+                    int64_t bit = base + is;
+                    if ((P[bit >> 6] >> (bit & 63)) & 1ull) {
+                        M[is >> 6] |= 1ull << (is & 63);
+                        L.slot_box[slot] = (int32_t)b;
+                        L.slot_cone[slot] = (int32_t)(base + is);
+                        ++slot;
+                    }
+                }
+            }
+        }, 1);
+    }
+    for (int d = 1; d < 3 && d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        L.slot_start.assign(L.nbox + 1, 0);
+    }
+
+    // Statistics.
+    ifgf_stats& st = hp.stats;
+    std::memset(&st, 0, sizeof(st));
+    st.D = D;
+    st.n_points = (int32_t)n;
+    st.H1 = H1;
+    for (int a = 0; a < 3; ++a) st.x1[a] = hp.x1[a];
+    st.kappa = kappa;
+    st.ps = ps;
+    st.pang = pang;
+    for (int d = 1; d <= D; ++d) {
+        const HostLevel& L = hp.L[d];
+        st.ns[d] = L.ns;
+        st.nc[d] = L.nc;
+        st.n_boxes[d] = L.nbox;
+        st.n_cones[d] = L.nslots;
+        st.n_cousin_boxes[d] = L.cou_start[L.nbox];
+        int64_t mx = 0, ce = 0, pe = 0;
+        for (int64_t b = 0; b < L.nbox; ++b) {
+            mx = std::max<int64_t>(mx, L.cou_start[b + 1] - L.cou_start[b]);
+            for (int32_t ci = L.cou_start[b]; ci < L.cou_start[b + 1]; ++ci) {
+                int32_t c = L.cou[ci];
+                ce += L.box_start[c + 1] - L.box_start[c];
+            }
+            if (d >= 4) {
+                int32_t p = L.parent[b];
+                pe += (int64_t)(hp.L[d - 1].slot_start[p + 1] - hp.L[d - 1].slot_start[p]) * hp.P;
+            }
+        }
+        st.max_cousin_boxes[d] = mx;
+        st.n_cousin_evals[d] = ce;
+        st.n_parent_evals[d] = pe;
+    }
+    {
+        const HostLevel& L = hp.L[D];
+        int64_t leaf = 0, nearp = 0;
+        for (int64_t b = 0; b < L.nbox; ++b) {
+            int64_t nb = L.box_start[b + 1] - L.box_start[b];
+            leaf += (int64_t)(L.slot_start[b + 1] - L.slot_start[b]) * hp.P * nb;
+            for (int32_t qi = L.nbr_start[b]; qi < L.nbr_start[b + 1]; ++qi) {
+                int32_t q = L.nbr[qi];
+                nearp += nb * (L.box_start[q + 1] - L.box_start[q]);
+            }
+        }
+        st.n_leaf_pairs = leaf;
+        st.n_near_pairs = nearp - n;
+    }
+    st.n_dilated = n_dilated;
+    st.t_plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    code = IFGF_OK;
+    return std::string();
+}
+
+}  // namespace ifgf

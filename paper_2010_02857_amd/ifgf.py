@@ -1,0 +1,273 @@
+"""Python binding of libifgf.so (C ABI in include/ifgf.h).
+
+Argument marshalling only: every step of the operator runs in the HIP
+library.  PyTorch supplies device memory and the current stream.  If the
+library has not been built, every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libifgf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ifgf.h")
+MAX_LEVELS = 24
+
+FP64 = 0
+MIXED = 1
+
+_STATUS = {0: "IFGF_OK", 1: "IFGF_E_INVALID_ARG", 2: "IFGF_E_OUT_OF_MEMORY", 3: "IFGF_E_HIP",
+           4: "IFGF_E_UNSUPPORTED", 5: "IFGF_E_INTERNAL"}
+
+
+class IFGFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("leaf_ns", ctypes.c_int32),
+        ("leaf_nc", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("max_nrhs", ctypes.c_int32),
+        ("store_levels", ctypes.c_int32),
+        ("host_only", ctypes.c_int32),
+        ("no_dilate", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("workspace_limit", ctypes.c_size_t),
+    ]
+
+
+_L = MAX_LEVELS + 1
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int32),
+        ("n_points", ctypes.c_int32),
+        ("H1", ctypes.c_double),
+        ("x1", ctypes.c_double * 3),
+        ("kappa", ctypes.c_double),
+        ("ps", ctypes.c_int32),
+        ("pang", ctypes.c_int32),
+        ("ns", ctypes.c_int32 * _L),
+        ("nc", ctypes.c_int32 * _L),
+        ("n_boxes", ctypes.c_int64 * _L),
+        ("n_cones", ctypes.c_int64 * _L),
+        ("n_cousin_boxes", ctypes.c_int64 * _L),
+        ("max_cousin_boxes", ctypes.c_int64 * _L),
+        ("n_cousin_evals", ctypes.c_int64 * _L),
+        ("n_parent_evals", ctypes.c_int64 * _L),
+        ("n_leaf_pairs", ctypes.c_int64),
+        ("n_near_pairs", ctypes.c_int64),
+        ("n_dilated", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+        ("t_plan_s", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2010_02857_amd._build.build() "
+                               "(or __graft_entry__.build()) before using the IFGF operator")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.ifgf_plan_create.argtypes = [P, I64, ctypes.c_double, I32, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+        L.ifgf_apply.argtypes = [P, P, I32, P, P]
+        L.ifgf_apply_adjoint.argtypes = [P, P, I32, P, P]
+        L.ifgf_grad_targets.argtypes = [P, P, P, I32, P, P]
+        L.ifgf_plan_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        L.ifgf_plan_check.argtypes = [P, ctypes.POINTER(I64)]
+        L.ifgf_plan_destroy.argtypes = [P]
+        L.ifgf_status_string.argtypes = [ctypes.c_int]
+        L.ifgf_status_string.restype = ctypes.c_char_p
+        L.ifgf_last_error.argtypes = []
+        L.ifgf_last_error.restype = ctypes.c_char_p
+        for f in (L.ifgf_plan_create, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
+                  L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions include/ifgf.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|ifgf_status)\s+(ifgf_\w+)\s*\(", text, re.M)))
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().ifgf_last_error().decode(errors="replace")
+        raise IFGFError(rc, msg)
+
+
+class Plan:
+    """An IFGF plan over a fixed point set (sources = targets).
+
+    points     (n, 3) float64 array-like (host); copied.
+    k          wavenumber >= 0.
+    levels     D, or 0 for H_D about a quarter wavelength.
+    degrees    (P_s, P_ang) Chebyshev nodes per cone direction.
+    precision  "fp64" (complex128 I/O) or "mixed" (complex64 I/O).
+    """
+
+    def __init__(self, points, k: float, levels: int = 0, degrees=(3, 5), precision: str = "fp64",
+                 leaf=(1, 2), max_nrhs: int = 16, store_levels: int = -1, host_only: bool = False,
+                 dilate: bool = True, workspace_limit: int = 0, device=None):
+        if hasattr(points, "detach"):
+            points = points.detach().cpu().numpy()
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+        self.n = pts.shape[0]
+        self.k = float(k)
+        self.precision = precision
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        opt = Options(int(leaf[0]), int(leaf[1]), FP64 if precision == "fp64" else MIXED, int(max_nrhs),
+                      int(store_levels), 1 if host_only else 0, 0 if dilate else 1, 0, int(workspace_limit))
+        deg = (ctypes.c_int32 * 2)(int(degrees[0]), int(degrees[1]))
+        h = ctypes.c_void_p()
+        self._h = None
+        self.host_only = host_only
+        self.device = None
+        if not host_only:
+            import torch
+            self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                       else torch.device(device).index or 0)
+            with torch.cuda.device(self.device):
+                _check(lib().ifgf_plan_create(pts.ctypes.data_as(ctypes.c_void_p), self.n, self.k, int(levels),
+                                              ctypes.cast(deg, ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(h)))
+        else:
+            _check(lib().ifgf_plan_create(pts.ctypes.data_as(ctypes.c_void_p), self.n, self.k, int(levels),
+                                          ctypes.cast(deg, ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+
+    # -- housekeeping
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().ifgf_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib().ifgf_plan_stats(self._h, ctypes.byref(st)))
+        D = st.D
+        out = {"D": D, "n_points": st.n_points, "H1": st.H1, "x1": list(st.x1), "kappa": st.kappa,
+               "ps": st.ps, "pang": st.pang, "n_leaf_pairs": st.n_leaf_pairs, "n_near_pairs": st.n_near_pairs,
+               "n_dilated": st.n_dilated, "device_bytes": st.device_bytes, "t_plan_s": st.t_plan_s}
+        for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
+                    "n_parent_evals"):
+            arr = getattr(st, key)
+            out[key] = [int(arr[d]) for d in range(D + 1)]
+        return out
+
+    def misses(self) -> int:
+        m = ctypes.c_int64()
+        _check(lib().ifgf_plan_check(self._h, ctypes.byref(m)))
+        return int(m.value)
+
+    # -- operator
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def _prep(self, a):
+        import torch
+        if not isinstance(a, torch.Tensor) or not a.is_cuda:
+            raise TypeError("expected a CUDA (HIP) tensor")
+        if a.dtype != self.dtype:
+            raise TypeError(f"expected {self.dtype}, got {a.dtype}")
+        squeeze = a.dim() == 1
+        a2 = a.reshape(1, -1) if squeeze else a
+        if a2.dim() != 2 or a2.shape[1] != self.n:
+            raise ValueError(f"expected shape (nrhs, {self.n}) or ({self.n},)")
+        return a2.contiguous(), squeeze
+
+    def _stream(self, t):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+    def apply(self, a, adjoint: bool = False):
+        """I = IFGF(a) (or the adjoint operator applied to a)."""
+        import torch
+        a2, squeeze = self._prep(a)
+        out = torch.empty_like(a2)
+        f = lib().ifgf_apply_adjoint if adjoint else lib().ifgf_apply
+        _check(f(self._h, ctypes.c_void_p(a2.data_ptr()), a2.shape[0], ctypes.c_void_p(out.data_ptr()),
+                 self._stream(a2)))
+        return out.reshape(-1) if squeeze else out
+
+    def adjoint(self, v):
+        return self.apply(v, adjoint=True)
+
+    def grad_targets(self, a, g):
+        """sum_r Re(conj(g_r) dI_r/dx) for every point, (n, 3) float64."""
+        import torch
+        a2, _ = self._prep(a)
+        g2, _ = self._prep(g)
+        if g2.shape != a2.shape:
+            raise ValueError("grad_out must match the densities' shape")
+        out = torch.empty((self.n, 3), dtype=torch.float64, device=a2.device)
+        _check(lib().ifgf_grad_targets(self._h, ctypes.c_void_p(a2.data_ptr()), ctypes.c_void_p(g2.data_ptr()),
+                                       a2.shape[0], ctypes.c_void_p(out.data_ptr()), self._stream(a2)))
+        return out
+
+
+def _function():
+    import torch
+
+    class IFGFFunction(torch.autograd.Function):
+        """I = IFGF(a) at the plan's points; backward gives the density
+        gradient through the adjoint operator and the target-coordinate
+        gradient through the differentiated interpolants."""
+
+        @staticmethod
+        def forward(ctx, plan, a, targets):
+            out = plan.apply(a)
+            ctx.plan = plan
+            ctx.save_for_backward(a)
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            (a,) = ctx.saved_tensors
+            plan = ctx.plan
+            g = g.contiguous()
+            ga = plan.adjoint(g) if ctx.needs_input_grad[1] else None
+            gx = None
+            if ctx.needs_input_grad[2]:
+                gx = plan.grad_targets(a, g)
+            return None, ga, gx
+
+    return IFGFFunction
+
+
+_FN = None
+
+
+def apply(plan: Plan, a, targets=None):
+    """Differentiable IFGF matvec.  `targets` is the plan's (n, 3) point
+    tensor, passed so that a gradient with respect to it can flow."""
+    global _FN
+    if _FN is None:
+        _FN = _function()
+    return _FN.apply(plan, a, targets)

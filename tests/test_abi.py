@@ -1,0 +1,128 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, validates its arguments, and its host-built hierarchy has exactly the
+counts of the independently written oracle (no GPU needed)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_02857_amd import ifgf, inputs
+
+
+def test_library_exports_every_header_symbol():
+    lib = ifgf.lib()
+    names = ifgf.header_symbols()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = ifgf.lib()
+    for code, name in ifgf._STATUS.items():
+        assert lib.ifgf_status_string(code).decode() == name
+
+
+@pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46"])
+def test_host_plan_matches_oracle_counts(case):
+    """Relevant boxes, cousins, relevant cones, child-to-parent and near-field
+    work per level equal those of the CPU oracle (Sec. 3.3.2)."""
+    kw = {}
+    okw = {}
+    if case == "cfg1":
+        w = inputs.WORKLOADS[1]
+        p, k = w.points(), w.kappa
+    elif case == "cloud":
+        p, k = inputs.random_box_points(3000, 5), 25.0
+        kw = okw = {"levels": 5}
+    elif case == "laplace":
+        p, k = inputs.cube_sphere(20), 0.0
+    elif case == "leaf23":
+        p, k = inputs.cube_sphere(20, 0.25), 15.0
+        kw = {"leaf": (2, 3)}
+        okw = {"leaf": (2, 3)}
+    else:
+        p, k = inputs.cube_sphere(20), 10.0
+        kw = {"degrees": (4, 6)}
+        okw = {"degrees": (4, 6)}
+    plan = ifgf.Plan(p, k, host_only=True, dilate=False, **kw)
+    st = plan.stats()
+    so = oracle.ifgf(p, inputs.densities(1, 1, p.shape[0]), k, **okw)["stats"]
+    assert st["D"] == so["D"]
+    for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
+                "n_parent_evals"):
+        assert st[key] == so[key], key
+    assert st["n_near_pairs"] == so["n_near_pairs"]
+    assert abs(st["H1"] - so["H1"]) == 0.0
+
+
+def test_auto_levels_quarter_wavelength():
+    """levels = 0 picks H_D ~ lambda / 4 (Sec. 4): D = 5 for kappa a = 4 pi and
+    D = 8 for 32 pi on the unit sphere."""
+    p = inputs.cube_sphere(32)
+    assert ifgf.Plan(p, 4 * math.pi, host_only=True).stats()["D"] == 5
+    assert ifgf.Plan(p, 32 * math.pi, host_only=True).stats()["D"] == 8
+    st = ifgf.Plan(p, 32 * math.pi, host_only=True).stats()
+    HD = st["H1"] / 2 ** (st["D"] - 1)
+    lam = 2 * math.pi / (32 * math.pi)
+    assert 0.17 * lam < HD < 0.35 * lam
+
+
+def test_dilation_only_adds_cones():
+    p = inputs.cube_sphere(24)
+    a = ifgf.Plan(p, 20.0, host_only=True, dilate=False).stats()
+    b = ifgf.Plan(p, 20.0, host_only=True, dilate=True).stats()
+    assert all(y >= x for x, y in zip(a["n_cones"], b["n_cones"]))
+    assert sum(b["n_cones"]) - sum(a["n_cones"]) >= b["n_dilated"] >= 0
+
+
+def _create(points, n, k=1.0, levels=0, degrees=(3, 5), opt=None):
+    lib = ifgf.lib()
+    h = ctypes.c_void_p()
+    deg = (ctypes.c_int32 * 2)(*degrees)
+    o = opt or ifgf.Options(0, 0, 0, 0, 0, 1, 0, 0, 0)
+    ptr = None if points is None else points.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.ifgf_plan_create(ptr, n, k, levels, ctypes.cast(deg, ctypes.c_void_p), ctypes.byref(o),
+                              ctypes.byref(h))
+    if rc == 0:
+        lib.ifgf_plan_destroy(h)
+    return rc, lib.ifgf_last_error().decode()
+
+
+def test_invalid_arguments_are_rejected():
+    p = inputs.random_box_points(50, 1)
+    assert _create(p, 50)[0] == 0
+    assert _create(None, 50)[0] == 1
+    assert _create(p, 1)[0] == 1
+    assert _create(p, 50, k=-1.0)[0] == 1
+    assert _create(p, 50, k=float("nan"))[0] == 1
+    assert _create(p, 50, levels=1)[0] == 1
+    assert _create(p, 50, levels=30)[0] == 1
+    assert _create(p, 50, degrees=(7, 7))[0] == 4
+    q = p.copy()
+    q[7] = q[3]
+    rc, msg = _create(q, 50)
+    assert rc == 1 and "pairwise different" in msg
+    q = p.copy()
+    q[2, 1] = np.inf
+    assert _create(q, 50)[0] == 1
+    o = ifgf.Options(0, 0, 5, 0, 0, 1, 0, 0, 0)
+    assert _create(p, 50, opt=o)[0] == 1
+
+
+def test_host_only_plan_refuses_apply():
+    plan = ifgf.Plan(inputs.random_box_points(40, 2), 3.0, host_only=True)
+    lib = ifgf.lib()
+    buf = (ctypes.c_double * 160)()
+    rc = lib.ifgf_apply(plan._h, ctypes.cast(buf, ctypes.c_void_p), 1,
+                        ctypes.cast(ctypes.byref(buf, 8 * 80), ctypes.c_void_p), None)
+    assert rc == 4
+    assert lib.ifgf_plan_destroy(None) == 0
+
+
+def test_two_points_single_level():
+    p = np.array([[0.0, 0.0, 0.0], [0.5, 0.0, 0.0]])
+    st = ifgf.Plan(p, 3.0, host_only=True).stats()
+    assert st["D"] == 2 and st["n_near_pairs"] == 2 and sum(st["n_cones"]) == 0

@@ -153,6 +153,23 @@ def test_cone_round_trip_and_cover():
             assert 0.0 <= sth[1] <= math.pi and 0.0 <= sth[2] < 2 * math.pi
 
 
+def test_cone_faces_belong_to_upper_interval():
+    """The cone intervals are half-open (eq. defconedomain): a point on a face
+    lies in the interval above it; phi wraps at 2 pi; theta = pi is in the
+    last (closed) polar interval."""
+    c = np.zeros(3)
+    H, ns, nc = 1.0, 2, 4
+    cases = [((1.0, -1.0, 0.0), 2, 7), ((1.0, 1.0, 0.0), 2, 1), ((1.0, 0.0, 0.0), 2, 0),
+             ((-1.0, 1.0, 0.0), 2, 3), ((0.0, 0.0, -1.0), 3, 0)]
+    for v, it, ip in cases:
+        idx, loc, _ = oracle.cone_coords(c, H, ns, nc, np.array(v) * 5.0)
+        assert idx[1] == it and idx[2] == ip, (v, idx)
+    idx, loc, _ = oracle.cone_coords(c, H, ns, nc, np.array([5.0, -1e-300, 1.0]))
+    assert idx[2] == 0 and abs(loc[2] + 1.0) < 1e-9
+    idx, loc, _ = oracle.cone_coords(c, H, ns, nc, np.array([0.0, 0.0, -5.0]))
+    assert idx[1] == nc - 1 and abs(loc[1] - 1.0) < 1e-12
+
+
 def test_separation_gives_s_below_eta():
     """Targets outside the 3x3x3 neighbourhood of a box have s <= sqrt(3)/3 (Sec. 3.1)."""
     rng = np.random.default_rng(8)
