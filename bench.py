@@ -1,0 +1,247 @@
+"""Benchmark: IFGF matvecs per second on one MI355X.
+
+Workload: unit sphere, N = 393,216 points (6 x 256 x 256 cube-sphere),
+kappa = 32 pi (diameter 32 wavelengths), complex Gaussian densities,
+(P_s, P_ang) = (3, 5) Chebyshev nodes, 1 x 2 x 4 leaf cones, H_D about a
+quarter wavelength.  One timed step is one IFGF matvec in the mixed path
+(FP32 arithmetic, FP64 geometry and phase reduction) with inputs resident in
+device memory.  Plan construction is excluded from the timed region and
+reported separately (as the paper reports T_pre apart from T_acc).
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for roofline fractions.
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+# The paper's time for this workload (Table timings2: sphere, N = 393216,
+# kappa a = 32 pi, eps = 1.13e-3): 133 s per matvec on one core of an
+# i7-8750H.  Another machine's number: context, not a target.
+PAPER_MATVECS_PER_S = 1.0 / 133.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ifgf_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2010_02857_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stage_work(stats: dict, stage: str, nrhs: int, P: int, elem_bytes: int) -> tuple[float, float]:
+    """Algorithmic (flops, bytes) of one apply's launches of a stage.
+
+    child_to_parent / cousin_eval: per interpolation, P complex-by-real
+    multiply-adds per right-hand side (4 P flops) plus the complex product with
+    the centred-factor ratio (8 flops); bytes: the cone values read once and
+    the parent values written once (child_to_parent), or the cone values read
+    once plus the output read and written (cousin_eval).
+    leaf_nodes / nearfield: one complex multiply-add (8 flops) per source pair
+    and right-hand side; bytes: densities read and values written once."""
+    D = stats["D"]
+    cones = stats["n_cones"]
+    n = stats["n_points"]
+    if stage == "child_to_parent":
+        ev = sum(stats["n_parent_evals"][3:D + 1])
+        flops = ev * nrhs * (4 * P + 8)
+        read = sum(cones[d] for d in range(4, D + 1))        # child cone values, once
+        write = sum(cones[d] for d in range(3, D))          # parent cone values, once
+        return flops, (read + write) * P * nrhs * elem_bytes
+    if stage == "cousin_eval":
+        ev = sum(stats["n_cousin_evals"][3:D + 1])
+        flops = ev * nrhs * (4 * P + 8)
+        byts = sum(cones[d] for d in range(3, D + 1)) * P * nrhs * elem_bytes + (D - 2) * 2 * n * nrhs * elem_bytes
+        return flops, byts
+    if stage == "leaf_nodes":
+        return stats["n_leaf_pairs"] * nrhs * 8.0, cones[D] * P * nrhs * elem_bytes + n * nrhs * elem_bytes
+    if stage == "nearfield":
+        return stats["n_near_pairs"] * nrhs * 8.0, 2 * n * nrhs * elem_bytes
+    return 0.0, 2 * n * nrhs * elem_bytes
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / batched / adjoint / gradient timings")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import oracle
+    from paper_2010_02857_amd import ifgf, inputs
+
+    torch.cuda.set_device(0)
+    w = inputs.WORKLOADS[2]
+    p = w.points()
+    n = p.shape[0]
+    a = w.densities()
+    P = 75
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    # ---- plan (excluded from the timed region)
+    t0 = time.time()
+    plan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=16, store_levels=0)
+    t_plan = time.time() - t0
+    st = plan.stats()
+    log(f"plan: N={n} D={st['D']} cones/level={st['n_cones'][3:]} {t_plan:.1f}s")
+    x = torch.from_numpy(a).to(torch.complex64).cuda()
+
+    for _ in range(args.warmup):
+        plan.apply(x)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K matvecs, per-stage HIP events on the same stream
+    plan.profile(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        out = plan.apply(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    stages = plan.stage_times()
+    plan.profile(False)
+    ms_step = ms_total / args.steps
+    value = 1000.0 / ms_step
+    log(f"mixed 1 RHS: {ms_step:.3f} ms/matvec; stages {stages}")
+    assert plan.misses() == 0
+
+    # ---- accuracy of this result against the direct sum (1000 targets)
+    idx = inputs.error_subset(2, n, 1000)
+    d = oracle.direct(p, a, w.kappa, targets=p[idx], skip=idx)
+    eps = float(np.linalg.norm(out.cpu().numpy()[0, idx] - d[0]) / np.linalg.norm(d[0]))
+    log(f"eps_M vs direct = {eps:.3e}")
+
+    # ---- roofline of the dominant forward kernel
+    fwd = ["permute_in", "nearfield", "leaf_nodes", "cousin_eval", "child_to_parent", "permute_out"]
+    dom = max(fwd, key=lambda s: stages[s][0])
+    dom_ms, dom_launches = stages[dom]
+    flops, byts = stage_work(st, dom, 1, P, 8)
+    per_launch_s = dom_ms / 1e3 / dom_launches
+    launches_per_apply = dom_launches / args.steps
+    flops_per_launch = flops / launches_per_apply
+    bytes_per_launch = byts / launches_per_apply
+    achieved = flops_per_launch / per_launch_s / 1e12
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_sphere393216.json")
+    if os.path.exists(tf):
+        rec = json.load(open(tf))
+        if rec.get("kernel_source_hash") == kernel_source_hash() and rec.get("nrhs") == 1:
+            traffic = rec.get("hbm_bytes_per_launch")
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
+                "avg_launch_ms": round(per_launch_s * 1e3, 4), "launches_per_step": launches_per_apply,
+                "algorithmic_flops_per_launch": flops_per_launch,
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "achieved_algorithmic_GBps": round(bytes_per_launch / per_launch_s / 1e9, 1),
+                "hbm_peak_GBps": PEAK_HBM_GBS}
+
+    result = {
+        "metric": "IFGF matvecs/s at rel err <=1e-3 (FP64 vs mixed, 1 vs batched RHS); N^2/s",
+        "value": round(value, 3),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_MATVECS_PER_S, 1),
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere-393216-k32pi", "n": n, "kappa": w.kappa, "nrhs": 1,
+                   "precision": "mixed (f32 arithmetic, f64 geometry)", "degrees": [3, 5], "leaf_cones": [1, 2, 4],
+                   "levels": st["D"]},
+        "eps_vs_direct": eps,
+        "n2_per_s": n * n * value,
+        "t_plan_s": round(t_plan, 2),
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
+        "roofline": roofline,
+    }
+
+    # ---- the other paths of the metric (timed outside the main region)
+    if not args.no_extras:
+        def time_fn(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            s0 = torch.cuda.Event(enable_timing=True)
+            s1 = torch.cuda.Event(enable_timing=True)
+            s0.record()
+            for _ in range(reps):
+                fn()
+            s1.record()
+            torch.cuda.synchronize()
+            return s0.elapsed_time(s1) / reps
+
+        ms_adj = time_fn(lambda: plan.adjoint(x), 5)
+        g = torch.from_numpy(inputs.densities(402, 1, n)).to(torch.complex64).cuda()
+        ms_grad = time_fn(lambda: plan.grad_targets(x, g), 3)
+        x16 = torch.from_numpy(inputs.densities(2, 16, n)).to(torch.complex64).cuda()
+        ms_b16 = time_fn(lambda: plan.apply(x16), 3)
+        del plan
+        torch.cuda.empty_cache()
+        plan64 = ifgf.Plan(p, w.kappa, precision="fp64", max_nrhs=1, store_levels=0)
+        x64 = torch.from_numpy(a).cuda()
+        ms64 = time_fn(lambda: plan64.apply(x64), 5)
+        out64 = plan64.apply(x64).cpu().numpy()
+        eps64 = float(np.linalg.norm(out64[0, idx] - d[0]) / np.linalg.norm(d[0]))
+        mixed_vs_fp64 = float(np.linalg.norm(out.cpu().numpy() - out64) / np.linalg.norm(out64))
+        del plan64
+        result.update({
+            "fp64_1rhs_matvecs_per_s": round(1000.0 / ms64, 3),
+            "fp64_eps_vs_direct": eps64,
+            "mixed_vs_fp64_rel": mixed_vs_fp64,
+            "speedup_mixed_vs_fp64_1rhs": round(ms64 / ms_step, 3),
+            "mixed_16rhs_matvecs_per_s": round(16 * 1000.0 / ms_b16, 3),
+            "speedup_mixed16_vs_fp64_1rhs": round(16 * ms64 / ms_b16, 3),
+            "adjoint_matvecs_per_s": round(1000.0 / ms_adj, 3),
+            "grad_targets_per_s": round(1000.0 / ms_grad, 3),
+        })
+        log(f"fp64 {ms64:.3f} ms, batched16 {ms_b16:.3f} ms, adjoint {ms_adj:.3f} ms, grad {ms_grad:.3f} ms")
+
+    # ---- the oracle on the host cores (one full matvec of the same workload)
+    if not args.no_cpu_baseline:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.time()
+        oracle.ifgf(p, a, w.kappa)
+        t_or = time.time() - t0
+        result["cpu_baseline"] = {"value": round(1.0 / t_or, 5), "unit": "matvecs/s", "cores": cores,
+                                  "kind": "oracle",
+                                  "sample": "one full FP64 oracle IFGF matvec of the same workload (N=393216, "
+                                            "includes the oracle's own hierarchy construction); "
+                                            f"{t_or:.1f} s"}
+        log(f"oracle: {t_or:.1f} s on {cores} threads")
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

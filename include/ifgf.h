@@ -73,8 +73,9 @@ typedef struct {
                                 the workspaces (0: 16)                        */
     int32_t store_levels;    /* cone values of every level kept after an
                                 apply for ifgf_grad_targets: 1 keep, 0
-                                recompute, -1 (or 0 from zero-init): decided
-                                by memory                                     */
+                                recompute them in the gradient call, -1 keep
+                                them if they fit in a quarter of the free
+                                device memory                                 */
     int32_t host_only;       /* 1: build the hierarchy on the host only (no
                                 GPU use); apply calls return
                                 IFGF_E_UNSUPPORTED but ifgf_plan_stats works */
@@ -108,6 +109,9 @@ typedef struct {
     int64_t n_leaf_pairs;                    /* (cone node, source) pairs, d=D */
     int64_t n_near_pairs;                    /* directly summed pairs           */
     int64_t n_dilated;                       /* cones marked only by dilation   */
+    int64_t n_frames[IFGF_MAX_LEVELS + 1];   /* distinct child-to-parent frames
+                                                tabulated for level d (0: the
+                                                geometry is computed on the fly) */
     int64_t device_bytes;                    /* device memory held by the plan  */
     double t_plan_s;                         /* host seconds to build the plan  */
 } ifgf_stats;
@@ -167,6 +171,31 @@ ifgf_status ifgf_plan_stats(ifgf_plan_t plan, ifgf_stats* out);
 /* Synchronises the plan's last stream and reports how many interpolation
  * queries found no computed cone since the plan was created (must be 0). */
 ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses);
+
+/* Kernel stages of an apply or gradient call, for ifgf_plan_stage_times. */
+typedef enum {
+    IFGF_STAGE_PERMUTE_IN = 0,   /* densities to Morton order                  */
+    IFGF_STAGE_NEARFIELD = 1,    /* direct sums over leaf neighbourhoods       */
+    IFGF_STAGE_LEAF_NODES = 2,   /* F_k^D at the leaf cone interpolation points */
+    IFGF_STAGE_COUSIN_EVAL = 3,  /* interpolation at cousin targets, per level */
+    IFGF_STAGE_CHILD_TO_PARENT = 4, /* interpolation onto parent cone points   */
+    IFGF_STAGE_PERMUTE_OUT = 5,  /* result back to input order                 */
+    IFGF_STAGE_NEAR_GRAD = 6,    /* near-field target gradient                 */
+    IFGF_STAGE_COUSIN_GRAD = 7,  /* far-field target gradient, per level       */
+    IFGF_STAGE_PERMUTE_GRAD = 8, /* gradient back to input order               */
+    IFGF_NUM_STAGES = 9
+} ifgf_stage;
+
+/* Stage timing with HIP events recorded on the caller's stream around every
+ * kernel launch.  enable = 1 starts recording (and clears the totals),
+ * enable = 0 stops.  Off by default; recording adds two events per launch. */
+ifgf_status ifgf_plan_profile(ifgf_plan_t plan, int32_t enable);
+
+/* Synchronises, then returns per stage the summed kernel milliseconds and the
+ * number of launches recorded since profiling was enabled (arrays of
+ * IFGF_NUM_STAGES entries, host).  Totals keep accumulating until the next
+ * ifgf_plan_profile(plan, 1). */
+ifgf_status ifgf_plan_stage_times(ifgf_plan_t plan, double* ms, int64_t* launches);
 
 /* Releases the plan and all memory it owns.  NULL is accepted. */
 ifgf_status ifgf_plan_destroy(ifgf_plan_t plan);

@@ -50,10 +50,12 @@ void release(ifgf::DevicePlan& p)
         (void)hipDeviceSynchronize();
         for (void* q : p.ws_allocs) (void)hipFree(q);
         for (void* q : p.allocs) (void)hipFree(q);
+        for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     p.ws_allocs.clear();
     p.allocs.clear();
+    p.events.clear();
 }
 
 hipError_t upload_plan(ifgf::DevicePlan& p)
@@ -115,6 +117,35 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
         }
         if (parent_of_interp) {
             if ((e = upload(p, H.chl_start, &L.chl_start)) != hipSuccess) return e;
+        }
+        L.use_frames = H.use_frames ? 1 : 0;
+        if (d >= 4 && H.use_frames) {
+            if ((e = upload(p, H.child_of, &L.child_of)) != hipSuccess) return e;
+            if ((e = upload(p, H.pframe, &L.pframe)) != hipSuccess) return e;
+            if ((e = upload(p, H.fr_key, &L.fr_key)) != hipSuccess) return e;
+            if (p.precision == IFGF_MIXED) {
+                std::vector<float> t(H.fr_t.begin(), H.fr_t.end()), r(H.fr_ratio.begin(), H.fr_ratio.end());
+                const float* dt = nullptr;
+                if ((e = upload(p, t, &dt)) != hipSuccess) return e;
+                L.fr_t = dt;
+                if ((e = upload(p, r, &dt)) != hipSuccess) return e;
+                L.fr_ratio = dt;
+            } else {
+                const double* dt = nullptr;
+                if ((e = upload(p, H.fr_t, &dt)) != hipSuccess) return e;
+                L.fr_t = dt;
+                if ((e = upload(p, H.fr_ratio, &dt)) != hipSuccess) return e;
+                L.fr_ratio = dt;
+            }
+            L.frame_groups_ok = H.frame_groups_ok ? 1 : 0;
+            if (H.frame_groups_ok) {
+                if ((e = upload(p, H.fr_ngrp, &L.fr_ngrp)) != hipSuccess) return e;
+                if ((e = upload(p, H.fr_gkey, &L.fr_gkey)) != hipSuccess) return e;
+                if ((e = upload(p, H.fr_grp, &L.fr_grp)) != hipSuccess) return e;
+            }
+            // the host copies are no longer needed
+            std::vector<double>().swap(H.fr_t);
+            std::vector<double>().swap(H.fr_ratio);
         }
     }
     return hipSuccess;
@@ -279,6 +310,50 @@ ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses)
     e = hipMemcpy(&m, plan->p.miss, sizeof(m), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "ifgf_plan_check");
     *misses = (int64_t)m;
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_profile(ifgf_plan_t plan, int32_t enable)
+{
+    if (!plan) return fail(IFGF_E_INVALID_ARG, "plan is NULL");
+    ifgf::DevicePlan& p = plan->p;
+    if (p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
+    DeviceGuard g(p.device);
+    if (enable) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "ifgf_plan_profile");
+        p.pending.clear();
+        p.next_event = 0;
+        for (int i = 0; i < IFGF_NUM_STAGES; ++i) {
+            p.stage_ms[i] = 0.0;
+            p.stage_launches[i] = 0;
+        }
+    }
+    p.profiling = enable != 0;
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_stage_times(ifgf_plan_t plan, double* ms, int64_t* launches)
+{
+    if (!plan || !ms || !launches) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    ifgf::DevicePlan& p = plan->p;
+    if (p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
+    DeviceGuard g(p.device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "ifgf_plan_stage_times");
+    for (const auto& q : p.pending) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, p.events[q.e0], p.events[q.e1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        p.stage_ms[q.stage] += t;
+        p.stage_launches[q.stage] += 1;
+    }
+    p.pending.clear();
+    p.next_event = 0;
+    for (int i = 0; i < IFGF_NUM_STAGES; ++i) {
+        ms[i] = p.stage_ms[i];
+        launches[i] = p.stage_launches[i];
+    }
     return IFGF_OK;
 }
 

@@ -18,6 +18,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxNodes = 8;       // Chebyshev nodes per direction, upper bound
 constexpr int kMaxRhsPass = 16;    // right-hand sides handled by one kernel pass
 constexpr double kDilateTol = 1e-9;
+constexpr int kMaxFrameGroups = 16;  // distinct child cones one frame may touch
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).
@@ -129,6 +130,25 @@ struct HostLevel {
     int64_t nslots = 0;
     std::vector<double> node_r;               // [ns][PS] h / s at radial nodes
     std::vector<double> node_dir;             // [ncell][PA][PA][3] unit directions
+    // Child-to-parent frames (levels d >= 4, children at d).  The geometry of
+    // the interpolation points of a parent cone gamma seen from the child in
+    // octant o depends on (gamma, o) only, not on the boxes; a "frame" holds it
+    // for the P points: child cone key (cell * ns + is), local coordinates in
+    // the child cone, and the re-centring ratio G(x, x_k) / G(x, x_j).
+    std::vector<int32_t> child_of;            // [nbox_{d-1}][8] child in octant o, -1
+    bool use_frames = false;                  // frames are shared enough to pay
+    int64_t npairs = 0;                       // (parent slot, child) pairs
+    int64_t nframes = 0;
+    std::vector<int32_t> pframe;              // [nslots_{d-1}][8] frame id, -1: no child
+    std::vector<uint32_t> fr_key;             // [nframes][P]
+    std::vector<double> fr_t;                 // [nframes][P][3]
+    std::vector<double> fr_ratio;             // [nframes][P][2]
+    // the distinct child cones of each frame ("groups") and the group of
+    // every interpolation point, for staging child cones in LDS
+    bool frame_groups_ok = false;             // every frame has <= kMaxFrameGroups
+    std::vector<uint8_t> fr_ngrp;             // [nframes]
+    std::vector<uint32_t> fr_gkey;            // [nframes][kMaxFrameGroups]
+    std::vector<uint8_t> fr_grp;              // [nframes][P]
 };
 
 struct HostPlan {
@@ -168,6 +188,18 @@ struct LevelDev {
     const int32_t* slot_cone;
     const double* node_r;
     const double* node_dir;
+    // child-to-parent frames (children at this level); fr_t / fr_ratio are
+    // float for the mixed path and double for FP64
+    int use_frames;
+    const int32_t* child_of;
+    const int32_t* pframe;
+    const uint32_t* fr_key;
+    const void* fr_t;
+    const void* fr_ratio;
+    int frame_groups_ok;
+    const uint8_t* fr_ngrp;
+    const uint32_t* fr_gkey;
+    const uint8_t* fr_grp;
 };
 
 struct KernelConsts {
@@ -205,10 +237,51 @@ struct DevicePlan {
     void* F[IFGF_MAX_LEVELS + 1] = {};  // cone values per level [nslots][P][rb]
     std::vector<void*> ws_allocs;
     size_t ws_bytes = 0;
+    // stage timing (ifgf_plan_profile)
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    size_t next_event = 0;
+    struct Pending { int stage; size_t e0, e1; };
+    std::vector<Pending> pending;
+    double stage_ms[IFGF_NUM_STAGES] = {};
+    int64_t stage_launches[IFGF_NUM_STAGES] = {};
     // what the stored cone values hold (for gradient reuse)
     const void* stored_dens = nullptr;
     int stored_nrhs = 0;
     bool stored_valid = false;
+};
+
+// Records a HIP event pair around one kernel launch when profiling is on.
+class StageTimer {
+  public:
+    StageTimer(DevicePlan& p, int stage, hipStream_t st) : p_(p), stage_(stage), st_(st)
+    {
+        if (p_.profiling) e0_ = record();
+    }
+    ~StageTimer()
+    {
+        if (p_.profiling && e0_ != (size_t)-1) {
+            size_t e1 = record();
+            if (e1 != (size_t)-1) p_.pending.push_back({stage_, e0_, e1});
+        }
+    }
+
+  private:
+    size_t record()
+    {
+        if (p_.next_event == p_.events.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+            p_.events.push_back(e);
+        }
+        size_t i = p_.next_event++;
+        if (hipEventRecord(p_.events[i], st_) != hipSuccess) return (size_t)-1;
+        return i;
+    }
+    DevicePlan& p_;
+    int stage_;
+    hipStream_t st_;
+    size_t e0_ = (size_t)-1;
 };
 
 // Kernel pipeline entry points (kernels.hip).  `kappa` is signed: -k for

@@ -100,28 +100,51 @@ __device__ inline int lookup(const LevelDev& L, int box, int cell, int is)
 }
 
 // sum_{a,b,c} F[a][b][c][r] Ls[a] Lt[b] Lp[c] for the RB right-hand sides.
+// With one right-hand side the 75-term sum is unrolled completely; with
+// several, only the innermost (c, r) loops are, so that the compiler cannot
+// hoist all P * RB loads at once and spill.
 template <typename T, int PS, int PA, int RB>
 __device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T* Lt, const T* Lp, cpx<T>* v)
 {
 #pragma unroll
     for (int r = 0; r < RB; ++r) v[r].x = v[r].y = (T)0;
+    if constexpr (RB == 1) {
 #pragma unroll
-    for (int a = 0; a < PS; ++a)
+        for (int a = 0; a < PS; ++a)
 #pragma unroll
-        for (int b = 0; b < PA; ++b) {
-            T wab = Ls[a] * Lt[b];
+            for (int b = 0; b < PA; ++b) {
+                T wab = Ls[a] * Lt[b];
+#pragma unroll
+                for (int c = 0; c < PA; ++c) {
+                    T w = wab * Lp[c];
+                    cpx<T> q = F[(a * PA + b) * PA + c];
+                    v[0].x += w * q.x;
+                    v[0].y += w * q.y;
+                }
+            }
+    } else {
+#pragma unroll 1
+        for (int ab = 0; ab < PS * PA; ++ab) {
+            const int a = ab / PA, b = ab - a * PA;
+            T la = Ls[0], lb = Lt[0];
+#pragma unroll
+            for (int i = 1; i < PS; ++i) la = a == i ? Ls[i] : la;
+#pragma unroll
+            for (int i = 1; i < PA; ++i) lb = b == i ? Lt[i] : lb;
+            const T wab = la * lb;
+            const cpx<T>* f = F + ab * PA * RB;
 #pragma unroll
             for (int c = 0; c < PA; ++c) {
-                T w = wab * Lp[c];
-                const cpx<T>* f = F + ((a * PA + b) * PA + c) * RB;
+                const T w = wab * Lp[c];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    cpx<T> q = f[r];
+                    cpx<T> q = f[c * RB + r];
                     v[r].x += w * q.x;
                     v[r].y += w * q.y;
                 }
             }
         }
+    }
 }
 
 // ------------------------------------------------------------------ kernels
@@ -352,6 +375,184 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, Lev
     for (int r = 0; r < RB; ++r) Fp[((size_t)pslot * P + nu) * RB + r] = acc[r];
 }
 
+// Child-to-parent interpolation through tabulated frames: the child cone,
+// local coordinates and re-centring ratio of interpolation point nu of the
+// parent cone of slot `pslot` seen from the child in octant o are read from
+// the frame of (parent cone, o); only the child's slot is looked up.  For
+// the adjoint (kappa < 0) the tabulated ratio is conjugated.
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_child_to_parent_frames(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                                   const cpx<T>* __restrict__ Fc,
+                                                                   cpx<T>* __restrict__ Fp)
+{
+    constexpr int P = PS * PA * PA;
+    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int pslot = (int)(gid / P);
+    int nu = (int)(gid - (size_t)pslot * P);
+    if (pslot >= Lp.nslots) return;
+    const int j = Lp.slot_box[pslot];
+    const T* frt = (const T*)Lc.fr_t;
+    const T* frr = (const T*)Lc.fr_ratio;
+    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int o = 0; o < 8; ++o) {
+        const int f = Lc.pframe[(size_t)pslot * 8 + o];
+        if (f < 0) continue;
+        const int k = Lc.child_of[(size_t)j * 8 + o];
+        const size_t e = (size_t)f * P + nu;
+        const unsigned key = Lc.fr_key[e];
+        const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
+        const int slot = lookup(Lc, k, cell, is);
+        if (slot < 0) {
+            atomicAdd(kc.miss, 1ull);
+            continue;
+        }
+        T Ls[PS], Lt[PA], Lpp[PA];
+        lagrange<T, PS>((double)frt[3 * e], kc.cs, Ls);
+        lagrange<T, PA>((double)frt[3 * e + 1], kc.ca, Lt);
+        lagrange<T, PA>((double)frt[3 * e + 2], kc.ca, Lpp);
+        cpx<T> val[RB];
+        interp<T, PS, PA, RB>(Fc + (size_t)slot * P * RB, Ls, Lt, Lpp, val);
+        const T gr = frr[2 * e], gi = conj_sign * frr[2 * e + 1];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            acc[r].x += val[r].x * gr - val[r].y * gi;
+            acc[r].y += val[r].x * gi + val[r].y * gr;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) Fp[((size_t)pslot * P + nu) * RB + r] = acc[r];
+}
+
+// Child-to-parent interpolation through frames, with the child cones staged
+// in LDS.  A block handles S consecutive parent slots.  It first gathers the
+// (slot, octant, group) entries of all its frames -- each group is one
+// distinct child cone a frame touches, on average 2-3 -- looks up their child
+// slots in parallel, copies each cone once from global memory into LDS, and
+// then every (slot, interpolation point) thread interpolates from LDS for all
+// eight octants.  A block whose cones exceed the LDS capacity GCAP stages
+// them in several rounds.
+template <typename T, int PS, int PA, int RB, int S, int GCAP>
+__global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                                   const cpx<T>* __restrict__ Fc,
+                                                                   cpx<T>* __restrict__ Fp)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int G = kMaxFrameGroups;
+    constexpr int MAXE = S * 8 * G;
+    static_assert(S * P <= kBlock, "block too small");
+    static_assert(S * 8 <= 64, "the (slot, octant) table must fit one wavefront");
+    __shared__ cpx<T> cone[GCAP * P * RB];
+    __shared__ int sof[S * 8];        // frame of (slot, octant), -1 none
+    __shared__ int soff[S * 8 + 1];   // first entry of (slot, octant)
+    __shared__ int staged[MAXE];      // child slot of each entry, -1 missing
+
+    const int tid = threadIdx.x;
+    const int slot0 = blockIdx.x * S;
+    const int s_me = tid / P;
+    const int nu = tid - s_me * P;
+    const int sp = slot0 + s_me;
+    const bool active = s_me < S && sp < Lp.nslots;
+    const T* frt = (const T*)Lc.fr_t;
+    const T* frr = (const T*)Lc.fr_ratio;
+    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+
+    // (slot, octant) frames and an inclusive scan of their group counts
+    if (tid < 64) {
+        int f = -1, ng = 0;
+        if (tid < S * 8) {
+            const int q = slot0 + tid / 8;
+            if (q < Lp.nslots) {
+                f = Lc.pframe[(size_t)q * 8 + (tid & 7)];
+                if (f >= 0) ng = Lc.fr_ngrp[f];
+            }
+        }
+        int x = ng;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            int y = __shfl_up(x, dd, 64);
+            if (tid >= dd) x += y;
+        }
+        if (tid < S * 8) {
+            sof[tid] = f;
+            soff[tid + 1] = x;
+        }
+        if (tid == 0) soff[0] = 0;
+    }
+    __syncthreads();
+    const int nent = soff[S * 8];
+    // child slot of every entry
+    for (int i = tid; i < nent; i += kBlock) {
+        int so = 0;
+        while (soff[so + 1] <= i) ++so;
+        const int f = sof[so];
+        const int g = i - soff[so];
+        const int q = slot0 + so / 8, o = so & 7;
+        const int k = Lc.child_of[(size_t)Lp.slot_box[q] * 8 + o];
+        const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
+        const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
+        staged[i] = lookup(Lc, k, cell, is);
+    }
+    __syncthreads();
+
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int base = 0; base < nent; base += GCAP) {
+        const int cnt = nent - base < GCAP ? nent - base : GCAP;
+        const int total = cnt * P * RB;
+        for (int i = tid; i < total; i += kBlock) {
+            const int q = i / (P * RB), off = i - q * (P * RB);
+            const int gs = staged[base + q];
+            if (gs >= 0) cone[i] = Fc[(size_t)gs * P * RB + off];
+        }
+        __syncthreads();
+        if (active) {
+            for (int o = 0; o < 8; ++o) {
+                const int f = sof[s_me * 8 + o];
+                if (f < 0) continue;
+                const size_t e = (size_t)f * P + nu;
+                const int ent = soff[s_me * 8 + o] + Lc.fr_grp[e];
+                const int pos = ent - base;
+                if (pos < 0 || pos >= cnt) continue;
+                if (staged[ent] < 0) {
+                    atomicAdd(kc.miss, 1ull);
+                    continue;
+                }
+                T Ls[PS], Lt[PA], Lpp[PA];
+                lagrange<T, PS>((double)frt[3 * e], kc.cs, Ls);
+                lagrange<T, PA>((double)frt[3 * e + 1], kc.ca, Lt);
+                lagrange<T, PA>((double)frt[3 * e + 2], kc.ca, Lpp);
+                cpx<T> val[RB];
+                interp<T, PS, PA, RB>(&cone[pos * P * RB], Ls, Lt, Lpp, val);
+                const T gr = frr[2 * e], gim = conj_sign * frr[2 * e + 1];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    acc[r].x += val[r].x * gr - val[r].y * gim;
+                    acc[r].y += val[r].x * gim + val[r].y * gr;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) Fp[((size_t)sp * P + nu) * RB + r] = acc[r];
+    }
+}
+
+// Capacity (cones) of the LDS stage for ~24 KB of cone values, at most
+// S * kMaxFrameGroups.
+template <typename T, int P, int RB, int S>
+constexpr int lds_gcap()
+{
+    return (24576 / (P * RB * (int)sizeof(cpx<T>))) < S * kMaxFrameGroups
+               ? (24576 / (P * RB * (int)sizeof(cpx<T>)))
+               : S * kMaxFrameGroups;
+}
+
 // ----------------------------------------------------------- gradients
 
 // d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
@@ -562,18 +763,46 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
     using C = cpx<T>;
     if (D < 3) return hipSuccess;
     if (!reuse && hp.L[D].nslots > 0)
-        k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
-            kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
+        {
+            StageTimer tm_(p, IFGF_STAGE_LEAF_NODES, st);
+            k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
+                kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
+        }
     for (int d = D; d >= 3; --d) {
         if (grad)
-            k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
-                                                                         (const C*)p.gout_m, p.grad_m);
+            {
+                StageTimer tm_(p, IFGF_STAGE_COUSIN_GRAD, st);
+                k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                             (const C*)p.gout_m, p.grad_m);
+            }
         else
-            k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
-                                                                         (C*)p.out_m);
+            {
+                StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st);
+                k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                             (C*)p.out_m);
+            }
         if (d > 3 && !reuse && hp.L[d - 1].nslots > 0)
-            k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)hp.L[d - 1].nslots * P), kBlock, 0, st>>>(
-                kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+            {
+                StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st);
+                constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
+                constexpr int GCAP = lds_gcap<T, P, RB, S>();
+                bool staged = false;
+                if constexpr (GCAP >= S) {
+                    if (p.L[d].use_frames && p.L[d].frame_groups_ok) {
+                        k_child_to_parent_lds<T, PS, PA, RB, S, GCAP>
+                            <<<(unsigned)((hp.L[d - 1].nslots + S - 1) / S), kBlock, 0, st>>>(
+                                kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+                        staged = true;
+                    }
+                }
+                if (staged) {
+                } else if (p.L[d].use_frames)
+                    k_child_to_parent_frames<T, PS, PA, RB><<<grid_for((size_t)hp.L[d - 1].nslots * P), kBlock, 0, st>>>(
+                        kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+                else
+                    k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)hp.L[d - 1].nslots * P), kBlock, 0, st>>>(
+                        kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+            }
     }
     return hipGetLastError();
 }
@@ -584,11 +813,20 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     const int n = (int)p.hp.n;
     using C = cpx<T>;
     KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), kappa, n, p.miss};
-    k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, r0);
-    k_nearfield<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m, (C*)p.out_m);
+    {
+        StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
+        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, r0);
+    }
+    {
+        StageTimer tm_(p, IFGF_STAGE_NEARFIELD, st);
+        k_nearfield<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m, (C*)p.out_m);
+    }
     hipError_t e = upward_and_eval<T, PS, PA, RB>(p, kc, st, false, false);
     if (e != hipSuccess) return e;
-    k_permute_out<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)p.out_m, (C*)out, p.iperm, n, nrhs, r0);
+    {
+        StageTimer tm_(p, IFGF_STAGE_PERMUTE_OUT, st);
+        k_permute_out<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)p.out_m, (C*)out, p.iperm, n, nrhs, r0);
+    }
     return hipGetLastError();
 }
 
@@ -600,13 +838,25 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
     using C = cpx<T>;
     KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), p.hp.kappa, n, p.miss};
     if (!reuse)
-        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, 0);
-    k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n, nrhs, 0);
-    k_near_grad<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m,
-                                                        (const C*)p.gout_m, p.grad_m);
+        {
+            StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
+            k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, 0);
+        }
+    {
+        StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
+        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n, nrhs, 0);
+    }
+    {
+        StageTimer tm_(p, IFGF_STAGE_NEAR_GRAD, st);
+        k_near_grad<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m,
+                                                            (const C*)p.gout_m, p.grad_m);
+    }
     hipError_t e = upward_and_eval<T, PS, PA, RB>(p, kc, st, true, reuse);
     if (e != hipSuccess) return e;
-    k_permute_grad<<<grid_for(n), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, n);
+    {
+        StageTimer tm_(p, IFGF_STAGE_PERMUTE_GRAD, st);
+        k_permute_grad<<<grid_for(n), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, n);
+    }
     return hipGetLastError();
 }
 

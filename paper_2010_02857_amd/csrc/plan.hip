@@ -86,6 +86,105 @@ int64_t find_prefix(const std::vector<uint64_t>& v, uint64_t key)
     return (int64_t)(it - v.begin());
 }
 
+// Child-to-parent frames of level d (children at d, parents at d - 1):
+// every (parent slot, child) pair is described by (parent cone, child
+// octant); the distinct pairs are tabulated once when they are shared at
+// least four times on average, otherwise the kernels compute the geometry.
+void build_frames(HostPlan& hp, int d)
+{
+    HostLevel& L = hp.L[d];
+    const HostLevel& Lp = hp.L[d - 1];
+    const int P = hp.P, ps = hp.ps, pang = hp.pang;
+    L.child_of.assign((size_t)Lp.nbox * 8, -1);
+    for (int64_t k = 0; k < L.nbox; ++k) L.child_of[(size_t)L.parent[k] * 8 + L.box_oct[k]] = (int32_t)k;
+    std::vector<uint64_t> keys;
+    keys.reserve((size_t)Lp.nslots * 4);
+    for (int64_t sl = 0; sl < Lp.nslots; ++sl) {
+        int32_t j = Lp.slot_box[sl];
+        for (int o = 0; o < 8; ++o)
+            if (L.child_of[(size_t)j * 8 + o] >= 0) keys.push_back((uint64_t)Lp.slot_cone[sl] * 8 + o);
+    }
+    L.npairs = (int64_t)keys.size();
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    L.nframes = (int64_t)keys.size();
+    L.use_frames = L.nframes * 4 <= L.npairs;
+    if (!L.use_frames) {
+        L.nframes = 0;
+        return;
+    }
+    L.pframe.assign((size_t)Lp.nslots * 8, -1);
+    parallel_for(Lp.nslots, [&](int64_t sl) {
+        int32_t j = Lp.slot_box[sl];
+        for (int o = 0; o < 8; ++o)
+            if (L.child_of[(size_t)j * 8 + o] >= 0) {
+                uint64_t key = (uint64_t)Lp.slot_cone[sl] * 8 + o;
+                L.pframe[(size_t)sl * 8 + o] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), key) - keys.begin());
+            }
+    }, 1024);
+    L.fr_key.resize((size_t)L.nframes * P);
+    L.fr_t.resize((size_t)L.nframes * P * 3);
+    L.fr_ratio.resize((size_t)L.nframes * P * 2);
+    const double kappa = hp.kappa;
+    parallel_for(L.nframes, [&](int64_t f) {
+        int64_t pc = (int64_t)(keys[f] >> 3);
+        int oct = (int)(keys[f] & 7);
+        double o[3];
+        for (int a = 0; a < 3; ++a) o[a] = ((oct >> a) & 1) ? 0.5 * L.H : -0.5 * L.H;
+        int pcell = (int)(pc / Lp.ns), pis = (int)(pc % Lp.ns);
+        for (int a = 0; a < ps; ++a) {
+            double rr = Lp.node_r[(size_t)pis * ps + a];
+            for (int bb = 0; bb < pang; ++bb)
+                for (int cc = 0; cc < pang; ++cc) {
+                    int nu = (a * pang + bb) * pang + cc;
+                    const double* dir = &Lp.node_dir[(((size_t)pcell * pang + bb) * pang + cc) * 3];
+                    double v[3];
+                    node_minus(rr, dir, o, v);
+                    ConeLoc cl;
+                    cone_locate(v[0], v[1], v[2], L.h, L.ds, L.dang, L.ns, L.nc, cl);
+                    size_t e = (size_t)f * P + nu;
+                    L.fr_key[e] = (uint32_t)((int64_t)cl.cell * L.ns + cl.is);
+                    L.fr_t[3 * e] = cl.ts;
+                    L.fr_t[3 * e + 1] = cl.tt;
+                    L.fr_t[3 * e + 2] = cl.tp;
+                    // G(x, x_k) / G(x, x_j) = |y| / |y - o| e^{i k (|y - o| - |y|)},
+                    // |y - o| - |y| = (|o|^2 - 2 y.o) / (|y - o| + |y|), y = x - x_j
+                    double y[3] = {rr * dir[0], rr * dir[1], rr * dir[2]};
+                    double ry = std::sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                    double num = (o[0] * o[0] + o[1] * o[1] + o[2] * o[2]) - 2.0 * (y[0] * o[0] + y[1] * o[1] + y[2] * o[2]);
+                    double diff = num / (cl.r + ry);
+                    double mag = ry / cl.r;
+                    L.fr_ratio[2 * e] = mag * std::cos(kappa * diff);
+                    L.fr_ratio[2 * e + 1] = mag * std::sin(kappa * diff);
+                }
+        }
+    }, 64);
+    // groups: distinct child cones per frame, in order of first appearance
+    L.fr_ngrp.assign(L.nframes, 0);
+    L.fr_gkey.assign((size_t)L.nframes * kMaxFrameGroups, 0);
+    L.fr_grp.assign((size_t)L.nframes * P, 0);
+    std::atomic<int> too_many{0};
+    parallel_for(L.nframes, [&](int64_t f) {
+        int ng = 0;
+        uint32_t* gk = &L.fr_gkey[(size_t)f * kMaxFrameGroups];
+        for (int nu = 0; nu < P; ++nu) {
+            uint32_t key = L.fr_key[(size_t)f * P + nu];
+            int g = 0;
+            while (g < ng && gk[g] != key) ++g;
+            if (g == ng) {
+                if (ng == kMaxFrameGroups) {
+                    too_many = 1;
+                    return;
+                }
+                gk[ng++] = key;
+            }
+            L.fr_grp[(size_t)f * P + nu] = (uint8_t)g;
+        }
+        L.fr_ngrp[f] = (uint8_t)ng;
+    }, 256);
+    L.frame_groups_ok = too_many.load() == 0;
+}
+
 }  // namespace
 
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
@@ -376,6 +475,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                     }
         };
         const HostLevel* Lp = &hp.L[d - 1];
+        if (d >= 4) build_frames(hp, d);
         parallel_for(L.nbox, [&](int64_t b) {
             const double* ctr = &L.box_ctr[3 * b];
             for (int32_t ci = L.cou_start[b]; ci < L.cou_start[b + 1]; ++ci) {
@@ -387,7 +487,20 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                     mark(b, cl);
                 }
             }
-            if (d >= 4) {
+            if (d >= 4 && L.use_frames) {
+                // (ii) through the frames: the same decisions the kernels use
+                int32_t p = L.parent[b];
+                int o = L.box_oct[b];
+                for (int32_t sl = Lp->slot_start[p]; sl < Lp->slot_start[p + 1]; ++sl) {
+                    int32_t f = L.pframe[(size_t)sl * 8 + o];
+                    const uint32_t* key = &L.fr_key[(size_t)f * hp.P];
+                    uint64_t* Pm = &prim[(size_t)b * wpb];
+                    for (int nu = 0; nu < hp.P; ++nu) {
+                        int64_t bit = key[nu];
+                        Pm[bit >> 6] |= 1ull << (bit & 63);
+                    }
+                }
+            } else if (d >= 4) {
                 int32_t p = L.parent[b];
                 double o[3];
                 for (int a = 0; a < 3; ++a) o[a] = ((L.box_oct[b] >> a) & 1) ? 0.5 * L.H : -0.5 * L.H;
@@ -498,6 +611,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         st.max_cousin_boxes[d] = mx;
         st.n_cousin_evals[d] = ce;
         st.n_parent_evals[d] = pe;
+        st.n_frames[d] = L.nframes;
     }
     {
         const HostLevel& L = hp.L[D];

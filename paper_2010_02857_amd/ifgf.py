@@ -67,6 +67,7 @@ class Stats(ctypes.Structure):
         ("n_leaf_pairs", ctypes.c_int64),
         ("n_near_pairs", ctypes.c_int64),
         ("n_dilated", ctypes.c_int64),
+        ("n_frames", ctypes.c_int64 * _L),
         ("device_bytes", ctypes.c_int64),
         ("t_plan_s", ctypes.c_double),
     ]
@@ -91,12 +92,15 @@ def lib() -> ctypes.CDLL:
         L.ifgf_plan_stats.argtypes = [P, ctypes.POINTER(Stats)]
         L.ifgf_plan_check.argtypes = [P, ctypes.POINTER(I64)]
         L.ifgf_plan_destroy.argtypes = [P]
+        L.ifgf_plan_profile.argtypes = [P, I32]
+        L.ifgf_plan_stage_times.argtypes = [P, P, P]
         L.ifgf_status_string.argtypes = [ctypes.c_int]
         L.ifgf_status_string.restype = ctypes.c_char_p
         L.ifgf_last_error.argtypes = []
         L.ifgf_last_error.restype = ctypes.c_char_p
         for f in (L.ifgf_plan_create, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
-                  L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy):
+                  L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy, L.ifgf_plan_profile,
+                  L.ifgf_plan_stage_times):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -174,7 +178,7 @@ class Plan:
                "ps": st.ps, "pang": st.pang, "n_leaf_pairs": st.n_leaf_pairs, "n_near_pairs": st.n_near_pairs,
                "n_dilated": st.n_dilated, "device_bytes": st.device_bytes, "t_plan_s": st.t_plan_s}
         for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
-                    "n_parent_evals"):
+                    "n_parent_evals", "n_frames"):
             arr = getattr(st, key)
             out[key] = [int(arr[d]) for d in range(D + 1)]
         return out
@@ -183,6 +187,21 @@ class Plan:
         m = ctypes.c_int64()
         _check(lib().ifgf_plan_check(self._h, ctypes.byref(m)))
         return int(m.value)
+
+    STAGES = ("permute_in", "nearfield", "leaf_nodes", "cousin_eval", "child_to_parent", "permute_out",
+              "near_grad", "cousin_grad", "permute_grad")
+
+    def profile(self, enable: bool = True):
+        """Start (clearing totals) or stop per-stage HIP-event timing."""
+        _check(lib().ifgf_plan_profile(self._h, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """{stage: (milliseconds, launches)} recorded since profile(True)."""
+        ms = np.zeros(len(self.STAGES), np.float64)
+        cnt = np.zeros(len(self.STAGES), np.int64)
+        _check(lib().ifgf_plan_stage_times(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                           cnt.ctypes.data_as(ctypes.c_void_p)))
+        return {s: (float(ms[i]), int(cnt[i])) for i, s in enumerate(self.STAGES)}
 
     # -- operator
     @property
