@@ -18,7 +18,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxNodes = 8;       // Chebyshev nodes per direction, upper bound
 constexpr int kMaxRhsPass = 16;    // right-hand sides handled by one kernel pass
 constexpr double kDilateTol = 1e-9;
-constexpr int kMaxFrameGroups = 16;  // distinct child cones one frame may touch
+constexpr int kMaxFrameGroups = 32;  // distinct child cones one frame may touch
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).

@@ -99,10 +99,11 @@ __device__ inline int lookup(const LevelDev& L, int box, int cell, int is)
     return L.cell_base[c] + cnt;
 }
 
-// sum_{a,b,c} F[a][b][c][r] Ls[a] Lt[b] Lp[c] for the RB right-hand sides.
-// With one right-hand side the 75-term sum is unrolled completely; with
-// several, only the innermost (c, r) loops are, so that the compiler cannot
-// hoist all P * RB loads at once and spill.
+// sum_{a,b,c} F[a][b][c][r] Ls[a] Lt[b] Lp[c] for the RB right-hand sides,
+// contracted one direction at a time (phi, then theta, then s), which needs
+// no products of the three weights.  With one right-hand side everything is
+// unrolled; with several, the (a, b) loop is kept rolled so that the
+// compiler cannot hoist all P * RB loads at once and spill.
 template <typename T, int PS, int PA, int RB>
 __device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T* Lt, const T* Lp, cpx<T>* v)
 {
@@ -110,19 +111,27 @@ __device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T
     for (int r = 0; r < RB; ++r) v[r].x = v[r].y = (T)0;
     if constexpr (RB == 1) {
 #pragma unroll
-        for (int a = 0; a < PS; ++a)
+        for (int a = 0; a < PS; ++a) {
+            T wx = (T)0, wy = (T)0;
 #pragma unroll
             for (int b = 0; b < PA; ++b) {
-                T wab = Ls[a] * Lt[b];
+                T ux = (T)0, uy = (T)0;
 #pragma unroll
                 for (int c = 0; c < PA; ++c) {
-                    T w = wab * Lp[c];
                     cpx<T> q = F[(a * PA + b) * PA + c];
-                    v[0].x += w * q.x;
-                    v[0].y += w * q.y;
+                    ux += Lp[c] * q.x;
+                    uy += Lp[c] * q.y;
                 }
+                wx += Lt[b] * ux;
+                wy += Lt[b] * uy;
             }
+            v[0].x += Ls[a] * wx;
+            v[0].y += Ls[a] * wy;
+        }
     } else {
+        cpx<T> w[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) w[r].x = w[r].y = (T)0;
 #pragma unroll 1
         for (int ab = 0; ab < PS * PA; ++ab) {
             const int a = ab / PA, b = ab - a * PA;
@@ -131,16 +140,25 @@ __device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T
             for (int i = 1; i < PS; ++i) la = a == i ? Ls[i] : la;
 #pragma unroll
             for (int i = 1; i < PA; ++i) lb = b == i ? Lt[i] : lb;
-            const T wab = la * lb;
             const cpx<T>* f = F + ab * PA * RB;
 #pragma unroll
-            for (int c = 0; c < PA; ++c) {
-                const T w = wab * Lp[c];
+            for (int r = 0; r < RB; ++r) {
+                T ux = (T)0, uy = (T)0;
+#pragma unroll
+                for (int c = 0; c < PA; ++c) {
+                    cpx<T> q = f[c * RB + r];
+                    ux += Lp[c] * q.x;
+                    uy += Lp[c] * q.y;
+                }
+                w[r].x += lb * ux;
+                w[r].y += lb * uy;
+            }
+            if (b == PA - 1) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    cpx<T> q = f[c * RB + r];
-                    v[r].x += w * q.x;
-                    v[r].y += w * q.y;
+                    v[r].x += la * w[r].x;
+                    v[r].y += la * w[r].y;
+                    w[r].x = w[r].y = (T)0;
                 }
             }
         }
