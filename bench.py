@@ -204,7 +204,12 @@ def main() -> int:
         g = torch.from_numpy(inputs.densities(402, 1, n)).to(torch.complex64).cuda()
         ms_grad = time_fn(lambda: plan.grad_targets(x, g), 3)
         x16 = torch.from_numpy(inputs.densities(2, 16, n)).to(torch.complex64).cuda()
+        plan.apply(x16)
+        plan.profile(True)
         ms_b16 = time_fn(lambda: plan.apply(x16), 3)
+        st16 = plan.stage_times()
+        plan.profile(False)
+        result["stage_ms_per_step_16rhs"] = {k: round(v[0] / 4, 4) for k, v in st16.items() if v[1]}
         del plan
         torch.cuda.empty_cache()
         plan64 = ifgf.Plan(p, w.kappa, precision="fp64", max_nrhs=1, store_levels=0)

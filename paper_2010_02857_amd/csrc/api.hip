@@ -142,6 +142,8 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
                 if ((e = upload(p, H.fr_ngrp, &L.fr_ngrp)) != hipSuccess) return e;
                 if ((e = upload(p, H.fr_gkey, &L.fr_gkey)) != hipSuccess) return e;
                 if ((e = upload(p, H.fr_grp, &L.fr_grp)) != hipSuccess) return e;
+                if ((e = upload(p, H.fr_order, &L.fr_order)) != hipSuccess) return e;
+                if ((e = upload(p, H.fr_goff, &L.fr_goff)) != hipSuccess) return e;
             }
             // the host copies are no longer needed
             std::vector<double>().swap(H.fr_t);

@@ -149,6 +149,8 @@ struct HostLevel {
     std::vector<uint8_t> fr_ngrp;             // [nframes]
     std::vector<uint32_t> fr_gkey;            // [nframes][kMaxFrameGroups]
     std::vector<uint8_t> fr_grp;              // [nframes][P]
+    std::vector<uint8_t> fr_order;            // [nframes][P] points sorted by group
+    std::vector<uint8_t> fr_goff;             // [nframes][kMaxFrameGroups + 1] group offsets
 };
 
 struct HostPlan {
@@ -200,6 +202,8 @@ struct LevelDev {
     const uint8_t* fr_ngrp;
     const uint32_t* fr_gkey;
     const uint8_t* fr_grp;
+    const uint8_t* fr_order;
+    const uint8_t* fr_goff;
 };
 
 struct KernelConsts {

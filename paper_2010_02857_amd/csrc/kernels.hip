@@ -12,6 +12,8 @@
 // interpolation weights and accumulation are FP32.
 #include "ifgf_internal.hpp"
 
+#include <type_traits>
+
 namespace ifgf {
 namespace {
 
@@ -571,6 +573,142 @@ constexpr int lds_gcap()
                : S * kMaxFrameGroups;
 }
 
+// Batched child-to-parent interpolation on the matrix cores (16 complex
+// right-hand sides, FP32).  One wavefront handles one parent slot.  For every
+// child octant and every child cone ("group") the frame's interpolation
+// points falling into that cone form the rows of 16 x 16 x 4 FP32 MFMA tiles:
+//   D[row][col] = sum_k A[row][k] B[k][col],
+// A = the tensor Chebyshev weights of the row's point, B = the child cone's
+// values, 32 real columns (re, im of 16 right-hand sides) in two tiles.  The
+// K index is ordered so that lane quarter q (lanes 16q..16q+15) always takes
+// the phi-node c = q: its weights are Ls[a] Lt[b] Lp[q] with (a, b) fixed
+// per step; the remaining phi-nodes c >= 4 follow in a short tail.  The
+// re-centring ratio is applied per row and the result accumulated into the
+// wavefront's own LDS copy of the slot's values, so no two wavefronts write
+// the same data and the result does not depend on scheduling.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+__device__ inline float pick(const float* v, int i)
+{
+    float x = v[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) x = i == j ? v[j] : x;
+    return x;
+}
+
+template <int PS, int PA>
+__global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                                 const cpx<float>* __restrict__ Fc,
+                                                                 cpx<float>* __restrict__ Fp)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int NC = 32;                     // real columns: 16 complex right-hand sides
+    constexpr int G = kMaxFrameGroups;
+    constexpr int W = kBlock / 64;             // wavefronts (parent slots) per block
+    constexpr int NAB = PS * PA;               // (a, b) pairs
+    constexpr int NREM = NAB * (PA - 4);       // entries with phi-node c >= 4
+    constexpr int KTAIL = (NREM + 3) / 4;
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    __shared__ float accs[W][P * NC];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int sp = blockIdx.x * W + wv;
+    if (sp >= Lp.nslots) return;               // whole wavefront leaves; no block barriers below
+    float* acc = accs[wv];
+    for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
+    __threadfence_block();
+
+    const float* F = (const float*)Fc;
+    const float* frt = (const float*)Lc.fr_t;
+    const float* frr = (const float*)Lc.fr_ratio;
+    const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
+    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int j = Lp.slot_box[sp];
+    for (int o = 0; o < 8; ++o) {
+        const int f = Lc.pframe[(size_t)sp * 8 + o];
+        if (f < 0) continue;
+        const int k = Lc.child_of[(size_t)j * 8 + o];
+        const int ng = Lc.fr_ngrp[f];
+        const uint8_t* ord = Lc.fr_order + (size_t)f * P;
+        const uint8_t* goff = Lc.fr_goff + (size_t)f * (G + 1);
+        for (int g = 0; g < ng; ++g) {
+            const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
+            const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
+            const int cs = lookup(Lc, k, cell, is);
+            const int g0 = goff[g], g1 = goff[g + 1];
+            if (cs < 0) {
+                if (lane == 0) atomicAdd(kc.miss, (unsigned long long)(g1 - g0));
+                continue;
+            }
+            const float* Fcs = F + (size_t)cs * P * NC;
+            for (int t0 = g0; t0 < g1; t0 += 16) {
+                // weights of this lane's row
+                float Ls[PS], Lt[PA], Lpv[PA];
+                const int rr = t0 + row;
+                if (rr < g1) {
+                    const size_t e = (size_t)f * P + ord[rr];
+                    lagrange<float, PS>((double)frt[3 * e], kc.cs, Ls);
+                    lagrange<float, PA>((double)frt[3 * e + 1], kc.ca, Lt);
+                    lagrange<float, PA>((double)frt[3 * e + 2], kc.ca, Lpv);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
+#pragma unroll
+                    for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
+                }
+                const float lq = pick<4>(Lpv, q);
+                mf4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ab = 0; ab < NAB; ++ab) {
+                    const int a = ab / PA, b = ab - a * PA;
+                    const float w = Ls[a] * Lt[b] * lq;
+                    const float* src = Fcs + (size_t)(ab * PA + q) * NC + col;
+                    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, src[0], c0, 0, 0, 0);
+                    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, src[16], c1, 0, 0, 0);
+                }
+#pragma unroll
+                for (int jt = 0; jt < KTAIL; ++jt) {
+                    const int m = 4 * jt + q;
+                    float w = 0.f, b0 = 0.f, b1 = 0.f;
+                    if (m < NREM) {
+                        const int abm = m / (PA - 4), c = 4 + (m - abm * (PA - 4));
+                        const int a = abm / PA, b = abm - a * PA;
+                        w = pick<PS>(Ls, a) * pick<PA>(Lt, b) * pick<PA>(Lpv, c);
+                        const float* src = Fcs + (size_t)(abm * PA + c) * NC + col;
+                        b0 = src[0];
+                        b1 = src[16];
+                    }
+                    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0, c0, 0, 0, 0);
+                    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1, c1, 0, 0, 0);
+                }
+                // rows 4q + i of the tile, column col: apply the ratio, accumulate
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int ri = t0 + 4 * q + i;
+                    const float v0 = c0[i], v1 = c1[i];
+                    const float p0 = __shfl_xor(v0, 1, 64), p1 = __shfl_xor(v1, 1, 64);
+                    if (ri < g1) {
+                        const int nu = ord[ri];
+                        const size_t e = (size_t)f * P + nu;
+                        const float gr = frr[2 * e], gi = conj_sign * frr[2 * e + 1];
+                        const bool re = (col & 1) == 0;
+                        // re column: re*gr - im*gi; im column: re*gi + im*gr
+                        const float o0 = re ? v0 * gr - p0 * gi : p0 * gi + v0 * gr;
+                        const float o1 = re ? v1 * gr - p1 * gi : p1 * gi + v1 * gr;
+                        acc[nu * NC + col] += o0;
+                        acc[nu * NC + 16 + col] += o1;
+                    }
+                }
+                __threadfence_block();
+            }
+        }
+    }
+    float* out = (float*)(Fp + (size_t)sp * P * 16);
+    for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
+}
+
 // ----------------------------------------------------------- gradients
 
 // d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
@@ -805,7 +943,16 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                 constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
                 constexpr int GCAP = lds_gcap<T, P, RB, S>();
                 bool staged = false;
-                if constexpr (GCAP >= S) {
+                if constexpr (std::is_same<T, float>::value && RB == 16 && PA >= 4) {
+                    if (p.L[d].use_frames && p.L[d].frame_groups_ok) {
+                        k_child_to_parent_mfma<PS, PA>
+                            <<<(unsigned)((hp.L[d - 1].nslots + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
+                                kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+                        staged = true;
+                    }
+                }
+                if (staged) {
+                } else if constexpr (GCAP >= S) {
                     if (p.L[d].use_frames && p.L[d].frame_groups_ok) {
                         k_child_to_parent_lds<T, PS, PA, RB, S, GCAP>
                             <<<(unsigned)((hp.L[d - 1].nslots + S - 1) / S), kBlock, 0, st>>>(

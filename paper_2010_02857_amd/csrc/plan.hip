@@ -182,7 +182,23 @@ void build_frames(HostPlan& hp, int d)
         }
         L.fr_ngrp[f] = (uint8_t)ng;
     }, 256);
-    L.frame_groups_ok = too_many.load() == 0;
+    L.frame_groups_ok = too_many.load() == 0 && P <= 255;
+    if (!L.frame_groups_ok) return;
+    // the points of each frame ordered by group (for tiles of one child cone)
+    L.fr_order.assign((size_t)L.nframes * P, 0);
+    L.fr_goff.assign((size_t)L.nframes * (kMaxFrameGroups + 1), 0);
+    parallel_for(L.nframes, [&](int64_t f) {
+        const uint8_t* grp = &L.fr_grp[(size_t)f * P];
+        uint8_t* off = &L.fr_goff[(size_t)f * (kMaxFrameGroups + 1)];
+        int ng = L.fr_ngrp[f];
+        int cnt[kMaxFrameGroups + 1] = {0};
+        for (int nu = 0; nu < P; ++nu) cnt[grp[nu] + 1]++;
+        for (int g = 0; g < ng; ++g) cnt[g + 1] += cnt[g];
+        for (int g = 0; g <= ng; ++g) off[g] = (uint8_t)cnt[g];
+        for (int g = ng + 1; g <= kMaxFrameGroups; ++g) off[g] = (uint8_t)P;
+        uint8_t* ord = &L.fr_order[(size_t)f * P];
+        for (int nu = 0; nu < P; ++nu) ord[cnt[grp[nu]]++] = (uint8_t)nu;
+    }, 256);
 }
 
 }  // namespace
