@@ -606,11 +606,14 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
     constexpr int NC = 32;                     // real columns: 16 complex right-hand sides
     constexpr int G = kMaxFrameGroups;
     constexpr int W = kBlock / 64;             // wavefronts (parent slots) per block
-    constexpr int NAB = PS * PA;               // (a, b) pairs
+    constexpr int NAB = PS * PA;               // (a, b) pairs: K steps with phi-node c = q
     constexpr int NREM = NAB * (PA - 4);       // entries with phi-node c >= 4
     constexpr int KTAIL = (NREM + 3) / 4;
+    constexpr int NK = NAB + KTAIL;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
     __shared__ float accs[W][P * NC];
+    __shared__ int ents[W][8 * G];             // (octant << 8) | group
+    __shared__ int entcs[W][8 * G];            // child slot of the entry, -1 missing
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -618,7 +621,6 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
     if (sp >= Lp.nslots) return;               // whole wavefront leaves; no block barriers below
     float* acc = accs[wv];
     for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
-    __threadfence_block();
 
     const float* F = (const float*)Fc;
     const float* frt = (const float*)Lc.fr_t;
@@ -626,83 +628,118 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
     const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
     const int j = Lp.slot_box[sp];
-    for (int o = 0; o < 8; ++o) {
+
+    // entries (octant, group) of this slot: lanes 0..7 hold the octants
+    int fo = -1, ngo = 0;
+    if (lane < 8) {
+        fo = Lc.pframe[(size_t)sp * 8 + lane];
+        ngo = fo >= 0 ? Lc.fr_ngrp[fo] : 0;
+    }
+    int incl = ngo;
+#pragma unroll
+    for (int dd = 1; dd < 8; dd <<= 1) {
+        int y = __shfl_up(incl, dd, 64);
+        if (lane >= dd) incl += y;
+    }
+    const int nent = __shfl(incl, 7, 64);
+    if (lane < 8)
+        for (int g = 0; g < ngo; ++g) ents[wv][incl - ngo + g] = (lane << 8) | g;
+    __threadfence_block();
+    // child slots of all entries, looked up in parallel
+    for (int e = lane; e < nent; e += 64) {
+        const int o = ents[wv][e] >> 8, g = ents[wv][e] & 255;
         const int f = Lc.pframe[(size_t)sp * 8 + o];
-        if (f < 0) continue;
         const int k = Lc.child_of[(size_t)j * 8 + o];
-        const int ng = Lc.fr_ngrp[f];
+        const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
+        const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
+        entcs[wv][e] = lookup(Lc, k, cell, is);
+    }
+    __threadfence_block();
+
+    for (int e = 0; e < nent; ++e) {
+        const int o = ents[wv][e] >> 8, g = ents[wv][e] & 255;
+        const int f = Lc.pframe[(size_t)sp * 8 + o];
+        const int cs = entcs[wv][e];
         const uint8_t* ord = Lc.fr_order + (size_t)f * P;
-        const uint8_t* goff = Lc.fr_goff + (size_t)f * (G + 1);
-        for (int g = 0; g < ng; ++g) {
-            const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
-            const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
-            const int cs = lookup(Lc, k, cell, is);
-            const int g0 = goff[g], g1 = goff[g + 1];
-            if (cs < 0) {
-                if (lane == 0) atomicAdd(kc.miss, (unsigned long long)(g1 - g0));
-                continue;
+        const int g0 = Lc.fr_goff[(size_t)f * (G + 1) + g], g1 = Lc.fr_goff[(size_t)f * (G + 1) + g + 1];
+        if (cs < 0) {
+            if (lane == 0) atomicAdd(kc.miss, (unsigned long long)(g1 - g0));
+            continue;
+        }
+        // the child cone's values as B operands, kept for all tiles of the group
+        const float* Fcs = F + (size_t)cs * P * NC;
+        float b0[NK], b1[NK];
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) {
+            const float* src = Fcs + (size_t)(ab * PA + q) * NC + col;
+            b0[ab] = src[0];
+            b1[ab] = src[16];
+        }
+#pragma unroll
+        for (int jt = 0; jt < KTAIL; ++jt) {
+            const int m = 4 * jt + q;
+            b0[NAB + jt] = b1[NAB + jt] = 0.f;
+            if (m < NREM) {
+                const int abm = m / (PA - 4), c = 4 + (m - abm * (PA - 4));
+                const float* src = Fcs + (size_t)(abm * PA + c) * NC + col;
+                b0[NAB + jt] = src[0];
+                b1[NAB + jt] = src[16];
             }
-            const float* Fcs = F + (size_t)cs * P * NC;
-            for (int t0 = g0; t0 < g1; t0 += 16) {
-                // weights of this lane's row
-                float Ls[PS], Lt[PA], Lpv[PA];
-                const int rr = t0 + row;
-                if (rr < g1) {
-                    const size_t e = (size_t)f * P + ord[rr];
-                    lagrange<float, PS>((double)frt[3 * e], kc.cs, Ls);
-                    lagrange<float, PA>((double)frt[3 * e + 1], kc.ca, Lt);
-                    lagrange<float, PA>((double)frt[3 * e + 2], kc.ca, Lpv);
-                } else {
+        }
+        for (int t0 = g0; t0 < g1; t0 += 16) {
+            float Ls[PS], Lt[PA], Lpv[PA];
+            const int rr = t0 + row;
+            if (rr < g1) {
+                const size_t ee = (size_t)f * P + ord[rr];
+                lagrange<float, PS>((double)frt[3 * ee], kc.cs, Ls);
+                lagrange<float, PA>((double)frt[3 * ee + 1], kc.ca, Lt);
+                lagrange<float, PA>((double)frt[3 * ee + 2], kc.ca, Lpv);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
+                for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
 #pragma unroll
-                    for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
-                }
-                const float lq = pick<4>(Lpv, q);
-                mf4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int ab = 0; ab < NAB; ++ab) {
-                    const int a = ab / PA, b = ab - a * PA;
-                    const float w = Ls[a] * Lt[b] * lq;
-                    const float* src = Fcs + (size_t)(ab * PA + q) * NC + col;
-                    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, src[0], c0, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, src[16], c1, 0, 0, 0);
-                }
-#pragma unroll
-                for (int jt = 0; jt < KTAIL; ++jt) {
-                    const int m = 4 * jt + q;
-                    float w = 0.f, b0 = 0.f, b1 = 0.f;
-                    if (m < NREM) {
-                        const int abm = m / (PA - 4), c = 4 + (m - abm * (PA - 4));
-                        const int a = abm / PA, b = abm - a * PA;
-                        w = pick<PS>(Ls, a) * pick<PA>(Lt, b) * pick<PA>(Lpv, c);
-                        const float* src = Fcs + (size_t)(abm * PA + c) * NC + col;
-                        b0 = src[0];
-                        b1 = src[16];
-                    }
-                    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0, c0, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1, c1, 0, 0, 0);
-                }
-                // rows 4q + i of the tile, column col: apply the ratio, accumulate
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int ri = t0 + 4 * q + i;
-                    const float v0 = c0[i], v1 = c1[i];
-                    const float p0 = __shfl_xor(v0, 1, 64), p1 = __shfl_xor(v1, 1, 64);
-                    if (ri < g1) {
-                        const int nu = ord[ri];
-                        const size_t e = (size_t)f * P + nu;
-                        const float gr = frr[2 * e], gi = conj_sign * frr[2 * e + 1];
-                        const bool re = (col & 1) == 0;
-                        // re column: re*gr - im*gi; im column: re*gi + im*gr
-                        const float o0 = re ? v0 * gr - p0 * gi : p0 * gi + v0 * gr;
-                        const float o1 = re ? v1 * gr - p1 * gi : p1 * gi + v1 * gr;
-                        acc[nu * NC + col] += o0;
-                        acc[nu * NC + 16 + col] += o1;
-                    }
-                }
-                __threadfence_block();
+                for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
             }
+            const float lq = pick<4>(Lpv, q);
+            mf4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ab = 0; ab < NAB; ++ab) {
+                const int a = ab / PA, b = ab - a * PA;
+                const float w = Ls[a] * Lt[b] * lq;
+                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0[ab], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1[ab], c1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int jt = 0; jt < KTAIL; ++jt) {
+                const int m = 4 * jt + q;
+                float w = 0.f;
+                if (m < NREM) {
+                    const int abm = m / (PA - 4), c = 4 + (m - abm * (PA - 4));
+                    const int a = abm / PA, b = abm - a * PA;
+                    w = pick<PS>(Ls, a) * pick<PA>(Lt, b) * pick<PA>(Lpv, c);
+                }
+                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0[NAB + jt], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1[NAB + jt], c1, 0, 0, 0);
+            }
+            // rows 4q + i of the tile, column col: apply the ratio, accumulate
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ri = t0 + 4 * q + i;
+                const float v0 = c0[i], v1 = c1[i];
+                const float p0 = __shfl_xor(v0, 1, 64), p1 = __shfl_xor(v1, 1, 64);
+                if (ri < g1) {
+                    const int nu = ord[ri];
+                    const size_t ee = (size_t)f * P + nu;
+                    const float gr = frr[2 * ee], gi = conj_sign * frr[2 * ee + 1];
+                    const bool re = (col & 1) == 0;
+                    // re column: re*gr - im*gi; im column: re*gi + im*gr
+                    const float o0 = re ? v0 * gr - p0 * gi : p0 * gi + v0 * gr;
+                    const float o1 = re ? v1 * gr - p1 * gi : p1 * gi + v1 * gr;
+                    acc[nu * NC + col] += o0;
+                    acc[nu * NC + 16 + col] += o1;
+                }
+            }
+            __threadfence_block();
         }
     }
     float* out = (float*)(Fp + (size_t)sp * P * 16);

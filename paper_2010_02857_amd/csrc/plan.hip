@@ -86,10 +86,20 @@ int64_t find_prefix(const std::vector<uint64_t>& v, uint64_t key)
     return (int64_t)(it - v.begin());
 }
 
+// Device bytes a level's frame table may take when its frames are not shared
+// (IFGF_FRAME_BUDGET_MB, default 3072).
+double frame_budget_bytes()
+{
+    const char* e = std::getenv("IFGF_FRAME_BUDGET_MB");
+    double mb = e ? std::atof(e) : 3072.0;
+    return mb * 1024.0 * 1024.0;
+}
+
 // Child-to-parent frames of level d (children at d, parents at d - 1):
 // every (parent slot, child) pair is described by (parent cone, child
 // octant); the distinct pairs are tabulated once when they are shared at
-// least four times on average, otherwise the kernels compute the geometry.
+// least four times on average or the table fits the frame budget, otherwise
+// the kernels compute the geometry.
 void build_frames(HostPlan& hp, int d)
 {
     HostLevel& L = hp.L[d];
@@ -108,7 +118,11 @@ void build_frames(HostPlan& hp, int d)
     std::sort(keys.begin(), keys.end());
     keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
     L.nframes = (int64_t)keys.size();
-    L.use_frames = L.nframes * 4 <= L.npairs;
+    // tabulate when frames are shared at least 4x, or when the table is small
+    // enough (it replaces FP64 geometry in the kernels, also at levels where
+    // every frame is used once)
+    const double budget = frame_budget_bytes();
+    L.use_frames = L.nframes * 4 <= L.npairs || (double)L.nframes * P * 26.0 <= budget;
     if (!L.use_frames) {
         L.nframes = 0;
         return;
