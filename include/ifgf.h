@@ -112,6 +112,8 @@ typedef struct {
     int64_t n_frames[IFGF_MAX_LEVELS + 1];   /* distinct child-to-parent frames
                                                 tabulated for level d (0: the
                                                 geometry is computed on the fly) */
+    int32_t pairs_tabulated[IFGF_MAX_LEVELS + 1]; /* 1: the cousin-target geometry
+                                                of level d is tabulated        */
     int64_t device_bytes;                    /* device memory held by the plan  */
     double t_plan_s;                         /* host seconds to build the plan  */
 } ifgf_stats;

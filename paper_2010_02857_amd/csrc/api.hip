@@ -118,6 +118,30 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
         if (parent_of_interp) {
             if ((e = upload(p, H.chl_start, &L.chl_start)) != hipSuccess) return e;
         }
+        L.use_pairs = H.use_pairs ? 1 : 0;
+        if (H.use_pairs) {
+            L.npairs_cou = (long long)H.pr_slot.size();
+            std::vector<long long> pb(H.pair_base.begin(), H.pair_base.end());
+            if ((e = upload(p, pb, &L.pair_base)) != hipSuccess) return e;
+            if ((e = upload(p, H.pr_slot, &L.pr_slot)) != hipSuccess) return e;
+            if (p.precision == IFGF_MIXED) {
+                std::vector<float> t(H.pr_t.begin(), H.pr_t.end()), g(H.pr_g.begin(), H.pr_g.end());
+                const float* dt = nullptr;
+                if ((e = upload(p, t, &dt)) != hipSuccess) return e;
+                L.pr_t = dt;
+                if ((e = upload(p, g, &dt)) != hipSuccess) return e;
+                L.pr_g = dt;
+            } else {
+                const double* dt = nullptr;
+                if ((e = upload(p, H.pr_t, &dt)) != hipSuccess) return e;
+                L.pr_t = dt;
+                if ((e = upload(p, H.pr_g, &dt)) != hipSuccess) return e;
+                L.pr_g = dt;
+            }
+            std::vector<double>().swap(H.pr_t);
+            std::vector<double>().swap(H.pr_g);
+            std::vector<int32_t>().swap(H.pr_slot);
+        }
         L.use_frames = H.use_frames ? 1 : 0;
         if (d >= 4 && H.use_frames) {
             if ((e = upload(p, H.child_of, &L.child_of)) != hipSuccess) return e;
@@ -206,7 +230,10 @@ ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t 
     ifgf_status code = IFGF_OK;
     std::string msg;
     try {
-        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, p.hp, code);
+        // a tabulated cousin-target pair: slot, 3 local coordinates, complex G
+        double pair_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 24.0 : 44.0);
+        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes,
+                                    p.hp, code);
     } catch (const std::bad_alloc&) {
         delete pl;
         return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed while building the plan");

@@ -151,6 +151,15 @@ struct HostLevel {
     std::vector<uint8_t> fr_grp;              // [nframes][P]
     std::vector<uint8_t> fr_order;            // [nframes][P] points sorted by group
     std::vector<uint8_t> fr_goff;             // [nframes][kMaxFrameGroups + 1] group offsets
+    // Cousin-target pairs (levels d >= 3): for every target box T, cousin
+    // c of T and target t of T, entry pair_base[T] + c * n_T + t holds the
+    // slot of the cone of cousin c that contains t, t's local coordinates in
+    // it and the centred factor G(x_t, x_c); built when they fit the budget.
+    bool use_pairs = false;
+    std::vector<int64_t> pair_base;           // [nbox + 1]
+    std::vector<int32_t> pr_slot;             // [npairs]
+    std::vector<double> pr_t;                 // [3][npairs] (structure of arrays)
+    std::vector<double> pr_g;                 // [2][npairs]
 };
 
 struct HostPlan {
@@ -166,8 +175,10 @@ struct HostPlan {
 
 // Builds the hierarchy; returns an empty string on success, else a message.
 // `code` receives the ifgf_status on failure.
+// tab_elem_bytes: device bytes of one tabulated cousin-target pair (0: none).
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
-                            int leaf_ns, int leaf_nc, bool dilate, HostPlan& hp, ifgf_status& code);
+                            int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, HostPlan& hp,
+                            ifgf_status& code);
 
 // ---------------------------------------------------------- device mirror
 
@@ -204,6 +215,13 @@ struct LevelDev {
     const uint8_t* fr_grp;
     const uint8_t* fr_order;
     const uint8_t* fr_goff;
+    // cousin-target pairs (float for mixed, double for FP64)
+    int use_pairs;
+    long long npairs_cou;
+    const long long* pair_base;
+    const int32_t* pr_slot;
+    const void* pr_t;
+    const void* pr_g;
 };
 
 struct KernelConsts {

@@ -334,6 +334,60 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval(KernelConsts kc, LevelDe
     }
 }
 
+// Interpolation at cousin targets through the tabulated pairs: the slot,
+// local coordinates and centred factor of (target, cousin box) were computed
+// with the plan, so no FP64 geometry is left.  Entries of one target box are
+// stored cousin-major, so the targets of a box read consecutive entries.
+// The centred factor is conjugated for the adjoint (kappa < 0).
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_eval_pairs(KernelConsts kc, LevelDev L,
+                                                              const cpx<T>* __restrict__ F, cpx<T>* __restrict__ out)
+{
+    constexpr int P = PS * PA * PA;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int tb = L.pt_box[i];
+    const int b0 = L.box_start[tb];
+    const long long nT = L.box_start[tb + 1] - b0;
+    const int tl = i - b0;
+    const long long base = L.pair_base[tb];
+    const int nc = L.cou_start[tb + 1] - L.cou_start[tb];
+    const long long np = L.npairs_cou;
+    const T* pt = (const T*)L.pr_t;
+    const T* pg = (const T*)L.pr_g;
+    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int c = 0; c < nc; ++c) {
+        const long long e = base + c * nT + tl;
+        const int slot = L.pr_slot[e];
+        if (slot < 0) {
+            atomicAdd(kc.miss, 1ull);
+            continue;
+        }
+        T Ls[PS], Lt[PA], Lp[PA];
+        lagrange<T, PS>((double)pt[e], kc.cs, Ls);
+        lagrange<T, PA>((double)pt[np + e], kc.ca, Lt);
+        lagrange<T, PA>((double)pt[2 * np + e], kc.ca, Lp);
+        cpx<T> v[RB];
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
+        const T gr = pg[e], gi = conj_sign * pg[np + e];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            acc[r].x += v[r].x * gr - v[r].y * gi;
+            acc[r].y += v[r].x * gi + v[r].y * gr;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        cpx<T> o = out[(size_t)i * RB + r];
+        o.x += acc[r].x;
+        o.y += acc[r].y;
+        out[(size_t)i * RB + r] = o;
+    }
+}
+
 // Child-to-parent interpolation, children at level d (Algorithm 1, second
 // inner loop): for every interpolation point x of every relevant cone of a
 // level-(d-1) box j,
@@ -971,8 +1025,12 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
         else
             {
                 StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st);
-                k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
-                                                                             (C*)p.out_m);
+                if (p.L[d].use_pairs)
+                    k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
+                                                                                       (C*)p.out_m);
+                else
+                    k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                                 (C*)p.out_m);
             }
         if (d > 3 && !reuse && hp.L[d - 1].nslots > 0)
             {

@@ -86,6 +86,67 @@ int64_t find_prefix(const std::vector<uint64_t>& v, uint64_t key)
     return (int64_t)(it - v.begin());
 }
 
+// Device bytes all cousin-target pair tables together may take
+// (IFGF_PAIR_BUDGET_MB, default 6144).
+double pair_budget_bytes()
+{
+    const char* e = std::getenv("IFGF_PAIR_BUDGET_MB");
+    double mb = e ? std::atof(e) : 6144.0;
+    return mb * 1024.0 * 1024.0;
+}
+
+// Slot of cone (cell, is) of box b, or -1 (host twin of the device lookup).
+int32_t host_lookup(const HostLevel& L, int64_t b, int cell, int is)
+{
+    size_t c = (size_t)b * L.ncell + cell;
+    const uint64_t* M = &L.cell_mask[c * L.W];
+    int w = is >> 6, bit = is & 63;
+    if (!((M[w] >> bit) & 1ull)) return -1;
+    int cnt = __builtin_popcountll(M[w] & ((1ull << bit) - 1ull));
+    for (int i = 0; i < w; ++i) cnt += __builtin_popcountll(M[i]);
+    return L.cell_base[c] + cnt;
+}
+
+// Cousin-target pair table of level d (see HostLevel::use_pairs).
+void build_pairs(HostPlan& hp, int d)
+{
+    HostLevel& L = hp.L[d];
+    L.pair_base.assign(L.nbox + 1, 0);
+    for (int64_t T = 0; T < L.nbox; ++T) {
+        int64_t nT = L.box_start[T + 1] - L.box_start[T];
+        int64_t cT = L.cou_start[T + 1] - L.cou_start[T];
+        L.pair_base[T + 1] = L.pair_base[T] + nT * cT;
+    }
+    const int64_t np = L.pair_base[L.nbox];
+    L.pr_slot.assign(np, -1);
+    L.pr_t.assign((size_t)3 * np, 0.0);
+    L.pr_g.assign((size_t)2 * np, 0.0);
+    const double kappa = hp.kappa;
+    const double inv4pi = 1.0 / (4.0 * kPi);
+    parallel_for(L.nbox, [&](int64_t T) {
+        const int64_t nT = L.box_start[T + 1] - L.box_start[T];
+        for (int32_t c = L.cou_start[T]; c < L.cou_start[T + 1]; ++c) {
+            const int32_t k = L.cou[c];
+            const double* ctr = &L.box_ctr[3 * k];
+            for (int64_t t = 0; t < nT; ++t) {
+                const int64_t j = L.box_start[T] + t;
+                ConeLoc cl;
+                cone_locate(hp.pts[3 * j] - ctr[0], hp.pts[3 * j + 1] - ctr[1], hp.pts[3 * j + 2] - ctr[2], L.h, L.ds,
+                            L.dang, L.ns, L.nc, cl);
+                const int64_t e = L.pair_base[T] + (int64_t)(c - L.cou_start[T]) * nT + t;
+                L.pr_slot[e] = host_lookup(L, k, cl.cell, cl.is);
+                L.pr_t[e] = cl.ts;
+                L.pr_t[np + e] = cl.tt;
+                L.pr_t[2 * np + e] = cl.tp;
+                // G(x, x_k) = e^{i k r} / (4 pi r)
+                L.pr_g[e] = std::cos(kappa * cl.r) * inv4pi / cl.r;
+                L.pr_g[np + e] = std::sin(kappa * cl.r) * inv4pi / cl.r;
+            }
+        }
+    }, 1);
+    L.use_pairs = true;
+}
+
 // Device bytes a level's frame table may take when its frames are not shared
 // (IFGF_FRAME_BUDGET_MB, default 3072).
 double frame_budget_bytes()
@@ -218,7 +279,8 @@ void build_frames(HostPlan& hp, int d)
 }  // namespace
 
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
-                            int leaf_ns, int leaf_nc, bool dilate, HostPlan& hp, ifgf_status& code)
+                            int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, HostPlan& hp,
+                            ifgf_status& code)
 {
     auto t0 = std::chrono::steady_clock::now();
     code = IFGF_E_INVALID_ARG;
@@ -609,6 +671,21 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         L.slot_start.assign(L.nbox + 1, 0);
     }
 
+    // Cousin-target pair tables, coarse levels first, while the budget lasts.
+    {
+        const double per = tab_elem_bytes;
+        double used = 0.0;
+        for (int d = 3; d <= D && per > 0.0; ++d) {
+            HostLevel& L = hp.L[d];
+            double npairs = 0.0;
+            for (int64_t T = 0; T < L.nbox; ++T)
+                npairs += (double)(L.box_start[T + 1] - L.box_start[T]) * (L.cou_start[T + 1] - L.cou_start[T]);
+            if (used + npairs * per > pair_budget_bytes()) break;
+            used += npairs * per;
+            build_pairs(hp, d);
+        }
+    }
+
     // Statistics.
     ifgf_stats& st = hp.stats;
     std::memset(&st, 0, sizeof(st));
@@ -642,6 +719,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         st.n_cousin_evals[d] = ce;
         st.n_parent_evals[d] = pe;
         st.n_frames[d] = L.nframes;
+        st.pairs_tabulated[d] = L.use_pairs ? 1 : 0;
     }
     {
         const HostLevel& L = hp.L[D];

@@ -68,6 +68,7 @@ class Stats(ctypes.Structure):
         ("n_near_pairs", ctypes.c_int64),
         ("n_dilated", ctypes.c_int64),
         ("n_frames", ctypes.c_int64 * _L),
+        ("pairs_tabulated", ctypes.c_int32 * _L),
         ("device_bytes", ctypes.c_int64),
         ("t_plan_s", ctypes.c_double),
     ]
@@ -178,7 +179,7 @@ class Plan:
                "ps": st.ps, "pang": st.pang, "n_leaf_pairs": st.n_leaf_pairs, "n_near_pairs": st.n_near_pairs,
                "n_dilated": st.n_dilated, "device_bytes": st.device_bytes, "t_plan_s": st.t_plan_s}
         for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
-                    "n_parent_evals", "n_frames"):
+                    "n_parent_evals", "n_frames", "pairs_tabulated"):
             arr = getattr(st, key)
             out[key] = [int(arr[d]) for d in range(D + 1)]
         return out
