@@ -143,8 +143,9 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
             std::vector<int32_t>().swap(H.pr_slot);
         }
         L.use_frames = H.use_frames ? 1 : 0;
-        if (d >= 4 && H.use_frames) {
+        if (d >= 4)
             if ((e = upload(p, H.child_of, &L.child_of)) != hipSuccess) return e;
+        if (d >= 4 && H.use_frames) {
             if ((e = upload(p, H.pframe, &L.pframe)) != hipSuccess) return e;
             if ((e = upload(p, H.fr_key, &L.fr_key)) != hipSuccess) return e;
             if (p.precision == IFGF_MIXED) {

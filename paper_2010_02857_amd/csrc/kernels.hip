@@ -651,23 +651,111 @@ __device__ inline float pick(const float* v, int i)
     return x;
 }
 
-template <int PS, int PA>
+// One 16-row MFMA tile: rows are interpolation points of one child cone,
+// columns the NC real values of the RB right-hand sides in NT tiles of 16.
+// `b` holds the child cone's values as B operands (K ordering as described
+// above); Ls/Lt/Lpv are the Chebyshev weights of this lane's row.
+template <int PS, int PA, int NT>
+__device__ inline void mfma_tile(const float (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4], const float* Ls,
+                                 const float* Lt, const float* Lpv, int q, mf4* c)
+{
+    constexpr int NAB = PS * PA;
+    constexpr int NREM = NAB * (PA - 4);
+    constexpr int KTAIL = (NREM + 3) / 4;
+    const float lq = pick<4>(Lpv, q);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) c[t] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ab = 0; ab < NAB; ++ab) {
+        const int a = ab / PA, bb = ab - a * PA;
+        const float w = Ls[a] * Lt[bb] * lq;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b[t][ab], c[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int jt = 0; jt < KTAIL; ++jt) {
+        const int m = 4 * jt + q;
+        float w = 0.f;
+        if (m < NREM) {
+            const int abm = m / (PA - 4), cc = 4 + (m - abm * (PA - 4));
+            const int a = abm / PA, bb = abm - a * PA;
+            w = pick<PS>(Ls, a) * pick<PA>(Lt, bb) * pick<PA>(Lpv, cc);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b[t][NAB + jt], c[t], 0, 0, 0);
+    }
+}
+
+// B operands of a child cone: lane (q, col) takes K entries (a, b, c = q)
+// and the tail entries c >= 4, column 16 t + col of every tile t.
+template <int PS, int PA, int NC, int NT>
+__device__ inline void mfma_load_b(const float* __restrict__ Fcs, int q, int col,
+                                   float (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4])
+{
+    constexpr int NAB = PS * PA;
+    constexpr int NREM = NAB * (PA - 4);
+    constexpr int KTAIL = (NREM + 3) / 4;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int cg = 16 * t + col;
+        const bool ok = cg < NC;
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) b[t][ab] = ok ? Fcs[(size_t)(ab * PA + q) * NC + cg] : 0.f;
+#pragma unroll
+        for (int jt = 0; jt < KTAIL; ++jt) {
+            const int m = 4 * jt + q;
+            float v = 0.f;
+            if (ok && m < NREM) {
+                const int abm = m / (PA - 4), cc = 4 + (m - abm * (PA - 4));
+                v = Fcs[(size_t)(abm * PA + cc) * NC + cg];
+            }
+            b[t][NAB + jt] = v;
+        }
+    }
+}
+
+// Epilogue of a tile: rows 4q + i, column col of each tile; multiply by the
+// row's ratio (complex: columns 2r, 2r+1 are re, im of right-hand side r) and
+// accumulate into the wavefront's LDS values of the parent slot.
+template <int NC, int NT>
+__device__ inline void mfma_epilogue(const mf4* c, int q, int col, int t0, int cnt, const int* rownode,
+                                     const float* ratio_re, const float* ratio_im, float* acc)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int ri = t0 + 4 * q + i;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float v = c[t][i];
+            const float pv = __shfl_xor(v, 1, 64);
+            const int cg = 16 * t + col;
+            if (ri < cnt && cg < NC) {
+                const int nu = rownode[ri];
+                const float gr = ratio_re[ri], gi = ratio_im[ri];
+                const float o = (col & 1) == 0 ? v * gr - pv * gi : pv * gi + v * gr;
+                acc[nu * NC + cg] += o;
+            }
+        }
+    }
+}
+
+template <int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                  const cpx<float>* __restrict__ Fc,
                                                                  cpx<float>* __restrict__ Fp)
 {
     constexpr int P = PS * PA * PA;
-    constexpr int NC = 32;                     // real columns: 16 complex right-hand sides
+    constexpr int NC = 2 * RB;                 // real columns
+    constexpr int NT = (NC + 15) / 16;         // 16-column tiles
     constexpr int G = kMaxFrameGroups;
     constexpr int W = kBlock / 64;             // wavefronts (parent slots) per block
-    constexpr int NAB = PS * PA;               // (a, b) pairs: K steps with phi-node c = q
-    constexpr int NREM = NAB * (PA - 4);       // entries with phi-node c >= 4
-    constexpr int KTAIL = (NREM + 3) / 4;
-    constexpr int NK = NAB + KTAIL;
+    constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
     __shared__ float accs[W][P * NC];
     __shared__ int ents[W][8 * G];             // (octant << 8) | group
     __shared__ int entcs[W][8 * G];            // child slot of the entry, -1 missing
+    __shared__ int rown[W][P];                 // point of each row of the current group
+    __shared__ float rre[W][P], rim[W][P];     // its ratio
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -699,7 +787,6 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
     if (lane < 8)
         for (int g = 0; g < ngo; ++g) ents[wv][incl - ngo + g] = (lane << 8) | g;
     __threadfence_block();
-    // child slots of all entries, looked up in parallel
     for (int e = lane; e < nent; e += 64) {
         const int o = ents[wv][e] >> 8, g = ents[wv][e] & 255;
         const int f = Lc.pframe[(size_t)sp * 8 + o];
@@ -716,35 +803,27 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
         const int cs = entcs[wv][e];
         const uint8_t* ord = Lc.fr_order + (size_t)f * P;
         const int g0 = Lc.fr_goff[(size_t)f * (G + 1) + g], g1 = Lc.fr_goff[(size_t)f * (G + 1) + g + 1];
+        const int cnt = g1 - g0;
         if (cs < 0) {
-            if (lane == 0) atomicAdd(kc.miss, (unsigned long long)(g1 - g0));
+            if (lane == 0) atomicAdd(kc.miss, (unsigned long long)cnt);
             continue;
         }
-        // the child cone's values as B operands, kept for all tiles of the group
-        const float* Fcs = F + (size_t)cs * P * NC;
-        float b0[NK], b1[NK];
-#pragma unroll
-        for (int ab = 0; ab < NAB; ++ab) {
-            const float* src = Fcs + (size_t)(ab * PA + q) * NC + col;
-            b0[ab] = src[0];
-            b1[ab] = src[16];
+        // rows of the group: their points and ratios
+        for (int r = lane; r < cnt; r += 64) {
+            const int nu = ord[g0 + r];
+            const size_t ee = (size_t)f * P + nu;
+            rown[wv][r] = nu;
+            rre[wv][r] = frr[2 * ee];
+            rim[wv][r] = conj_sign * frr[2 * ee + 1];
         }
-#pragma unroll
-        for (int jt = 0; jt < KTAIL; ++jt) {
-            const int m = 4 * jt + q;
-            b0[NAB + jt] = b1[NAB + jt] = 0.f;
-            if (m < NREM) {
-                const int abm = m / (PA - 4), c = 4 + (m - abm * (PA - 4));
-                const float* src = Fcs + (size_t)(abm * PA + c) * NC + col;
-                b0[NAB + jt] = src[0];
-                b1[NAB + jt] = src[16];
-            }
-        }
-        for (int t0 = g0; t0 < g1; t0 += 16) {
+        float b[NT][NK];
+        mfma_load_b<PS, PA, NC, NT>(F + (size_t)cs * P * NC, q, col, b);
+        __threadfence_block();
+        for (int t0 = 0; t0 < cnt; t0 += 16) {
             float Ls[PS], Lt[PA], Lpv[PA];
             const int rr = t0 + row;
-            if (rr < g1) {
-                const size_t ee = (size_t)f * P + ord[rr];
+            if (rr < cnt) {
+                const size_t ee = (size_t)f * P + rown[wv][rr];
                 lagrange<float, PS>((double)frt[3 * ee], kc.cs, Ls);
                 lagrange<float, PA>((double)frt[3 * ee + 1], kc.ca, Lt);
                 lagrange<float, PA>((double)frt[3 * ee + 2], kc.ca, Lpv);
@@ -754,49 +833,142 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
 #pragma unroll
                 for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
             }
-            const float lq = pick<4>(Lpv, q);
-            mf4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ab = 0; ab < NAB; ++ab) {
-                const int a = ab / PA, b = ab - a * PA;
-                const float w = Ls[a] * Lt[b] * lq;
-                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0[ab], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1[ab], c1, 0, 0, 0);
-            }
-#pragma unroll
-            for (int jt = 0; jt < KTAIL; ++jt) {
-                const int m = 4 * jt + q;
-                float w = 0.f;
-                if (m < NREM) {
-                    const int abm = m / (PA - 4), c = 4 + (m - abm * (PA - 4));
-                    const int a = abm / PA, b = abm - a * PA;
-                    w = pick<PS>(Ls, a) * pick<PA>(Lt, b) * pick<PA>(Lpv, c);
-                }
-                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b0[NAB + jt], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b1[NAB + jt], c1, 0, 0, 0);
-            }
-            // rows 4q + i of the tile, column col: apply the ratio, accumulate
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ri = t0 + 4 * q + i;
-                const float v0 = c0[i], v1 = c1[i];
-                const float p0 = __shfl_xor(v0, 1, 64), p1 = __shfl_xor(v1, 1, 64);
-                if (ri < g1) {
-                    const int nu = ord[ri];
-                    const size_t ee = (size_t)f * P + nu;
-                    const float gr = frr[2 * ee], gi = conj_sign * frr[2 * ee + 1];
-                    const bool re = (col & 1) == 0;
-                    // re column: re*gr - im*gi; im column: re*gi + im*gr
-                    const float o0 = re ? v0 * gr - p0 * gi : p0 * gi + v0 * gr;
-                    const float o1 = re ? v1 * gr - p1 * gi : p1 * gi + v1 * gr;
-                    acc[nu * NC + col] += o0;
-                    acc[nu * NC + 16 + col] += o1;
-                }
-            }
+            mf4 c[NT];
+            mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
+            mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
             __threadfence_block();
         }
     }
-    float* out = (float*)(Fp + (size_t)sp * P * 16);
+    float* out = (float*)(Fp + (size_t)sp * P * RB);
+    for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
+}
+
+// The same on levels without tabulated frames: every lane computes the
+// child-frame geometry of its interpolation points in FP64 (as
+// k_child_to_parent does), and the wavefront groups the points by child cone
+// with ballots before running the MFMA tiles.
+template <int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                                     const cpx<float>* __restrict__ Fc,
+                                                                     cpx<float>* __restrict__ Fp)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int NC = 2 * RB;
+    constexpr int NT = (NC + 15) / 16;
+    constexpr int W = kBlock / 64;
+    constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    static_assert(P <= 128, "two passes of 64 points");
+    __shared__ float accs[W][P * NC];
+    __shared__ float nt[W][P][3];              // local coordinates of every point
+    __shared__ float nrr[W][P], nri[W][P];     // ratio of every point
+    __shared__ int rown[W][P];
+    __shared__ float rre[W][P], rim[W][P];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int sp = blockIdx.x * W + wv;
+    if (sp >= Lp.nslots) return;
+    float* acc = accs[wv];
+    for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
+
+    const float* F = (const float*)Fc;
+    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int j = Lp.slot_box[sp];
+    const int pcone = Lp.slot_cone[sp];
+    const int pcell = pcone / Lp.ns, pis = pcone - pcell * Lp.ns;
+    const double half = 0.5 * Lc.H;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+
+    for (int o = 0; o < 8; ++o) {
+        const int k = Lc.child_of[(size_t)j * 8 + o];
+        if (k < 0) continue;
+        const double ov[3] = {(o & 1) ? half : -half, (o & 2) ? half : -half, (o & 4) ? half : -half};
+        // geometry of the points nu = lane and nu = lane + 64
+        unsigned key[2] = {0xffffffffu, 0xffffffffu};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int nu = lane + 64 * h;
+            if (nu < P) {
+                const int a = nu / (PA * PA), bc = nu - a * PA * PA;
+                const double rr = Lp.node_r[pis * PS + a];
+                const double* dir = &Lp.node_dir[((size_t)pcell * PA * PA + bc) * 3];
+                const double y0 = rr * dir[0], y1 = rr * dir[1], y2 = rr * dir[2];
+                const double ry = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+                double v[3];
+                node_minus(rr, dir, ov, v);
+                ConeLoc cl;
+                cone_locate(v[0], v[1], v[2], Lc.h, Lc.ds, Lc.dang, Lc.ns, Lc.nc, cl);
+                key[h] = (unsigned)(cl.cell * Lc.ns + cl.is);
+                nt[wv][nu][0] = (float)cl.ts;
+                nt[wv][nu][1] = (float)cl.tt;
+                nt[wv][nu][2] = (float)cl.tp;
+                const double num = (ov[0] * ov[0] + ov[1] * ov[1] + ov[2] * ov[2]) -
+                                   2.0 * (y0 * ov[0] + y1 * ov[1] + y2 * ov[2]);
+                const double diff = num / (cl.r + ry);
+                float cph, sph;
+                expi<float>(kc.kappa * diff, cph, sph);
+                const float mag = (float)(ry / cl.r);
+                nrr[wv][nu] = mag * cph;
+                nri[wv][nu] = mag * sph;
+            }
+        }
+        __threadfence_block();
+        bool un0 = lane < P, un1 = lane + 64 < P;
+        for (;;) {
+            const unsigned long long m0 = __ballot(un0), m1 = __ballot(un1);
+            if (!m0 && !m1) break;
+            const int leader = m0 ? (__ffsll((long long)m0) - 1) : 64 + (__ffsll((long long)m1) - 1);
+            const unsigned lkey = __shfl(leader < 64 ? key[0] : key[1], leader & 63, 64);
+            const bool in0 = un0 && key[0] == lkey, in1 = un1 && key[1] == lkey;
+            const unsigned long long g0 = __ballot(in0), g1 = __ballot(in1);
+            const int c0n = __popcll(g0);
+            const int cnt = c0n + __popcll(g1);
+            if (in0) {
+                const int r = __popcll(g0 & lt_mask);
+                rown[wv][r] = lane;
+                rre[wv][r] = nrr[wv][lane];
+                rim[wv][r] = nri[wv][lane];
+            }
+            if (in1) {
+                const int r = c0n + __popcll(g1 & lt_mask);
+                rown[wv][r] = lane + 64;
+                rre[wv][r] = nrr[wv][lane + 64];
+                rim[wv][r] = nri[wv][lane + 64];
+            }
+            un0 = un0 && !in0;
+            un1 = un1 && !in1;
+            const int cell = (int)(lkey / (unsigned)Lc.ns), is = (int)(lkey - (unsigned)cell * Lc.ns);
+            const int cs = lookup(Lc, k, cell, is);
+            __threadfence_block();
+            if (cs < 0) {
+                if (lane == 0) atomicAdd(kc.miss, (unsigned long long)cnt);
+                continue;
+            }
+            float b[NT][NK];
+            mfma_load_b<PS, PA, NC, NT>(F + (size_t)cs * P * NC, q, col, b);
+            for (int t0 = 0; t0 < cnt; t0 += 16) {
+                float Ls[PS], Lt[PA], Lpv[PA];
+                const int rr = t0 + row;
+                if (rr < cnt) {
+                    const int nu = rown[wv][rr];
+                    lagrange<float, PS>((double)nt[wv][nu][0], kc.cs, Ls);
+                    lagrange<float, PA>((double)nt[wv][nu][1], kc.ca, Lt);
+                    lagrange<float, PA>((double)nt[wv][nu][2], kc.ca, Lpv);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
+#pragma unroll
+                    for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
+                }
+                mf4 c[NT];
+                mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
+                mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
+                __threadfence_block();
+            }
+        }
+    }
+    float* out = (float*)(Fp + (size_t)sp * P * RB);
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
 }
 
@@ -1038,13 +1210,15 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                 constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
                 constexpr int GCAP = lds_gcap<T, P, RB, S>();
                 bool staged = false;
-                if constexpr (std::is_same<T, float>::value && RB == 16 && PA >= 4) {
-                    if (p.L[d].use_frames && p.L[d].frame_groups_ok) {
-                        k_child_to_parent_mfma<PS, PA>
-                            <<<(unsigned)((hp.L[d - 1].nslots + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
-                                kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
-                        staged = true;
-                    }
+                if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
+                    const unsigned nb = (unsigned)((hp.L[d - 1].nslots + kBlock / 64 - 1) / (kBlock / 64));
+                    if (p.L[d].use_frames && p.L[d].frame_groups_ok)
+                        k_child_to_parent_mfma<PS, PA, RB><<<nb, kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1],
+                                                                                  (const C*)p.F[d], (C*)p.F[d - 1]);
+                    else
+                        k_child_to_parent_mfma_geo<PS, PA, RB><<<nb, kBlock, 0, st>>>(
+                            kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+                    staged = true;
                 }
                 if (staged) {
                 } else if constexpr (GCAP >= S) {

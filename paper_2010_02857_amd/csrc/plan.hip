@@ -148,7 +148,8 @@ void build_pairs(HostPlan& hp, int d)
 }
 
 // Device bytes a level's frame table may take when its frames are not shared
-// (IFGF_FRAME_BUDGET_MB, default 3072).
+// (IFGF_FRAME_BUDGET_MB, default 3072).  IFGF_NO_FRAMES=1 disables the
+// tables (the kernels then compute every geometry themselves).
 double frame_budget_bytes()
 {
     const char* e = std::getenv("IFGF_FRAME_BUDGET_MB");
@@ -183,7 +184,9 @@ void build_frames(HostPlan& hp, int d)
     // enough (it replaces FP64 geometry in the kernels, also at levels where
     // every frame is used once)
     const double budget = frame_budget_bytes();
-    L.use_frames = L.nframes * 4 <= L.npairs || (double)L.nframes * P * 26.0 <= budget;
+    const char* nf = std::getenv("IFGF_NO_FRAMES");
+    L.use_frames = !(nf && std::atoi(nf) != 0) &&
+                   (L.nframes * 4 <= L.npairs || (double)L.nframes * P * 26.0 <= budget);
     if (!L.use_frames) {
         L.nframes = 0;
         return;

@@ -80,8 +80,8 @@ def test_cfg1_repeatable_and_plan_reuse(torch, w1):
     assert np.array_equal(o1, o2)          # gather-only kernels: bitwise repeatable
 
 
-@pytest.mark.parametrize("prec,nrhs", [("fp64", 2), ("fp64", 3), ("fp64", 16), ("fp64", 20), ("mixed", 5),
-                                       ("mixed", 16)])
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 2), ("fp64", 3), ("fp64", 16), ("fp64", 20), ("mixed", 3),
+                                       ("mixed", 5), ("mixed", 16)])
 def test_batched_rhs(torch, prec, nrhs):
     """Several density vectors per call (padded to 1/4/16 per pass; more
     than 16 in several passes) equal the oracle vector by vector."""
@@ -189,6 +189,25 @@ def test_small_and_degenerate(torch, case):
     out = plan.apply(dev(torch, a, "fp64")).cpu().numpy()
     ref = oracle.ifgf(p, a, k, levels=levels, degrees=deg, leaf=leaf)["out"]
     assert rel(out, ref) < FP64_TOL
+    assert plan.misses() == 0
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("mixed", 1), ("mixed", 4), ("mixed", 16)])
+def test_without_frame_tables(torch, monkeypatch, prec, nrhs):
+    """The kernels that compute the child-to-parent geometry themselves (used
+    where the frame tables would not fit) give the same results."""
+    monkeypatch.setenv("IFGF_NO_FRAMES", "1")
+    p = inputs.cube_sphere(20)
+    k = 5.0 * math.pi
+    a = inputs.densities(12, nrhs, p.shape[0])
+    plan = make_plan(p, k, prec, max_nrhs=16)
+    assert sum(plan.stats()["n_frames"]) == 0
+    out = plan.apply(dev(torch, a, prec)).cpu().numpy()
+    ref = oracle.ifgf(p, a if prec == "fp64" else as_c64(a), k)["out"]
+    assert rel(out, ref) < (FP64_TOL if prec == "fp64" else MIXED_TOL)
+    adj = plan.adjoint(dev(torch, a, prec)).cpu().numpy()
+    ref_adj = np.conj(oracle.ifgf(p, np.conj(a if prec == "fp64" else as_c64(a)), k)["out"])
+    assert rel(adj, ref_adj) < (FP64_TOL if prec == "fp64" else MIXED_TOL)
     assert plan.misses() == 0
 
 
