@@ -10,6 +10,13 @@ reported separately (as the paper reports T_pre apart from T_acc).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 Prints one JSON line.
+
+Profiling: `python bench.py --profile-commands DIR` prints the three
+rocprofv3 commands (kernel trace with stats; FETCH_SIZE; WRITE_SIZE) whose
+outputs `python bench.py --summarize DIR` turns into the summaries under
+profiles/.  The counter runs also time a plain copy kernel of known size
+(--copy-calibration), whose counter readings give the bytes-per-KiB scale
+applied to the IFGF kernels' readings.
 """
 from __future__ import annotations
 
@@ -42,6 +49,91 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2010_02857_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+WORKLOAD_TAG = "sphere393216"
+TRACE_ARGS = "--steps 5 --warmup 1 --no-extras --no-cpu-baseline"
+PMC_ARGS = "--steps 2 --warmup 1 --no-extras --no-cpu-baseline --copy-calibration"
+COPY_NUMEL = 64 << 20          # float32 elements read and written by the calibration copy
+
+
+def profile_commands(d: str) -> list[str]:
+    return [
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- python3 bench.py {TRACE_ARGS}",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- python3 bench.py {PMC_ARGS}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- python3 bench.py {PMC_ARGS}",
+    ]
+
+
+def _short(name: str) -> str:
+    name = name.replace("void ifgf::(anonymous namespace)::", "")
+    return name.split("(")[0] if name.startswith("k_") else name[:60]
+
+
+def _find(d: str, suffix: str) -> str:
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def summarize(d: str) -> int:
+    """Writes profiles/<stage>_<workload>_kernel_trace.md and, from the two
+    counter runs, profiles/traffic_<stage>_<workload>.{json,md}."""
+    import csv
+    cmds = profile_commands(d)
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    stage = "child_to_parent"
+    # kernel trace statistics
+    rows = list(csv.DictReader(open(_find(os.path.join(d, "trace"), "kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# Kernel trace, {WORKLOAD_TAG} (mixed, 1 RHS): {TRACE_ARGS}", "",
+             "Command (repository root):", "", "    " + cmds[0], "",
+             "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
+    st_calls, st_ns = 0, 0.0
+    for r in rows[:16]:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
+    for r in rows:
+        if "k_child_to_parent" in r["Name"]:
+            st_calls += int(r["Calls"])
+            st_ns += float(r["TotalDurationNs"])
+    lines += ["", f"Stage `{stage}` (all k_child_to_parent* kernels): {st_calls} launches, "
+              f"average {st_ns / max(st_calls, 1) / 1e6:.4f} ms per launch.", ""]
+    with open(os.path.join(out_dir, f"{stage}_{WORKLOAD_TAG}_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    # HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+    rec = {"kernel_source_hash": kernel_source_hash(), "nrhs": 1, "stage": stage, "workload": WORKLOAD_TAG,
+           "commands": cmds[1:]}
+    md = [f"# HBM traffic of `{stage}`, {WORKLOAD_TAG} (mixed, 1 RHS)", "", "Commands (repository root):", ""]
+    md += ["    " + c for c in cmds[1:]] + [""]
+    for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        crow = list(csv.DictReader(open(_find(os.path.join(d, sub), "counter_collection.csv"))))
+        copy = [float(r["Counter_Value"]) for r in crow if "neg" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
+        kib = [float(r["Counter_Value"]) for r in crow
+               if "k_child_to_parent" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
+        if not copy or not kib:
+            raise RuntimeError(f"{ctr}: copy or {stage} dispatches missing")
+        scale = COPY_NUMEL * 4 / (sum(copy) / len(copy) * 1024.0)      # bytes per counter KiB
+        per_launch = sum(kib) / len(kib) * 1024.0 * scale
+        key = "fetch" if sub == "fetch" else "write"
+        rec[f"{key}_bytes_per_launch"] = per_launch
+        rec[f"{key}_copy_scale"] = scale
+        rec[f"{key}_dispatches"] = len(kib)
+        md.append(f"* {ctr}: copy kernel ({COPY_NUMEL * 4} B read and written) counts "
+                  f"{sum(copy) / len(copy):.1f} KiB per dispatch, scale {scale:.4f} B per counted byte; "
+                  f"`{stage}`: {len(kib)} dispatches, {per_launch / 1e6:.2f} MB per launch after scaling.")
+    rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    md += ["", f"HBM bytes per launch (fetch + write): {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB. "
+           f"Kernel source hash {rec['kernel_source_hash']}.", ""]
+    with open(os.path.join(out_dir, f"traffic_{stage}_{WORKLOAD_TAG}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    with open(os.path.join(out_dir, f"traffic_{stage}_{WORKLOAD_TAG}.md"), "w") as fh:
+        fh.write("\n".join(md))
+    print(json.dumps(rec))
+    return 0
 
 
 def stage_work(stats: dict, stage: str, nrhs: int, P: int, elem_bytes: int) -> tuple[float, float]:
@@ -82,7 +174,16 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / batched / adjoint / gradient timings")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain copy of known size (for scaling HBM byte counters)")
+    ap.add_argument("--profile-commands", metavar="DIR", help="print the profiling commands and exit")
+    ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from profiling outputs and exit")
     args = ap.parse_args()
+    if args.profile_commands:
+        print("\n".join(profile_commands(args.profile_commands)))
+        return 0
+    if args.summarize:
+        return summarize(args.summarize)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -94,6 +195,13 @@ def main() -> int:
     from paper_2010_02857_amd import ifgf, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(COPY_NUMEL, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.WORKLOADS[2]
     p = w.points()
     n = p.shape[0]
@@ -150,7 +258,7 @@ def main() -> int:
     bytes_per_launch = byts / launches_per_apply
     achieved = flops_per_launch / per_launch_s / 1e12
     traffic = None
-    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_sphere393216.json")
+    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{WORKLOAD_TAG}.json")
     if os.path.exists(tf):
         rec = json.load(open(tf))
         if rec.get("kernel_source_hash") == kernel_source_hash() and rec.get("nrhs") == 1:
