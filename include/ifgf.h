@@ -85,7 +85,14 @@ typedef struct {
                                 of a cone face, so that the GPU's own
                                 evaluation of the point's cone always finds
                                 computed data                                 */
-    int32_t reserved0;
+    int32_t use_graph;       /* 1: ifgf_apply / ifgf_apply_adjoint capture
+                                their kernel launches into a HIP graph the
+                                first time a (densities, out, nrhs,
+                                direction) combination is seen and replay it
+                                afterwards (on the caller's stream); at most
+                                8 graphs are kept per plan, least recently
+                                used dropped.  Ignored while stage profiling
+                                is on.  0: launch eagerly                     */
     size_t workspace_limit;  /* device bytes the plan may allocate, 0: none  */
 } ifgf_options;
 
@@ -173,6 +180,34 @@ ifgf_status ifgf_plan_stats(ifgf_plan_t plan, ifgf_stats* out);
 /* Synchronises the plan's last stream and reports how many interpolation
  * queries found no computed cone since the plan was created (must be 0). */
 ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses);
+
+/* Child-to-parent kernel variants (the interpolation from child to parent
+ * cone values, Sec. 3.3, Algorithm 1), for ifgf_plan_kernel_choice.  All
+ * compute the same values up to FP rounding order. */
+typedef enum {
+    IFGF_C2P_GEOMETRY = 0,      /* per point, child-frame geometry in FP64      */
+    IFGF_C2P_FRAMES = 1,        /* per point, tabulated frames                  */
+    IFGF_C2P_LDS = 2,           /* frames, child cones staged in LDS            */
+    IFGF_C2P_MFMA = 3,          /* batched RHS on matrix cores, per slot        */
+    IFGF_C2P_MFMA_GEOMETRY = 4, /* the same without frame tables                */
+    IFGF_C2P_BOXES = 5          /* matrix cores, boxes of one parent cone as
+                                   matrix columns (FP32, 1 or 4 RHS per pass) */
+} ifgf_c2p_variant;
+
+/* Times every applicable child-to-parent variant at every level for nrhs
+ * right-hand sides (1, 2-4 and 5-16 share a setting) and keeps the fastest
+ * for later apply and gradient calls of that size.  Runs on `stream` with
+ * zero densities, synchronously (returns when done); overwrites the plan's
+ * workspaces, so cone values stored by an earlier apply are discarded.  Must
+ * not be called while a stream capture is active.  Invalidates captured
+ * graphs.  IFGF_E_INVALID_ARG for nrhs outside [1, max_nrhs]. */
+ifgf_status ifgf_plan_autotune(ifgf_plan_t plan, int32_t nrhs, void* stream);
+
+/* variant[d] (host array of IFGF_MAX_LEVELS + 1 entries) receives the
+ * ifgf_c2p_variant used for the child-to-parent step from level d to d - 1
+ * for nrhs right-hand sides: the tuned one, or the default rule; -1 where
+ * there is no such step (d < 4, d > D, host_only plans). */
+ifgf_status ifgf_plan_kernel_choice(ifgf_plan_t plan, int32_t nrhs, int32_t* variant);
 
 /* Kernel stages of an apply or gradient call, for ifgf_plan_stage_times. */
 typedef enum {

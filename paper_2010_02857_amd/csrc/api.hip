@@ -51,8 +51,12 @@ void release(ifgf::DevicePlan& p)
         for (void* q : p.ws_allocs) (void)hipFree(q);
         for (void* q : p.allocs) (void)hipFree(q);
         for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
+        for (auto& g : p.graphs) (void)hipGraphExecDestroy(g.exec);
+        if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
+    p.graphs.clear();
+    p.cap_stream = nullptr;
     p.ws_allocs.clear();
     p.allocs.clear();
     p.events.clear();
@@ -78,6 +82,11 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
     p.allocs.push_back(m);
     p.miss = (unsigned long long*)m;
     if ((e = hipMemset(m, 0, sizeof(unsigned long long))) != hipSuccess) return e;
+    const size_t zb = (size_t)hp.P * kMaxRhsPass * 2 * sizeof(float);
+    if ((e = hipMalloc(&m, zb)) != hipSuccess) return e;
+    p.allocs.push_back(m);
+    p.zero_cone = m;
+    if ((e = hipMemset(m, 0, zb)) != hipSuccess) return e;
     p.L.assign(hp.D + 1, LevelDev{});
     for (int d = 1; d <= hp.D; ++d) {
         HostLevel& H = hp.L[d];
@@ -169,6 +178,9 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
                 if ((e = upload(p, H.fr_grp, &L.fr_grp)) != hipSuccess) return e;
                 if ((e = upload(p, H.fr_order, &L.fr_order)) != hipSuccess) return e;
                 if ((e = upload(p, H.fr_goff, &L.fr_goff)) != hipSuccess) return e;
+                L.ntiles = (int)H.ntiles;
+                if ((e = upload(p, H.bt_slot, &L.bt_slot)) != hipSuccess) return e;
+                if ((e = upload(p, H.bt_frame, &L.bt_frame)) != hipSuccess) return e;
             }
             // the host copies are no longer needed
             std::vector<double>().swap(H.fr_t);
@@ -227,6 +239,7 @@ ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t 
     p.max_nrhs = max_nrhs;
     p.store_levels = o.store_levels;
     p.host_only = o.host_only != 0;
+    p.use_graph = o.use_graph != 0;
     p.ws_limit = o.workspace_limit;
     ifgf_status code = IFGF_OK;
     std::string msg;
@@ -284,6 +297,52 @@ ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t 
     return IFGF_OK;
 }
 
+// The apply as a captured graph: captured on the plan's own stream the first
+// time a (densities, out, nrhs, direction) combination is seen with the
+// current workspaces and kernel choices, then replayed on the caller's
+// stream.  The graph holds kernel launches only.
+static hipError_t apply_graph(ifgf::DevicePlan& p, const void* a, int nrhs, void* out, double kappa, bool adj,
+                              hipStream_t st)
+{
+    hipError_t e = ifgf::run_prepare(p, nrhs);
+    if (e != hipSuccess) return e;
+    ifgf::DevicePlan::GraphEntry* hit = nullptr;
+    for (auto& g : p.graphs)
+        if (g.a == a && g.out == out && g.nrhs == nrhs && g.adj == adj && g.ws_gen == p.ws_gen &&
+            g.tune_gen == p.tune_gen)
+            hit = &g;
+    if (!hit) {
+        if (!p.cap_stream && (e = hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return e;
+        if ((e = hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+        hipError_t ea = ifgf::run_apply(p, a, nrhs, out, kappa, p.cap_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(p.cap_stream, &graph);
+        if (ea != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return ea != hipSuccess ? ea : e;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        const size_t kMaxGraphs = 8;
+        if (p.graphs.size() >= kMaxGraphs) {
+            size_t old = 0;
+            for (size_t i = 1; i < p.graphs.size(); ++i)
+                if (p.graphs[i].used < p.graphs[old].used) old = i;
+            (void)hipGraphExecDestroy(p.graphs[old].exec);
+            p.graphs.erase(p.graphs.begin() + (long)old);
+        }
+        p.graphs.push_back({a, out, nrhs, adj, p.ws_gen, p.tune_gen, exec, 0});
+        hit = &p.graphs.back();
+    }
+    hit->used = ++p.graph_clock;
+    if ((e = hipGraphLaunch(hit->exec, st)) != hipSuccess) return e;
+    ifgf::note_apply(p, a, nrhs, kappa);
+    return hipSuccess;
+}
+
 static ifgf_status apply_common(ifgf_plan_t plan, const void* a, int32_t nrhs, void* out, void* stream, bool adj)
 {
     ifgf_status s = check_apply_args(plan, a, out, nrhs);
@@ -291,8 +350,30 @@ static ifgf_status apply_common(ifgf_plan_t plan, const void* a, int32_t nrhs, v
     ifgf::DevicePlan& p = plan->p;
     DeviceGuard g(p.device);
     double kappa = adj ? -p.hp.kappa : p.hp.kappa;
-    hipError_t e = ifgf::run_apply(p, a, nrhs, out, kappa, (hipStream_t)stream);
+    hipError_t e = p.use_graph && !p.profiling
+                       ? apply_graph(p, a, nrhs, out, kappa, adj, (hipStream_t)stream)
+                       : ifgf::run_apply(p, a, nrhs, out, kappa, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, adj ? "ifgf_apply_adjoint" : "ifgf_apply");
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_autotune(ifgf_plan_t plan, int32_t nrhs, void* stream)
+{
+    if (!plan) return fail(IFGF_E_INVALID_ARG, "plan is NULL");
+    if (plan->p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
+    if (nrhs < 1 || nrhs > plan->p.max_nrhs) return fail(IFGF_E_INVALID_ARG, "nrhs out of range");
+    ifgf::DevicePlan& p = plan->p;
+    DeviceGuard g(p.device);
+    hipError_t e = ifgf::run_autotune(p, nrhs, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ifgf_plan_autotune");
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_kernel_choice(ifgf_plan_t plan, int32_t nrhs, int32_t* variant)
+{
+    if (!plan || !variant) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    if (nrhs < 1) return fail(IFGF_E_INVALID_ARG, "nrhs out of range");
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) variant[d] = ifgf::kernel_choice(plan->p, nrhs, d);
     return IFGF_OK;
 }
 

@@ -19,6 +19,10 @@ constexpr int kMaxNodes = 8;       // Chebyshev nodes per direction, upper bound
 constexpr int kMaxRhsPass = 16;    // right-hand sides handled by one kernel pass
 constexpr double kDilateTol = 1e-9;
 constexpr int kMaxFrameGroups = 32;  // distinct child cones one frame may touch
+constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone per box tile
+// child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)
+enum { kC2PGeometry = 0, kC2PFrames = 1, kC2PLds = 2, kC2PMfma = 3, kC2PMfmaGeometry = 4, kC2PBoxes = 5,
+       kC2PVariants = 6 };
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).
@@ -151,6 +155,12 @@ struct HostLevel {
     std::vector<uint8_t> fr_grp;              // [nframes][P]
     std::vector<uint8_t> fr_order;            // [nframes][P] points sorted by group
     std::vector<uint8_t> fr_goff;             // [nframes][kMaxFrameGroups + 1] group offsets
+    // Box tiles: the parent slots sorted by parent cone and cut into runs of
+    // at most kBoxTile slots of one cone (boxes that share every frame), for
+    // the child-to-parent kernel that batches boxes as matrix columns.
+    int64_t ntiles = 0;
+    std::vector<int32_t> bt_slot;             // [ntiles][kBoxTile] parent slot, -1 pad
+    std::vector<int32_t> bt_frame;            // [ntiles][8] frame of octant o, -1 none
     // Cousin-target pairs (levels d >= 3): for every target box T, cousin
     // c of T and target t of T, entry pair_base[T] + c * n_T + t holds the
     // slot of the cone of cousin c that contains t, t's local coordinates in
@@ -215,6 +225,9 @@ struct LevelDev {
     const uint8_t* fr_grp;
     const uint8_t* fr_order;
     const uint8_t* fr_goff;
+    int ntiles;
+    const int32_t* bt_slot;
+    const int32_t* bt_frame;
     // cousin-target pairs (float for mixed, double for FP64)
     int use_pairs;
     long long npairs_cou;
@@ -246,6 +259,7 @@ struct DevicePlan {
     int32_t* iperm = nullptr;   // input index -> Morton position
     std::vector<LevelDev> L;
     unsigned long long* miss = nullptr;
+    void* zero_cone = nullptr;  // [P][kMaxRhsPass] complex zeros (FP32 view)
     std::vector<void*> allocs;
     size_t tree_bytes = 0;
     // workspaces, sized for `ws_rb` right-hand sides per pass
@@ -267,6 +281,24 @@ struct DevicePlan {
     std::vector<Pending> pending;
     double stage_ms[IFGF_NUM_STAGES] = {};
     int64_t stage_launches[IFGF_NUM_STAGES] = {};
+    // child-to-parent variant per (right-hand-side block 1 / 4 / 16, level),
+    // -1: the default rule; set by ifgf_plan_autotune
+    int c2p_choice[3][IFGF_MAX_LEVELS + 1];
+    DevicePlan()
+    {
+        for (auto& r : c2p_choice)
+            for (int& c : r) c = -1;
+    }
+    int tune_gen = 0;            // bumped when the choices change
+    int ws_gen = 0;              // bumped when the workspaces are reallocated
+    // captured apply graphs (use_graph)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        const void* a; void* out; int nrhs; bool adj; int ws_gen, tune_gen; hipGraphExec_t exec; uint64_t used;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     // what the stored cone values hold (for gradient reuse)
     const void* stored_dens = nullptr;
     int stored_nrhs = 0;
@@ -310,6 +342,16 @@ class StageTimer {
 // the adjoint.  Each enqueues on `stream` and returns hipSuccess or the
 // first launch error.
 hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t stream);
+// Allocates the workspaces an apply with nrhs right-hand sides needs (so
+// that the apply itself allocates nothing and can be captured).
+hipError_t run_prepare(DevicePlan& p, int nrhs);
+// Records after an apply (eager or replayed) what the stored cone values hold.
+void note_apply(DevicePlan& p, const void* dens, int nrhs, double kappa);
+// Times every child-to-parent variant of every level for nrhs right-hand
+// sides (densities zero, synchronous) and keeps the fastest.
+hipError_t run_autotune(DevicePlan& p, int nrhs, hipStream_t st);
+// Variant of level d for nrhs right-hand sides (-1: no child-to-parent step).
+int kernel_choice(const DevicePlan& p, int nrhs, int d);
 hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
                     hipStream_t stream);
 

@@ -12,6 +12,7 @@
 // interpolation weights and accumulation are FP32.
 #include "ifgf_internal.hpp"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace ifgf {
@@ -42,6 +43,18 @@ __device__ inline void expi<float>(double ph, float& c, float& s)
     double q = rint(ph * kInv2Pi);
     float red = (float)(ph - q * k2Pi);
     sincosf(red, &s, &c);
+}
+
+// The dispatcher hands workgroups to the eight XCDs in turn (workgroup b to
+// XCD b mod 8), and each XCD has its own L2.  Neighbouring work items read
+// the same cone values, so the workgroup index is renumbered to give each XCD
+// one contiguous range of the grid: XCD x takes indices
+// [x per + min(x, rem), ...) in dispatch order.  A bijection of [0, nb).
+__device__ inline int xcd_block(int b, int nb)
+{
+    const int x = b & 7, l = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return x * per + (x < rem ? x : rem) + l;
 }
 
 // Lagrange basis of the N first-kind Chebyshev nodes at t:
@@ -209,7 +222,7 @@ template <typename T, int RB>
 __global__ void __launch_bounds__(kBlock) k_nearfield(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
                                                       const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int b = L.pt_box[i];
     const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
@@ -247,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_leaf_nodes(KernelConsts kc, LevelDev
                                                        const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ F)
 {
     constexpr int P = PS * PA * PA;
-    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     int slot = (int)(gid / P);
     int nu = (int)(gid - (size_t)slot * P);
     if (slot >= L.nslots) return;
@@ -292,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval(KernelConsts kc, LevelDe
                                                         const cpx<T>* __restrict__ F, cpx<T>* __restrict__ out)
 {
     constexpr int P = PS * PA * PA;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int t = L.pt_box[i];
     const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
@@ -344,7 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval_pairs(KernelConsts kc, L
                                                               const cpx<T>* __restrict__ F, cpx<T>* __restrict__ out)
 {
     constexpr int P = PS * PA * PA;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int tb = L.pt_box[i];
     const int b0 = L.box_start[tb];
@@ -399,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, Lev
                                                             const cpx<T>* __restrict__ Fc, cpx<T>* __restrict__ Fp)
 {
     constexpr int P = PS * PA * PA;
-    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     int pslot = (int)(gid / P);
     int nu = (int)(gid - (size_t)pslot * P);
     if (pslot >= Lp.nslots) return;
@@ -460,7 +473,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_frames(KernelConsts 
                                                                    cpx<T>* __restrict__ Fp)
 {
     constexpr int P = PS * PA * PA;
-    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     int pslot = (int)(gid / P);
     int nu = (int)(gid - (size_t)pslot * P);
     if (pslot >= Lp.nslots) return;
@@ -524,7 +537,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
     __shared__ int staged[MAXE];      // child slot of each entry, -1 missing
 
     const int tid = threadIdx.x;
-    const int slot0 = blockIdx.x * S;
+    const int slot0 = xcd_block(blockIdx.x, gridDim.x) * S;
     const int s_me = tid / P;
     const int nu = tid - s_me * P;
     const int sp = slot0 + s_me;
@@ -642,12 +655,20 @@ constexpr int lds_gcap()
 // the same data and the result does not depend on scheduling.
 typedef float mf4 __attribute__((ext_vector_type(4)));
 
+// v[i] for a lane-dependent i, as a chain of selects on register values.
+// The empty asm makes each element opaque, so the compiler cannot fold the
+// chain back into an indexed load, which would move the array to scratch
+// memory and make every use wait for all outstanding global loads.
 template <int N>
 __device__ inline float pick(const float* v, int i)
 {
     float x = v[0];
 #pragma unroll
-    for (int j = 1; j < N; ++j) x = i == j ? v[j] : x;
+    for (int j = 1; j < N; ++j) {
+        float y = v[j];
+        asm("" : "+v"(y));
+        x = i == j ? y : x;
+    }
     return x;
 }
 
@@ -759,7 +780,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int sp = blockIdx.x * W + wv;
+    const int sp = xcd_block(blockIdx.x, gridDim.x) * W + wv;
     if (sp >= Lp.nslots) return;               // whole wavefront leaves; no block barriers below
     float* acc = accs[wv];
     for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
@@ -867,7 +888,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConst
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int sp = blockIdx.x * W + wv;
+    const int sp = xcd_block(blockIdx.x, gridDim.x) * W + wv;
     if (sp >= Lp.nslots) return;
     float* acc = accs[wv];
     for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
@@ -972,6 +993,306 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConst
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
 }
 
+// Orders the LDS accesses of one wavefront (which the LDS executes in issue
+// order) without waiting for outstanding global loads, so prefetches stay in
+// flight across it.
+__device__ inline void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Child-to-parent interpolation batched over boxes on the matrix cores
+// (FP32).  A frame depends only on the parent cone and the octant, so the
+// interpolation weights of a (frame, child cone) group are the same in every
+// box that holds the parent cone.  A box tile lists up to kBoxTile parent
+// slots of one parent cone; one wavefront runs, for every (octant, group)
+// entry, 16 x 16 x 4 MFMA tiles whose rows are the group's interpolation
+// points, K the child cone's nodes (ordered as in mfma_tile) and columns
+// (box, right-hand side, re / im), two 16-column tiles per pass: BX boxes per
+// pass, the tile's slots in ceil(n / BX) passes.
+//   Per octant, the frame's points are staged once (the products
+// Ls[a] Lt[b] and Lp[c] of every point, its re-centring ratio), the tiles
+// store their raw results in LDS, and one combine step multiplies them by the
+// ratio into accumulators held in registers: lane (ph, cc) owns complex
+// column cc and the points nu = ph + 4k.  All child slots of a pass are
+// looked up first, in parallel, and the B operands of the next entry and the
+// points of the next octant are loaded while the current tiles run.  Each
+// parent slot is written by exactly one wavefront.
+constexpr int kBoxMaxEnt = 32;    // (octant, group) entries looked up at once
+
+template <int PS, int PA, int RB>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<float>* __restrict__ Fc,
+                        cpx<float>* __restrict__ Fp, const cpx<float>* __restrict__ zero_cone)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int NT = 2;                      // tiles per pass: real and imaginary parts
+    static_assert(16 % RB == 0, "a pass holds whole boxes");
+    constexpr int BX = 16 / RB;                // boxes per pass (16 complex columns)
+    constexpr int AS = 33;                     // row stride of the raw results (odd: LDS banks)
+    constexpr int G = kMaxFrameGroups;
+    constexpr int ME = kBoxMaxEnt;
+    constexpr int NAB = PS * PA;
+    constexpr int NREM = NAB * (PA - 4);
+    constexpr int NK = NAB + (NREM + 3) / 4;
+    constexpr int WS = NAB + PA + 1;           // staged weights per point (odd stride: LDS banks)
+    constexpr int RPL = (P + 63) / 64;         // points per lane when staging
+    constexpr int KC = (P + 3) / 4;            // points per lane in the combine
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    static_assert(P <= 255 && ME >= G, "entry and point indices");
+    __shared__ float tmp[P * AS];              // raw tile results (re | im) by group position
+    __shared__ float wts[P * WS];              // Ls[a] Lt[b] (ab < NAB), then Lp[c], by group position
+    __shared__ float srat[P][2];               // ratio of point nu
+    __shared__ uint8_t spos[P];                // group position of point nu
+    __shared__ uint8_t sord[8 * P];            // points of the 8 frames in group order
+    __shared__ int sfr[8];                     // frame of each octant, -1
+    __shared__ int sgo[9];                     // first entry of each octant
+    __shared__ int bslot[kBoxTile];
+    __shared__ int kch[kBoxTile * 8];          // child box of (tile box, octant), -1
+    __shared__ int einfo[ME];                  // g0 | cnt << 8 | o << 16
+    __shared__ unsigned ekey[ME];              // child cone key of the entry
+    __shared__ int ecs[ME * BX];               // child slot of (entry, box of the pass), -1
+
+    const int lane = threadIdx.x;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    if (tile >= Lc.ntiles) return;
+    const float* frt = (const float*)Lc.fr_t;
+    const float* frr = (const float*)Lc.fr_ratio;
+    const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
+    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int cc = lane & 15, ph = lane >> 4;  // combine: complex column, point phase
+
+    // the tile's slots, their boxes' children, the octants' frames
+    int my_slot = -1, fo = -1, ng = 0;
+    if (lane < kBoxTile) {
+        my_slot = Lc.bt_slot[(size_t)tile * kBoxTile + lane];
+        bslot[lane] = my_slot;
+    }
+    if (lane < 8) {
+        fo = Lc.bt_frame[(size_t)tile * 8 + lane];
+        ng = fo >= 0 ? Lc.fr_ngrp[fo] : 0;
+    }
+    const int nbt = __popcll(__ballot(my_slot >= 0));
+    int incl = ng;
+#pragma unroll
+    for (int dd = 1; dd < 8; dd <<= 1) {
+        const int y = __shfl_up(incl, dd, 64);
+        if (lane >= dd) incl += y;
+    }
+    const int nent = __shfl(incl, 7, 64);
+    if (lane < 8) {
+        sfr[lane] = fo;
+        sgo[lane] = incl - ng;
+    }
+    if (lane == 0) sgo[8] = nent;
+    const int my_box = my_slot >= 0 ? Lp.slot_box[my_slot] : -1;
+    for (int i = lane; i < kBoxTile * 8; i += 64) {
+        const int b = __shfl(my_box, i >> 3, 64);
+        kch[i] = b >= 0 ? Lc.child_of[(size_t)b * 8 + (i & 7)] : -1;
+    }
+    wave_lds_fence();
+    for (int i = lane; i < 8 * P; i += 64) {
+        const int o = i / P, r = i - o * P;
+        const int f = sfr[o];
+        const uint8_t v = Lc.fr_order[(size_t)(f >= 0 ? f : 0) * P + r];
+        sord[i] = f >= 0 ? v : (uint8_t)0;
+    }
+    wave_lds_fence();
+
+    // point data of an octant's frame (by group position r = lane + 64 h)
+    int pn[RPL];
+    float pt[RPL][3], pg[RPL][2];
+    auto fetch_points = [&](int o) {
+        const int f = sfr[o];
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+            int r = lane + 64 * h;
+            r = r < P ? r : 0;
+            const int nu = sord[o * P + r];
+            const size_t ee = (size_t)(f >= 0 ? f : 0) * P + nu;
+            pn[h] = nu;
+            pt[h][0] = frt[3 * ee];
+            pt[h][1] = frt[3 * ee + 1];
+            pt[h][2] = frt[3 * ee + 2];
+            pg[h][0] = frr[2 * ee];
+            pg[h][1] = frr[2 * ee + 1];
+        }
+    };
+    // B operands of an entry: column col is (box col / RB, right-hand side
+    // col % RB); tile 0 takes the real parts, tile 1 the imaginary parts, so
+    // each value is one 8-byte load.  A missing child reads the zero cone.
+    float bn[NT][NK];
+    auto fetch_b = [&](int ei) {
+        const int cs = ecs[ei * BX + col / RB];
+        const cpx<float>* src = cs >= 0 ? Fc + (size_t)cs * P * RB + (col % RB) : zero_cone;
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) {
+            const cpx<float> v = src[(size_t)(ab * PA + q) * RB];
+            bn[0][ab] = v.x;
+            bn[1][ab] = v.y;
+        }
+#pragma unroll
+        for (int jt = 0; jt < NK - NAB; ++jt) {
+            int m = 4 * jt + q;
+            m = m < NREM ? m : NREM - 1;
+            const int abm = m / (PA - 4), c4 = 4 + (m - abm * (PA - 4));
+            const cpx<float> v = src[(size_t)(abm * PA + c4) * RB];
+            bn[0][NAB + jt] = v.x;
+            bn[1][NAB + jt] = v.y;
+        }
+    };
+
+    for (int b0 = 0; b0 < nbt; b0 += BX) {
+        float accr[KC], acci[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) accr[k] = acci[k] = 0.f;
+        int o0 = 0;
+        while (o0 < 8) {
+            // a chunk of whole octants with at most ME entries
+            int o1 = o0 + 1;
+            while (o1 < 8 && sgo[o1 + 1] - sgo[o0] <= ME) ++o1;
+            const int e0 = sgo[o0], ne = sgo[o1] - e0;
+            for (int i = lane; i < ne; i += 64) {
+                const int e = e0 + i;
+                int o = o0;
+                for (int oo = o0 + 1; oo < o1; ++oo) o = sgo[oo] <= e ? oo : o;
+                const int g = e - sgo[o], f = sfr[o];
+                const int g0 = Lc.fr_goff[(size_t)f * (G + 1) + g], g1 = Lc.fr_goff[(size_t)f * (G + 1) + g + 1];
+                einfo[i] = g0 | ((g1 - g0) << 8) | (o << 16);
+                ekey[i] = Lc.fr_gkey[(size_t)f * G + g];
+            }
+            wave_lds_fence();
+            for (int i = lane; i < ne * BX; i += 64) {
+                const int ei = i / BX, bl = i - ei * BX;
+                const int bi = b0 + bl;
+                const int info = einfo[ei];
+                const int o = info >> 16;
+                const int k = bi < kBoxTile ? kch[bi * 8 + o] : -1;
+                int cs = -1;
+                if (k >= 0) {
+                    const unsigned key = ekey[ei];
+                    const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
+                    cs = lookup(Lc, k, cell, is);
+                    if (cs < 0) atomicAdd(kc.miss, (unsigned long long)((info >> 8) & 255));
+                }
+                ecs[i] = cs;
+            }
+            wave_lds_fence();
+            if (ne > 0) fetch_b(0);
+            int o_pts = o0;
+            while (o_pts < o1 && sfr[o_pts] < 0) ++o_pts;
+            if (o_pts < o1) fetch_points(o_pts);
+            int ei = 0;
+            for (int o = o0; o < o1; ++o) {
+                if (sfr[o] < 0) continue;
+                // stage the frame's points: weights by group position, ratio and position by point
+#pragma unroll
+                for (int h = 0; h < RPL; ++h) {
+                    const int r = lane + 64 * h;
+                    if (r < P) {
+                        float Ls[PS], Lt[PA], Lpv[PA];
+                        lagrange<float, PS>((double)pt[h][0], kc.cs, Ls);
+                        lagrange<float, PA>((double)pt[h][1], kc.ca, Lt);
+                        lagrange<float, PA>((double)pt[h][2], kc.ca, Lpv);
+                        float* w = &wts[r * WS];
+#pragma unroll
+                        for (int a = 0; a < PS; ++a)
+#pragma unroll
+                            for (int bb = 0; bb < PA; ++bb) w[a * PA + bb] = Ls[a] * Lt[bb];
+#pragma unroll
+                        for (int c4 = 0; c4 < PA; ++c4) w[NAB + c4] = Lpv[c4];
+                        srat[pn[h]][0] = pg[h][0];
+                        srat[pn[h]][1] = conj_sign * pg[h][1];
+                        spos[pn[h]] = (uint8_t)r;
+                    }
+                }
+                {
+                    int on = o + 1;
+                    while (on < o1 && sfr[on] < 0) ++on;
+                    if (on < o1) fetch_points(on);
+                }
+                wave_lds_fence();
+                const int e_end = sgo[o + 1] - e0;
+                for (; ei < e_end; ++ei) {
+                    const int info = einfo[ei];
+                    const int g0 = info & 255, cnt = (info >> 8) & 255;
+                    float b[NT][NK];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) b[t][k] = bn[t][k];
+                    if (ei + 1 < ne) fetch_b(ei + 1);
+                    for (int t0 = 0; t0 < cnt; t0 += 16) {
+                        const int rr = t0 + row;
+                        const int r = g0 + (rr < cnt ? rr : 0);
+                        const float* w = &wts[r * WS];
+                        const float z = rr < cnt ? 1.f : 0.f;
+                        const float lq = w[NAB + q] * z;
+                        mf4 c[NT];
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) c[t] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int ab = 0; ab < NAB; ++ab) {
+                            const float wk = w[ab] * lq;
+#pragma unroll
+                            for (int t = 0; t < NT; ++t)
+                                c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wk, b[t][ab], c[t], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int jt = 0; jt < NK - NAB; ++jt) {
+                            const int m = 4 * jt + q;
+                            const int mm = m < NREM ? m : 0;
+                            const int abm = mm / (PA - 4), c4 = 4 + (mm - abm * (PA - 4));
+                            const float wk = m < NREM ? w[abm] * w[NAB + c4] * z : 0.f;
+#pragma unroll
+                            for (int t = 0; t < NT; ++t)
+                                c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wk, b[t][NAB + jt], c[t], 0, 0, 0);
+                        }
+                        // rows 4q + i of the tile go to group positions g0 + t0 + 4q + i
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int ri = t0 + 4 * q + i;
+                            if (ri < cnt) {
+#pragma unroll
+                                for (int t = 0; t < NT; ++t) tmp[(g0 + ri) * AS + 16 * t + col] = c[t][i];
+                            }
+                        }
+                    }
+                }
+                wave_lds_fence();
+                // combine: value times ratio into the register accumulators
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int nu = ph + 4 * k;
+                    if (nu < P) {
+                        const int r = spos[nu];
+                        const float vr = tmp[r * AS + cc], vi = tmp[r * AS + 16 + cc];
+                        const float gr = srat[nu][0], gi = srat[nu][1];
+                        accr[k] += vr * gr - vi * gi;
+                        acci[k] += vr * gi + vi * gr;
+                    }
+                }
+                wave_lds_fence();
+            }
+            o0 = o1;
+        }
+        // write the pass's slots: column cc is (box bl, right-hand side rr)
+        const int bl = cc / RB, rr = cc - bl * RB;
+        const int bi = b0 + bl;
+        const int s = bi < kBoxTile ? bslot[bi] : -1;
+        if (s >= 0) {
+            cpx<float>* out = Fp + (size_t)s * P * RB + rr;
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const int nu = ph + 4 * k;
+                if (nu < P) out[(size_t)nu * RB] = cpx<float>{accr[k], acci[k]};
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- gradients
 
 // d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
@@ -981,7 +1302,7 @@ __global__ void __launch_bounds__(kBlock) k_near_grad(KernelConsts kc, LevelDev 
                                                       const cpx<T>* __restrict__ dens, const cpx<T>* __restrict__ gout,
                                                       double* __restrict__ grad)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int b = L.pt_box[i];
     const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
@@ -1031,7 +1352,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDe
                                                         double* __restrict__ grad)
 {
     constexpr int P = PS * PA * PA;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int t = L.pt_box[i];
     const double x0 = pts[3 * i], x1 = pts[3 * i + 1], x2 = pts[3 * i + 2];
@@ -1169,7 +1490,121 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     }
     p.ws_rb = rb;
     p.ws_store = store;
+    ++p.ws_gen;
     return hipSuccess;
+}
+
+// Least average number of slots per box tile (as a fraction of kBoxTile) for
+// which the box-batched child-to-parent kernel is used; IFGF_BOX_FILL
+// overrides it (a value above 1 disables the kernel).
+inline double box_fill_min(int rb)
+{
+    const char* v = std::getenv("IFGF_BOX_FILL");
+    if (v && *v) return std::atof(v);
+    return rb == 1 ? 0.5 : 0.25;
+}
+
+// Child-to-parent kernel variants of level d (children at d).  Every
+// variant writes every parent slot, so any one of them can serve a level.
+template <typename T, int PS, int PA, int RB>
+int c2p_candidates(const DevicePlan& p, int d, int* v)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
+    constexpr int GCAP = lds_gcap<T, P, RB, S>();
+    const LevelDev& L = p.L[d];
+    const bool groups = L.use_frames && L.frame_groups_ok;
+    int n = 0;
+    v[n++] = kC2PGeometry;
+    if (L.use_frames) v[n++] = kC2PFrames;
+    if constexpr (GCAP >= S) {
+        if (groups) v[n++] = kC2PLds;
+    }
+    if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
+        v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
+    }
+    if constexpr (std::is_same<T, float>::value && (RB == 1 || RB == 4) && PA >= 4 && P <= 128) {
+        if (groups && L.ntiles > 0) v[n++] = kC2PBoxes;
+    }
+    return n;
+}
+
+// The variant used when the plan has not been tuned: the box-batched kernel
+// where its tiles are full enough, else the matrix-core kernel for batched
+// FP32, else LDS staging, else the frame or geometry kernel.
+template <typename T, int PS, int PA, int RB>
+int c2p_default(const DevicePlan& p, int d)
+{
+    int v[kC2PVariants];
+    const int n = c2p_candidates<T, PS, PA, RB>(p, d, v);
+    auto has = [&](int x) {
+        for (int i = 0; i < n; ++i)
+            if (v[i] == x) return true;
+        return false;
+    };
+    if (has(kC2PBoxes) &&
+        (double)p.hp.L[d - 1].nslots >= box_fill_min(RB) * kBoxTile * (double)p.L[d].ntiles)
+        return kC2PBoxes;
+    if (has(kC2PMfma)) return kC2PMfma;
+    if (has(kC2PMfmaGeometry)) return kC2PMfmaGeometry;
+    if (has(kC2PLds)) return kC2PLds;
+    if (has(kC2PFrames)) return kC2PFrames;
+    return kC2PGeometry;
+}
+
+inline int rb_index(int rb) { return rb == 1 ? 0 : (rb == 4 ? 1 : 2); }
+
+template <typename T, int PS, int PA, int RB>
+int c2p_variant(const DevicePlan& p, int d)
+{
+    const int c = p.c2p_choice[rb_index(RB)][d];
+    return c >= 0 ? c : c2p_default<T, PS, PA, RB>(p, d);
+}
+
+template <typename T, int PS, int PA, int RB>
+void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipStream_t st)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
+    constexpr int GCAP = lds_gcap<T, P, RB, S>();
+    using C = cpx<T>;
+    const int64_t nps = p.hp.L[d - 1].nslots;
+    const C* Fc = (const C*)p.F[d];
+    C* Fp = (C*)p.F[d - 1];
+    switch (variant) {
+    case kC2PBoxes:
+        if constexpr (std::is_same<T, float>::value && (RB == 1 || RB == 4) && PA >= 4 && P <= 128) {
+            k_child_to_parent_boxes<PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+            return;
+        }
+        break;
+    case kC2PMfma:
+    case kC2PMfmaGeometry:
+        if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
+            const unsigned nb = (unsigned)((nps + kBlock / 64 - 1) / (kBlock / 64));
+            if (variant == kC2PMfma)
+                k_child_to_parent_mfma<PS, PA, RB><<<nb, kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            else
+                k_child_to_parent_mfma_geo<PS, PA, RB><<<nb, kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            return;
+        }
+        break;
+    case kC2PLds:
+        if constexpr (GCAP >= S) {
+            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP>
+                <<<(unsigned)((nps + S - 1) / S), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            return;
+        }
+        break;
+    case kC2PFrames:
+        k_child_to_parent_frames<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1],
+                                                                                             Fc, Fp);
+        return;
+    default:
+        break;
+    }
+    k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
 }
 
 template <typename T, int PS, int PA, int RB>
@@ -1207,35 +1642,7 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
         if (d > 3 && !reuse && hp.L[d - 1].nslots > 0)
             {
                 StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st);
-                constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
-                constexpr int GCAP = lds_gcap<T, P, RB, S>();
-                bool staged = false;
-                if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
-                    const unsigned nb = (unsigned)((hp.L[d - 1].nslots + kBlock / 64 - 1) / (kBlock / 64));
-                    if (p.L[d].use_frames && p.L[d].frame_groups_ok)
-                        k_child_to_parent_mfma<PS, PA, RB><<<nb, kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1],
-                                                                                  (const C*)p.F[d], (C*)p.F[d - 1]);
-                    else
-                        k_child_to_parent_mfma_geo<PS, PA, RB><<<nb, kBlock, 0, st>>>(
-                            kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
-                    staged = true;
-                }
-                if (staged) {
-                } else if constexpr (GCAP >= S) {
-                    if (p.L[d].use_frames && p.L[d].frame_groups_ok) {
-                        k_child_to_parent_lds<T, PS, PA, RB, S, GCAP>
-                            <<<(unsigned)((hp.L[d - 1].nslots + S - 1) / S), kBlock, 0, st>>>(
-                                kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
-                        staged = true;
-                    }
-                }
-                if (staged) {
-                } else if (p.L[d].use_frames)
-                    k_child_to_parent_frames<T, PS, PA, RB><<<grid_for((size_t)hp.L[d - 1].nslots * P), kBlock, 0, st>>>(
-                        kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
-                else
-                    k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)hp.L[d - 1].nslots * P), kBlock, 0, st>>>(
-                        kc, p.L[d], p.L[d - 1], (const C*)p.F[d], (C*)p.F[d - 1]);
+                c2p_launch<T, PS, PA, RB>(p, kc, d, c2p_variant<T, PS, PA, RB>(p, d), st);
             }
     }
     return hipGetLastError();
@@ -1324,7 +1731,120 @@ hipError_t grad_t(DevicePlan& p, const void* dens, const void* gout, int nrhs, d
     return grad_pass<T, PS, PA, 16>(p, dens, gout, nrhs, grad, reuse, st);
 }
 
+template <typename T, int PS, int PA, int RB>
+hipError_t autotune_t(DevicePlan& p, hipStream_t st)
+{
+    const HostPlan& hp = p.hp;
+    const int D = hp.D;
+    constexpr int P = PS * PA * PA;
+    using C = cpx<T>;
+    hipError_t e = ensure_workspace<T>(p, RB, p.ws_store_pref, nullptr);
+    if (e != hipSuccess) return e;
+    p.stored_valid = false;
+    if (D < 4) return hipSuccess;
+    const bool prof = p.profiling;
+    p.profiling = false;
+    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), hp.kappa, (int)hp.n, p.miss};
+    if ((e = hipMemsetAsync(p.dens_m, 0, (size_t)hp.n * RB * sizeof(C), st)) != hipSuccess) return e;
+    if (hp.L[D].nslots > 0)
+        k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
+            kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    for (int d = D; d >= 4 && e == hipSuccess; --d) {
+        if (hp.L[d - 1].nslots == 0) continue;
+        int v[kC2PVariants];
+        const int nv = c2p_candidates<T, PS, PA, RB>(p, d, v);
+        int best = c2p_default<T, PS, PA, RB>(p, d);
+        float best_ms = 1e30f;
+        for (int i = 0; i < nv && e == hipSuccess; ++i) {
+            float ms = 1e30f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                (void)hipEventRecord(e0, st);
+                c2p_launch<T, PS, PA, RB>(p, kc, d, v[i], st);
+                (void)hipEventRecord(e1, st);
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+                if ((e = hipGetLastError()) != hipSuccess) break;
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ms = t < ms ? t : ms;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = v[i];
+            }
+        }
+        if (e != hipSuccess) break;
+        p.c2p_choice[rb_index(RB)][d] = best;
+        c2p_launch<T, PS, PA, RB>(p, kc, d, best, st);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p.profiling = prof;
+    ++p.tune_gen;
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+template <typename T, int PS, int PA>
+hipError_t autotune_rb(DevicePlan& p, int rb, hipStream_t st)
+{
+    if (rb == 1) return autotune_t<T, PS, PA, 1>(p, st);
+    if (rb == 4) return autotune_t<T, PS, PA, 4>(p, st);
+    return autotune_t<T, PS, PA, 16>(p, st);
+}
+
+template <typename T, int PS, int PA>
+int choice_t(const DevicePlan& p, int rb, int d)
+{
+    if (rb == 1) return c2p_variant<T, PS, PA, 1>(p, d);
+    if (rb == 4) return c2p_variant<T, PS, PA, 4>(p, d);
+    return c2p_variant<T, PS, PA, 16>(p, d);
+}
+
 }  // namespace
+
+hipError_t run_prepare(DevicePlan& p, int nrhs)
+{
+    const int rb = rb_for(std::min(kMaxRhsPass, nrhs));
+    const bool store = p.ws_store_pref && nrhs <= kMaxRhsPass;
+    return p.precision == IFGF_MIXED ? ensure_workspace<float>(p, rb, store, nullptr)
+                                     : ensure_workspace<double>(p, rb, store, nullptr);
+}
+
+void note_apply(DevicePlan& p, const void* dens, int nrhs, double kappa)
+{
+    p.stored_valid = p.ws_store && kappa == p.hp.kappa && nrhs <= kMaxRhsPass && p.ws_rb == rb_for(nrhs);
+    p.stored_dens = dens;
+    p.stored_nrhs = nrhs;
+}
+
+hipError_t run_autotune(DevicePlan& p, int nrhs, hipStream_t st)
+{
+    const int rb = rb_for(std::min(kMaxRhsPass, nrhs));
+    const int ps = p.hp.ps, pa = p.hp.pang;
+    const bool mixed = p.precision == IFGF_MIXED;
+    if (ps == 3 && pa == 5) return mixed ? autotune_rb<float, 3, 5>(p, rb, st) : autotune_rb<double, 3, 5>(p, rb, st);
+    if (ps == 4 && pa == 6) return mixed ? autotune_rb<float, 4, 6>(p, rb, st) : autotune_rb<double, 4, 6>(p, rb, st);
+    if (ps == 2 && pa == 3) return mixed ? autotune_rb<float, 2, 3>(p, rb, st) : autotune_rb<double, 2, 3>(p, rb, st);
+    return hipErrorInvalidValue;
+}
+
+int kernel_choice(const DevicePlan& p, int nrhs, int d)
+{
+    if (d < 4 || d > p.hp.D || p.hp.L[d - 1].nslots == 0 || p.host_only) return -1;
+    const int rb = rb_for(std::min(kMaxRhsPass, nrhs));
+    const int ps = p.hp.ps, pa = p.hp.pang;
+    const bool mixed = p.precision == IFGF_MIXED;
+    if (ps == 3 && pa == 5) return mixed ? choice_t<float, 3, 5>(p, rb, d) : choice_t<double, 3, 5>(p, rb, d);
+    if (ps == 4 && pa == 6) return mixed ? choice_t<float, 4, 6>(p, rb, d) : choice_t<double, 4, 6>(p, rb, d);
+    if (ps == 2 && pa == 3) return mixed ? choice_t<float, 2, 3>(p, rb, d) : choice_t<double, 2, 3>(p, rb, d);
+    return -1;
+}
 
 hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t st)
 {
@@ -1339,11 +1859,7 @@ hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, doubl
         e = mixed ? apply_t<float, 2, 3>(p, dens, nrhs, out, kappa, st) : apply_t<double, 2, 3>(p, dens, nrhs, out, kappa, st);
     else
         return hipErrorInvalidValue;
-    if (e == hipSuccess) {
-        p.stored_valid = p.ws_store && kappa == p.hp.kappa && nrhs <= kMaxRhsPass && p.ws_rb == rb_for(nrhs);
-        p.stored_dens = dens;
-        p.stored_nrhs = nrhs;
-    }
+    if (e == hipSuccess) note_apply(p, dens, nrhs, kappa);
     return e;
 }
 

@@ -150,6 +150,14 @@ void build_pairs(HostPlan& hp, int d)
 // Device bytes a level's frame table may take when its frames are not shared
 // (IFGF_FRAME_BUDGET_MB, default 3072).  IFGF_NO_FRAMES=1 disables the
 // tables (the kernels then compute every geometry themselves).
+// Parent boxes per block of the box tiles (IFGF_TILE_BLOCK overrides).
+int64_t tile_box_block()
+{
+    const char* e = std::getenv("IFGF_TILE_BLOCK");
+    const int64_t v = e ? std::atoll(e) : 64;
+    return v < 1 ? 1 : v;
+}
+
 double frame_budget_bytes()
 {
     const char* e = std::getenv("IFGF_FRAME_BUDGET_MB");
@@ -277,6 +285,53 @@ void build_frames(HostPlan& hp, int d)
         uint8_t* ord = &L.fr_order[(size_t)f * P];
         for (int nu = 0; nu < P; ++nu) ord[cnt[grp[nu]]++] = (uint8_t)nu;
     }, 256);
+    // box tiles.  The parent boxes are cut into blocks of consecutive
+    // (Morton-ordered) boxes; within a block the slots are sorted by cone
+    // (boxes in order) and every run of one cone is cut into tiles.  Tiles of
+    // one block run close together in time and share the block's child cone
+    // values in cache; the block size trades that locality against the fill
+    // of the tiles.
+    const int64_t blk = tile_box_block();
+    const int64_t nblk = (Lp.nbox + blk - 1) / blk;
+    std::vector<std::vector<int32_t>> bslots(nblk);
+    std::vector<int64_t> bt(nblk + 1, 0);
+    parallel_for(nblk, [&](int64_t b) {
+        const int64_t j0 = b * blk, j1 = std::min<int64_t>(Lp.nbox, j0 + blk);
+        std::vector<int32_t>& v = bslots[b];
+        for (int64_t sl = Lp.slot_start[j0]; sl < Lp.slot_start[j1]; ++sl) v.push_back((int32_t)sl);
+        std::stable_sort(v.begin(), v.end(),
+                         [&](int32_t x, int32_t y) { return Lp.slot_cone[x] < Lp.slot_cone[y]; });
+        int64_t nt = 0;
+        for (size_t i = 0; i < v.size();) {
+            size_t e = i;
+            while (e < v.size() && Lp.slot_cone[v[e]] == Lp.slot_cone[v[i]]) ++e;
+            nt += (int64_t)((e - i + kBoxTile - 1) / kBoxTile);
+            i = e;
+        }
+        bt[b + 1] = nt;
+    }, 1);
+    for (int64_t b = 0; b < nblk; ++b) bt[b + 1] += bt[b];
+    L.ntiles = bt[nblk];
+    L.bt_slot.assign((size_t)L.ntiles * kBoxTile, -1);
+    L.bt_frame.assign((size_t)L.ntiles * 8, -1);
+    parallel_for(nblk, [&](int64_t b) {
+        const std::vector<int32_t>& v = bslots[b];
+        int64_t t = bt[b];
+        for (size_t i = 0; i < v.size();) {
+            size_t e = i;
+            while (e < v.size() && Lp.slot_cone[v[e]] == Lp.slot_cone[v[i]]) ++e;
+            for (size_t k0 = i; k0 < e; k0 += kBoxTile, ++t) {
+                const size_t k1 = std::min(e, k0 + kBoxTile);
+                for (size_t k = k0; k < k1; ++k) {
+                    const int32_t sl = v[k];
+                    L.bt_slot[(size_t)t * kBoxTile + (k - k0)] = sl;
+                    for (int o = 0; o < 8; ++o)
+                        if (L.pframe[(size_t)sl * 8 + o] >= 0) L.bt_frame[(size_t)t * 8 + o] = L.pframe[(size_t)sl * 8 + o];
+                }
+            }
+            i = e;
+        }
+    }, 1);
 }
 
 }  // namespace

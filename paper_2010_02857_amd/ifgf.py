@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
         ("store_levels", ctypes.c_int32),
         ("host_only", ctypes.c_int32),
         ("no_dilate", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
         ("workspace_limit", ctypes.c_size_t),
     ]
 
@@ -95,13 +95,15 @@ def lib() -> ctypes.CDLL:
         L.ifgf_plan_destroy.argtypes = [P]
         L.ifgf_plan_profile.argtypes = [P, I32]
         L.ifgf_plan_stage_times.argtypes = [P, P, P]
+        L.ifgf_plan_autotune.argtypes = [P, I32, P]
+        L.ifgf_plan_kernel_choice.argtypes = [P, I32, P]
         L.ifgf_status_string.argtypes = [ctypes.c_int]
         L.ifgf_status_string.restype = ctypes.c_char_p
         L.ifgf_last_error.argtypes = []
         L.ifgf_last_error.restype = ctypes.c_char_p
         for f in (L.ifgf_plan_create, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
                   L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy, L.ifgf_plan_profile,
-                  L.ifgf_plan_stage_times):
+                  L.ifgf_plan_stage_times, L.ifgf_plan_autotune, L.ifgf_plan_kernel_choice):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -127,11 +129,12 @@ class Plan:
     levels     D, or 0 for H_D about a quarter wavelength.
     degrees    (P_s, P_ang) Chebyshev nodes per cone direction.
     precision  "fp64" (complex128 I/O) or "mixed" (complex64 I/O).
+    use_graph  capture apply calls into HIP graphs and replay them.
     """
 
     def __init__(self, points, k: float, levels: int = 0, degrees=(3, 5), precision: str = "fp64",
                  leaf=(1, 2), max_nrhs: int = 16, store_levels: int = -1, host_only: bool = False,
-                 dilate: bool = True, workspace_limit: int = 0, device=None):
+                 dilate: bool = True, workspace_limit: int = 0, use_graph: bool = False, device=None):
         if hasattr(points, "detach"):
             points = points.detach().cpu().numpy()
         pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
@@ -141,7 +144,8 @@ class Plan:
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         opt = Options(int(leaf[0]), int(leaf[1]), FP64 if precision == "fp64" else MIXED, int(max_nrhs),
-                      int(store_levels), 1 if host_only else 0, 0 if dilate else 1, 0, int(workspace_limit))
+                      int(store_levels), 1 if host_only else 0, 0 if dilate else 1, 1 if use_graph else 0,
+                      int(workspace_limit))
         deg = (ctypes.c_int32 * 2)(int(degrees[0]), int(degrees[1]))
         h = ctypes.c_void_p()
         self._h = None
@@ -204,6 +208,22 @@ class Plan:
                                            cnt.ctypes.data_as(ctypes.c_void_p)))
         return {s: (float(ms[i]), int(cnt[i])) for i, s in enumerate(self.STAGES)}
 
+    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes")
+
+    def autotune(self, nrhs: int = 1):
+        """Time the child-to-parent kernel variants of every level for nrhs
+        right-hand sides on the current stream and keep the fastest."""
+        import torch
+        with torch.cuda.device(self.device):
+            _check(lib().ifgf_plan_autotune(self._h, int(nrhs),
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def kernel_choice(self, nrhs: int = 1) -> dict:
+        """{level d: variant name} of the child-to-parent step from d to d - 1."""
+        v = (ctypes.c_int32 * (MAX_LEVELS + 1))()
+        _check(lib().ifgf_plan_kernel_choice(self._h, int(nrhs), ctypes.cast(v, ctypes.c_void_p)))
+        return {d: self.C2P_VARIANTS[v[d]] for d in range(MAX_LEVELS + 1) if v[d] >= 0}
+
     # -- operator
     @property
     def dtype(self):
@@ -226,15 +246,25 @@ class Plan:
         import torch
         return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
-    def apply(self, a, adjoint: bool = False):
-        """I = IFGF(a) (or the adjoint operator applied to a)."""
+    def apply(self, a, adjoint: bool = False, out=None):
+        """I = IFGF(a) (or the adjoint operator applied to a).  `out`, if
+        given, is a contiguous tensor of a's shape and dtype that receives the
+        result (with use_graph, reusing the same a and out replays the
+        captured graph)."""
         import torch
         a2, squeeze = self._prep(a)
-        out = torch.empty_like(a2)
+        if out is None:
+            out = torch.empty_like(a2)
+        else:
+            if out.dtype != a2.dtype or out.device != a2.device or out.numel() != a2.numel() \
+                    or not out.is_contiguous():
+                raise ValueError("out must be a contiguous tensor like the densities")
+            if out.data_ptr() == a2.data_ptr():
+                raise ValueError("out must not alias the densities")
         f = lib().ifgf_apply_adjoint if adjoint else lib().ifgf_apply
         _check(f(self._h, ctypes.c_void_p(a2.data_ptr()), a2.shape[0], ctypes.c_void_p(out.data_ptr()),
                  self._stream(a2)))
-        return out.reshape(-1) if squeeze else out
+        return out.reshape(-1) if squeeze else out.reshape(a2.shape)
 
     def adjoint(self, v):
         return self.apply(v, adjoint=True)

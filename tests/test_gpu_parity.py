@@ -211,6 +211,86 @@ def test_without_frame_tables(torch, monkeypatch, prec, nrhs):
     assert plan.misses() == 0
 
 
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_box_batched_child_to_parent(torch, monkeypatch, nrhs):
+    """Child-to-parent batched over the boxes of a parent cone (forced on at
+    every level with frame tables, IFGF_BOX_FILL=0) and switched off
+    (IFGF_BOX_FILL=2): both against the oracle, forward and adjoint, on a
+    sphere (boxes with missing octants) and a ragged random cloud."""
+    for pts, k in ((inputs.cube_sphere(20), 5.0 * math.pi), (inputs.random_box_points(5000, 7), 9.0)):
+        a = as_c64(inputs.densities(13, nrhs, pts.shape[0]))
+        ref = oracle.ifgf(pts, a, k)["out"]
+        ref_adj = np.conj(oracle.ifgf(pts, np.conj(a), k)["out"])
+        outs = {}
+        for fill in ("0", "2"):
+            monkeypatch.setenv("IFGF_BOX_FILL", fill)
+            plan = make_plan(pts, k, "mixed", max_nrhs=16)
+            outs[fill] = plan.apply(dev(torch, a, "mixed")).cpu().numpy()
+            adj = plan.adjoint(dev(torch, a, "mixed")).cpu().numpy()
+            assert rel(outs[fill], ref) < MIXED_TOL
+            assert rel(adj, ref_adj) < MIXED_TOL
+            assert plan.misses() == 0
+        assert rel(outs["0"], outs["2"]) < 1e-6
+    monkeypatch.delenv("IFGF_BOX_FILL")
+
+
+def test_autotune_and_kernel_choice(torch):
+    """Autotuning picks, per level, one of the child-to-parent variants; the
+    tuned plan still matches the oracle and the untuned plan."""
+    from paper_2010_02857_amd import ifgf
+    p = inputs.cube_sphere(24)
+    k = 6.0 * math.pi
+    for nrhs in (1, 4, 16):
+        a = as_c64(inputs.densities(14, nrhs, p.shape[0]))
+        plan = make_plan(p, k, "mixed", max_nrhs=16)
+        before = plan.apply(dev(torch, a, "mixed")).cpu().numpy()
+        default = plan.kernel_choice(nrhs)
+        assert default and all(v in ifgf.Plan.C2P_VARIANTS for v in default.values())
+        plan.autotune(nrhs)
+        tuned = plan.kernel_choice(nrhs)
+        assert set(tuned) == set(default)
+        after = plan.apply(dev(torch, a, "mixed")).cpu().numpy()
+        ref = oracle.ifgf(p, a, k)["out"]
+        assert rel(after, ref) < MIXED_TOL
+        assert rel(after, before) < 1e-6
+        assert plan.misses() == 0
+    plan64 = make_plan(p, k, "fp64", max_nrhs=4)
+    plan64.autotune(4)
+    a = inputs.densities(15, 4, p.shape[0])
+    assert rel(plan64.apply(dev(torch, a, "fp64")).cpu().numpy(), oracle.ifgf(p, a, k)["out"]) < FP64_TOL
+
+
+@pytest.mark.parametrize("prec,nrhs", [("mixed", 1), ("mixed", 16), ("fp64", 4)])
+def test_graph_replay(torch, prec, nrhs):
+    """use_graph: the first apply captures a graph, later ones replay it.
+    Every replay, with new densities written into the same buffer and eager
+    work and synchronisations in between, equals the eagerly launched
+    result; forward and adjoint, before and after autotuning."""
+    p = inputs.cube_sphere(16)
+    k = 4.0 * math.pi
+    eager = make_plan(p, k, prec, max_nrhs=16)
+    graph = make_plan(p, k, prec, max_nrhs=16, use_graph=True)
+    x = dev(torch, inputs.densities(16, nrhs, p.shape[0]), prec)
+    out = torch.empty_like(x)
+    for it in range(4):
+        if it == 2:
+            graph.autotune(nrhs)
+            eager.autotune(nrhs)
+        x.copy_(dev(torch, inputs.densities(100 + it, nrhs, p.shape[0]), prec))
+        for adj in (False, True):
+            y = graph.apply(x, adjoint=adj, out=out).clone()
+            torch.cuda.synchronize()
+            z = eager.apply(x, adjoint=adj)
+            scratch = (x.abs() ** 2).sum()          # eager work between replays
+            torch.cuda.synchronize()
+            assert float(scratch) > 0
+            if it < 2:
+                assert torch.equal(y, z)            # same kernels, same order
+            else:                                   # the two plans may tune differently
+                assert rel(y.cpu().numpy(), z.cpu().numpy()) < 1e-6
+    assert graph.misses() == 0
+
+
 def test_argument_errors(torch):
     from paper_2010_02857_amd import ifgf
     p = inputs.cube_sphere(8)
