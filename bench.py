@@ -78,30 +78,58 @@ def _find(d: str, suffix: str) -> str:
     raise FileNotFoundError(f"no *{suffix} under {d}")
 
 
+def _steps(args: str) -> int:
+    a = args.split()
+    return int(a[a.index("--steps") + 1])
+
+
+def _timed(rows: list, steps: int) -> list:
+    """The rows of the timed region: every dispatch from the start of the
+    last `steps` applies on (each apply launches k_leaf_nodes once; the
+    autotuning and warm-up launches come before)."""
+    rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+    leaf = sorted({int(r["Dispatch_Id"]) for r in rows if "k_leaf_nodes" in r["Kernel_Name"]})
+    if len(leaf) < steps:
+        raise RuntimeError("fewer applies in the profile than timed steps")
+    first = leaf[-steps]
+    # the apply starts with its permutation, launched before the leaf values
+    perm = [int(r["Dispatch_Id"]) for r in rows if "k_permute_in" in r["Kernel_Name"]
+            and int(r["Dispatch_Id"]) < first]
+    if perm:
+        first = max(perm)
+    return [r for r in rows if int(r["Dispatch_Id"]) >= first]
+
+
 def summarize(d: str) -> int:
     """Writes profiles/<stage>_<workload>_kernel_trace.md and, from the two
-    counter runs, profiles/traffic_<stage>_<workload>.{json,md}."""
+    counter runs, profiles/traffic_<stage>_<workload>.{json,md}; only the
+    launches of the timed matvecs are counted."""
+    import collections
     import csv
     cmds = profile_commands(d)
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     stage = "child_to_parent"
-    # kernel trace statistics
-    rows = list(csv.DictReader(open(_find(os.path.join(d, "trace"), "kernel_stats.csv"))))
-    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    # kernel trace of the timed region
+    steps = _steps(TRACE_ARGS)
+    rows = _timed(list(csv.DictReader(open(_find(os.path.join(d, "trace"), "kernel_trace.csv")))), steps)
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        a = agg[r["Kernel_Name"]]
+        a[0] += 1
+        a[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    total = sum(v[1] for v in agg.values())
     lines = [f"# Kernel trace, {WORKLOAD_TAG} (mixed, 1 RHS): {TRACE_ARGS}", "",
              "Command (repository root):", "", "    " + cmds[0], "",
+             f"Launches of the {steps} timed matvecs (autotuning and warm-up launches excluded).", "",
              "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
-    st_calls, st_ns = 0, 0.0
-    for r in rows[:16]:
-        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
-                     f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
-    for r in rows:
-        if "k_child_to_parent" in r["Name"]:
-            st_calls += int(r["Calls"])
-            st_ns += float(r["TotalDurationNs"])
+    for name, (c, ns) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{_short(name)}` | {c} | {ns / 1e6:.3f} | {ns / c / 1e6:.4f} | {100.0 * ns / total:.2f} |")
+    st_calls = sum(c for name, (c, ns) in agg.items() if "k_child_to_parent" in name)
+    st_ns = sum(ns for name, (c, ns) in agg.items() if "k_child_to_parent" in name)
     lines += ["", f"Stage `{stage}` (all k_child_to_parent* kernels): {st_calls} launches, "
-              f"average {st_ns / max(st_calls, 1) / 1e6:.4f} ms per launch.", ""]
+              f"average {st_ns / max(st_calls, 1) / 1e6:.4f} ms per launch; "
+              f"{total / steps / 1e6:.3f} ms of kernel time per matvec.", ""]
     with open(os.path.join(out_dir, f"{stage}_{WORKLOAD_TAG}_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(lines))
     # HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
@@ -109,22 +137,24 @@ def summarize(d: str) -> int:
            "commands": cmds[1:]}
     md = [f"# HBM traffic of `{stage}`, {WORKLOAD_TAG} (mixed, 1 RHS)", "", "Commands (repository root):", ""]
     md += ["    " + c for c in cmds[1:]] + [""]
+    psteps = _steps(PMC_ARGS)
     for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        crow = list(csv.DictReader(open(_find(os.path.join(d, sub), "counter_collection.csv"))))
-        copy = [float(r["Counter_Value"]) for r in crow if "neg" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
+        allrows = list(csv.DictReader(open(_find(os.path.join(d, sub), "counter_collection.csv"))))
+        copy = [float(r["Counter_Value"]) for r in allrows if "neg" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
+        crow = _timed(allrows, psteps)
         kib = [float(r["Counter_Value"]) for r in crow
                if "k_child_to_parent" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
         if not copy or not kib:
             raise RuntimeError(f"{ctr}: copy or {stage} dispatches missing")
         scale = COPY_NUMEL * 4 / (sum(copy) / len(copy) * 1024.0)      # bytes per counter KiB
         per_launch = sum(kib) / len(kib) * 1024.0 * scale
-        key = "fetch" if sub == "fetch" else "write"
-        rec[f"{key}_bytes_per_launch"] = per_launch
-        rec[f"{key}_copy_scale"] = scale
-        rec[f"{key}_dispatches"] = len(kib)
+        rec[f"{sub}_bytes_per_launch"] = per_launch
+        rec[f"{sub}_copy_scale"] = scale
+        rec[f"{sub}_dispatches"] = len(kib)
         md.append(f"* {ctr}: copy kernel ({COPY_NUMEL * 4} B read and written) counts "
                   f"{sum(copy) / len(copy):.1f} KiB per dispatch, scale {scale:.4f} B per counted byte; "
-                  f"`{stage}`: {len(kib)} dispatches, {per_launch / 1e6:.2f} MB per launch after scaling.")
+                  f"`{stage}`: {len(kib)} dispatches of the {psteps} timed matvecs, "
+                  f"{per_launch / 1e6:.2f} MB per launch after scaling.")
     rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     md += ["", f"HBM bytes per launch (fetch + write): {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB. "
            f"Kernel source hash {rec['kernel_source_hash']}.", ""]
@@ -217,6 +247,14 @@ def main() -> int:
     t_plan = time.time() - t0
     st = plan.stats()
     log(f"plan: N={n} D={st['D']} cones/level={st['n_cones'][3:]} {t_plan:.1f}s")
+    # kernel selection per level (part of the set-up, like the plan)
+    t0 = time.time()
+    plan.autotune(1)
+    if not args.no_extras:
+        plan.autotune(16)
+    t_tune = time.time() - t0
+    choice = {str(d): v for d, v in plan.kernel_choice(1).items()}
+    log(f"autotune {t_tune:.2f}s: {choice}")
     x = torch.from_numpy(a).to(torch.complex64).cuda()
 
     for _ in range(args.warmup):
@@ -290,6 +328,8 @@ def main() -> int:
         "eps_vs_direct": eps,
         "n2_per_s": n * n * value,
         "t_plan_s": round(t_plan, 2),
+        "t_autotune_s": round(t_tune, 2),
+        "child_to_parent_kernels": choice,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
         "roofline": roofline,
     }
@@ -309,6 +349,13 @@ def main() -> int:
             return s0.elapsed_time(s1) / reps
 
         ms_adj = time_fn(lambda: plan.adjoint(x), 5)
+        # the same matvec replayed from a captured HIP graph
+        gplan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=1, store_levels=0, use_graph=True)
+        gplan.autotune(1)
+        gout = torch.empty_like(x)
+        ms_graph = time_fn(lambda: gplan.apply(x, out=gout), 10)
+        graph_eq = bool(torch.equal(gout, plan.apply(x))) if gplan.kernel_choice(1) == plan.kernel_choice(1) else None
+        del gplan
         g = torch.from_numpy(inputs.densities(402, 1, n)).to(torch.complex64).cuda()
         ms_grad = time_fn(lambda: plan.grad_targets(x, g), 3)
         x16 = torch.from_numpy(inputs.densities(2, 16, n)).to(torch.complex64).cuda()
@@ -318,6 +365,7 @@ def main() -> int:
         st16 = plan.stage_times()
         plan.profile(False)
         result["stage_ms_per_step_16rhs"] = {k: round(v[0] / 4, 4) for k, v in st16.items() if v[1]}
+        plan_choice16 = plan.kernel_choice(16)
         del plan
         torch.cuda.empty_cache()
         plan64 = ifgf.Plan(p, w.kappa, precision="fp64", max_nrhs=1, store_levels=0)
@@ -335,6 +383,9 @@ def main() -> int:
             "mixed_16rhs_matvecs_per_s": round(16 * 1000.0 / ms_b16, 3),
             "speedup_mixed16_vs_fp64_1rhs": round(16 * ms64 / ms_b16, 3),
             "adjoint_matvecs_per_s": round(1000.0 / ms_adj, 3),
+            "graph_replay_1rhs_matvecs_per_s": round(1000.0 / ms_graph, 3),
+            "graph_replay_equals_eager": graph_eq,
+            "child_to_parent_kernels_16rhs": {str(d): v for d, v in plan_choice16.items()},
             "grad_targets_per_s": round(1000.0 / ms_grad, 3),
         })
         log(f"fp64 {ms64:.3f} ms, batched16 {ms_b16:.3f} ms, adjoint {ms_adj:.3f} ms, grad {ms_grad:.3f} ms")

@@ -190,8 +190,11 @@ typedef enum {
     IFGF_C2P_LDS = 2,           /* frames, child cones staged in LDS            */
     IFGF_C2P_MFMA = 3,          /* batched RHS on matrix cores, per slot        */
     IFGF_C2P_MFMA_GEOMETRY = 4, /* the same without frame tables                */
-    IFGF_C2P_BOXES = 5          /* matrix cores, boxes of one parent cone as
+    IFGF_C2P_BOXES = 5,         /* matrix cores, boxes of one parent cone as
                                    matrix columns (FP32, 1 or 4 RHS per pass) */
+    IFGF_C2P_QUADS = 6          /* vector units, 1 RHS: each child cone value
+                                   read from LDS once for up to 4 points (2 in
+                                   FP64) of the same child cone               */
 } ifgf_c2p_variant;
 
 /* Times every applicable child-to-parent variant at every level for nrhs
@@ -208,6 +211,19 @@ ifgf_status ifgf_plan_autotune(ifgf_plan_t plan, int32_t nrhs, void* stream);
  * for nrhs right-hand sides: the tuned one, or the default rule; -1 where
  * there is no such step (d < 4, d > D, host_only plans). */
 ifgf_status ifgf_plan_kernel_choice(ifgf_plan_t plan, int32_t nrhs, int32_t* variant);
+
+/* mask[d] (host array of IFGF_MAX_LEVELS + 1 entries) receives the set of
+ * ifgf_c2p_variant values (bit v) that apply to the step from level d to
+ * d - 1 for nrhs right-hand sides; 0 where there is no such step. */
+ifgf_status ifgf_plan_kernel_candidates(ifgf_plan_t plan, int32_t nrhs, int32_t* mask);
+
+/* Sets the child-to-parent variant per level for nrhs right-hand sides:
+ * variant[d] (host array of IFGF_MAX_LEVELS + 1 entries) >= 0 selects that
+ * ifgf_c2p_variant for the step from level d to d - 1, -1 restores the
+ * default rule.  IFGF_E_INVALID_ARG (and nothing changed) if a variant is
+ * given for a level without such a step or does not apply there (e.g. a
+ * matrix-core variant on an FP64 plan).  Invalidates captured graphs. */
+ifgf_status ifgf_plan_set_kernel_choice(ifgf_plan_t plan, int32_t nrhs, const int32_t* variant);
 
 /* Kernel stages of an apply or gradient call, for ifgf_plan_stage_times. */
 typedef enum {

@@ -369,6 +369,45 @@ ifgf_status ifgf_plan_autotune(ifgf_plan_t plan, int32_t nrhs, void* stream)
     return IFGF_OK;
 }
 
+ifgf_status ifgf_plan_set_kernel_choice(ifgf_plan_t plan, int32_t nrhs, const int32_t* variant)
+{
+    if (!plan || !variant) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    if (nrhs < 1) return fail(IFGF_E_INVALID_ARG, "nrhs out of range");
+    if (plan->p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d)
+        if (variant[d] >= 0 && ifgf::kernel_choice(plan->p, nrhs, d) < 0)
+            return fail(IFGF_E_INVALID_ARG, "level has no child-to-parent step");
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d)
+        if (variant[d] >= ifgf::kC2PVariants || variant[d] < -1)
+            return fail(IFGF_E_INVALID_ARG, "unknown kernel variant");
+    // validate all levels first, then set, so a failed call changes nothing
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) {
+        if (variant[d] < 0) continue;
+        int v[ifgf::kC2PVariants];
+        const int n = ifgf::kernel_candidates(plan->p, nrhs, d, v);
+        bool ok = false;
+        for (int i = 0; i < n; ++i) ok = ok || v[i] == variant[d];
+        if (!ok) return fail(IFGF_E_INVALID_ARG, "kernel variant does not apply at this level");
+    }
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) (void)ifgf::set_kernel_choice(plan->p, nrhs, d, variant[d]);
+    ++plan->p.tune_gen;
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_kernel_candidates(ifgf_plan_t plan, int32_t nrhs, int32_t* mask)
+{
+    if (!plan || !mask) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    if (nrhs < 1) return fail(IFGF_E_INVALID_ARG, "nrhs out of range");
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) {
+        int v[ifgf::kC2PVariants];
+        const int n = ifgf::kernel_candidates(plan->p, nrhs, d, v);
+        int32_t m = 0;
+        for (int i = 0; i < n; ++i) m |= 1 << v[i];
+        mask[d] = m;
+    }
+    return IFGF_OK;
+}
+
 ifgf_status ifgf_plan_kernel_choice(ifgf_plan_t plan, int32_t nrhs, int32_t* variant)
 {
     if (!plan || !variant) return fail(IFGF_E_INVALID_ARG, "NULL argument");

@@ -22,7 +22,7 @@ constexpr int kMaxFrameGroups = 32;  // distinct child cones one frame may touch
 constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone per box tile
 // child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)
 enum { kC2PGeometry = 0, kC2PFrames = 1, kC2PLds = 2, kC2PMfma = 3, kC2PMfmaGeometry = 4, kC2PBoxes = 5,
-       kC2PVariants = 6 };
+       kC2PQuads = 6, kC2PVariants = 7 };
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).
@@ -352,6 +352,12 @@ void note_apply(DevicePlan& p, const void* dens, int nrhs, double kappa);
 hipError_t run_autotune(DevicePlan& p, int nrhs, hipStream_t st);
 // Variant of level d for nrhs right-hand sides (-1: no child-to-parent step).
 int kernel_choice(const DevicePlan& p, int nrhs, int d);
+// Variants applicable at level d for nrhs right-hand sides (count; v gets
+// up to kC2PVariants entries).
+int kernel_candidates(const DevicePlan& p, int nrhs, int d, int* v);
+// Sets (variant >= 0) or resets (-1) the variant of level d; false if the
+// variant does not apply there.
+bool set_kernel_choice(DevicePlan& p, int nrhs, int d, int variant);
 hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
                     hipStream_t stream);
 

@@ -993,6 +993,188 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConst
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
 }
 
+constexpr int kQuadSlots = 12;    // parent slots per block of the quad kernel
+
+// Child cones staged at once by the quad kernel: about 24 KB.
+template <typename T, int P>
+constexpr int quad_gcap()
+{
+    return 24576 / (P * (int)sizeof(cpx<T>)) < 4 ? 4 : 24576 / (P * (int)sizeof(cpx<T>));
+}
+
+// Child-to-parent interpolation, one right-hand side, on the vector units,
+// with each child cone value read from LDS once for up to QR interpolation
+// points.  A block handles S consecutive parent slots, octant by octant: the
+// child cones of the octant's (slot, group) entries are staged in LDS, and
+// every thread takes a "quad" -- up to QR consecutive points of one group in
+// the frame's group order -- and contracts the cone one direction at a time
+// (phi, then theta, then s) for all its points together.  The points' values,
+// times the re-centring ratio, are added to the slot's accumulators in LDS
+// (each (slot, point) belongs to one quad per octant, so no two threads touch
+// the same accumulator in a step).
+template <typename T, int PS, int PA, int S, int QR, int GCAP>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_child_to_parent_quads(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                                  const cpx<T>* __restrict__ Fc,
+                                                                  cpx<T>* __restrict__ Fp)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int G = kMaxFrameGroups;
+    constexpr int MAXE = S * G;
+    static_assert(S <= 64, "slots of a block are scanned in one wavefront");
+    __shared__ cpx<T> cone[GCAP * P];
+    __shared__ cpx<T> acc[S * P];
+    __shared__ int sfr[S];             // frame of (slot, octant), -1
+    __shared__ int soff[S + 1];        // first entry of each slot
+    __shared__ int qoff[S + 1];        // first quad of each slot
+    __shared__ int staged[MAXE];       // child slot of each entry, -1 missing
+
+    const int tid = threadIdx.x;
+    const int slot0 = xcd_block(blockIdx.x, gridDim.x) * S;
+    const T* frt = (const T*)Lc.fr_t;
+    const T* frr = (const T*)Lc.fr_ratio;
+    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    for (int i = tid; i < S * P; i += kBlock) acc[i] = cpx<T>{(T)0, (T)0};
+
+    for (int o = 0; o < 8; ++o) {
+        // frames, entry and quad counts of the slots, exclusive scans
+        if (tid < 64) {
+            int f = -1, ng = 0, nq = 0;
+            if (tid < S && slot0 + tid < Lp.nslots) {
+                f = Lc.pframe[(size_t)(slot0 + tid) * 8 + o];
+                if (f >= 0) {
+                    ng = Lc.fr_ngrp[f];
+                    const uint8_t* go = Lc.fr_goff + (size_t)f * (G + 1);
+                    for (int g = 0; g < ng; ++g) nq += (go[g + 1] - go[g] + QR - 1) / QR;
+                }
+            }
+            int xe = ng, xq = nq;
+#pragma unroll
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const int ye = __shfl_up(xe, dd, 64), yq = __shfl_up(xq, dd, 64);
+                if (tid >= dd) {
+                    xe += ye;
+                    xq += yq;
+                }
+            }
+            if (tid < S) {
+                sfr[tid] = f;
+                soff[tid + 1] = xe;
+                qoff[tid + 1] = xq;
+            }
+            if (tid == 0) soff[0] = qoff[0] = 0;
+        }
+        __syncthreads();
+        const int nent = soff[S], nquad = qoff[S];
+        for (int i = tid; i < nent; i += kBlock) {
+            int sl = 0;
+            while (soff[sl + 1] <= i) ++sl;
+            const int g = i - soff[sl], f = sfr[sl];
+            const int k = Lc.child_of[(size_t)Lp.slot_box[slot0 + sl] * 8 + o];
+            const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
+            const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
+            const int cs = k >= 0 ? lookup(Lc, k, cell, is) : -1;
+            staged[i] = cs;
+        }
+        __syncthreads();
+        for (int base = 0; base < nent; base += GCAP) {
+            const int cnt = nent - base < GCAP ? nent - base : GCAP;
+            for (int i = tid; i < cnt * P; i += kBlock) {
+                const int q = i / P, off = i - q * P;
+                const int cs = staged[base + q];
+                if (cs >= 0) cone[i] = Fc[(size_t)cs * P + off];
+            }
+            __syncthreads();
+            for (int qi = tid; qi < nquad; qi += kBlock) {
+                int sl = 0;
+                while (qoff[sl + 1] <= qi) ++sl;
+                const int f = sfr[sl];
+                const uint8_t* go = Lc.fr_goff + (size_t)f * (G + 1);
+                int rest = qi - qoff[sl], g = 0;
+                for (;;) {
+                    const int nqg = (go[g + 1] - go[g] + QR - 1) / QR;
+                    if (rest < nqg) break;
+                    rest -= nqg;
+                    ++g;
+                }
+                const int ent = soff[sl] + g;
+                if (ent < base || ent >= base + cnt) continue;
+                const int r0 = go[g] + rest * QR;
+                const int nr = go[g + 1] - r0 < QR ? go[g + 1] - r0 : QR;
+                if (staged[ent] < 0) {
+                    atomicAdd(kc.miss, (unsigned long long)nr);
+                    continue;
+                }
+                const uint8_t* ord = Lc.fr_order + (size_t)f * P;
+                int nu[QR];
+                T Ls[QR][PS], Lt[QR][PA], Lq[QR][PA];
+#pragma unroll
+                for (int r = 0; r < QR; ++r) {
+                    nu[r] = ord[r0 + (r < nr ? r : 0)];
+                    const size_t e = (size_t)f * P + nu[r];
+                    lagrange<T, PS>((double)frt[3 * e], kc.cs, Ls[r]);
+                    lagrange<T, PA>((double)frt[3 * e + 1], kc.ca, Lt[r]);
+                    lagrange<T, PA>((double)frt[3 * e + 2], kc.ca, Lq[r]);
+                }
+                const cpx<T>* F = &cone[(ent - base) * P];
+                cpx<T> U[QR][PS];
+#pragma unroll
+                for (int r = 0; r < QR; ++r)
+#pragma unroll
+                    for (int a = 0; a < PS; ++a) U[r][a] = cpx<T>{(T)0, (T)0};
+                // one phi-row of the cone per step, the next one loaded ahead;
+                // the empty asm keeps the compiler from hoisting all loads
+                cpx<T> fv[PA], fn[PA];
+#pragma unroll
+                for (int c = 0; c < PA; ++c) fv[c] = F[c];
+#pragma unroll
+                for (int ab = 0; ab < PS * PA; ++ab) {
+                    const int a = ab / PA, b = ab - a * PA;
+                    if (ab + 1 < PS * PA) {
+#pragma unroll
+                        for (int c = 0; c < PA; ++c) fn[c] = F[(ab + 1) * PA + c];
+                    }
+                    asm volatile("" ::: "memory");
+#pragma unroll
+                    for (int r = 0; r < QR; ++r) {
+                        T sr = (T)0, si = (T)0;
+#pragma unroll
+                        for (int c = 0; c < PA; ++c) {
+                            sr += fv[c].x * Lq[r][c];
+                            si += fv[c].y * Lq[r][c];
+                        }
+                        U[r][a].x += sr * Lt[r][b];
+                        U[r][a].y += si * Lt[r][b];
+                    }
+#pragma unroll
+                    for (int c = 0; c < PA; ++c) fv[c] = fn[c];
+                }
+#pragma unroll
+                for (int r = 0; r < QR; ++r) {
+                    if (r < nr) {
+                        T vr = (T)0, vi = (T)0;
+#pragma unroll
+                        for (int a = 0; a < PS; ++a) {
+                            vr += U[r][a].x * Ls[r][a];
+                            vi += U[r][a].y * Ls[r][a];
+                        }
+                        const size_t e = (size_t)f * P + nu[r];
+                        const T gr = frr[2 * e], gi = conj_sign * frr[2 * e + 1];
+                        cpx<T>& A = acc[sl * P + nu[r]];
+                        A.x += vr * gr - vi * gi;
+                        A.y += vr * gi + vi * gr;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < S * P; i += kBlock) {
+        const int sl = i / P;
+        if (slot0 + sl < Lp.nslots) Fp[(size_t)slot0 * P + i] = acc[i];
+    }
+}
+
 // Orders the LDS accesses of one wavefront (which the LDS executes in issue
 // order) without waiting for outstanding global loads, so prefetches stay in
 // flight across it.
@@ -1526,6 +1708,9 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
     if constexpr (std::is_same<T, float>::value && (RB == 1 || RB == 4) && PA >= 4 && P <= 128) {
         if (groups && L.ntiles > 0) v[n++] = kC2PBoxes;
     }
+    if constexpr (RB == 1 && P <= 255) {
+        if (groups) v[n++] = kC2PQuads;
+    }
     return n;
 }
 
@@ -1601,6 +1786,16 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
         k_child_to_parent_frames<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1],
                                                                                              Fc, Fp);
         return;
+    case kC2PQuads:
+        if constexpr (RB == 1 && P <= 255) {
+            constexpr int QS = kQuadSlots;
+            constexpr int QR = std::is_same<T, float>::value ? 4 : 2;
+            constexpr int QG = quad_gcap<T, P>();
+            k_child_to_parent_quads<T, PS, PA, QS, QR, QG>
+                <<<(unsigned)((nps + QS - 1) / QS), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            return;
+        }
+        break;
     default:
         break;
     }
@@ -1799,6 +1994,14 @@ hipError_t autotune_rb(DevicePlan& p, int rb, hipStream_t st)
 }
 
 template <typename T, int PS, int PA>
+int candidates_t(const DevicePlan& p, int rb, int d, int* v)
+{
+    if (rb == 1) return c2p_candidates<T, PS, PA, 1>(p, d, v);
+    if (rb == 4) return c2p_candidates<T, PS, PA, 4>(p, d, v);
+    return c2p_candidates<T, PS, PA, 16>(p, d, v);
+}
+
+template <typename T, int PS, int PA>
 int choice_t(const DevicePlan& p, int rb, int d)
 {
     if (rb == 1) return c2p_variant<T, PS, PA, 1>(p, d);
@@ -1832,6 +2035,35 @@ hipError_t run_autotune(DevicePlan& p, int nrhs, hipStream_t st)
     if (ps == 4 && pa == 6) return mixed ? autotune_rb<float, 4, 6>(p, rb, st) : autotune_rb<double, 4, 6>(p, rb, st);
     if (ps == 2 && pa == 3) return mixed ? autotune_rb<float, 2, 3>(p, rb, st) : autotune_rb<double, 2, 3>(p, rb, st);
     return hipErrorInvalidValue;
+}
+
+int kernel_candidates(const DevicePlan& p, int nrhs, int d, int* v)
+{
+    if (d < 4 || d > p.hp.D || p.hp.L[d - 1].nslots == 0 || p.host_only) return 0;
+    const int rb = rb_for(std::min(kMaxRhsPass, nrhs));
+    const int ps = p.hp.ps, pa = p.hp.pang;
+    const bool mixed = p.precision == IFGF_MIXED;
+    if (ps == 3 && pa == 5) return mixed ? candidates_t<float, 3, 5>(p, rb, d, v) : candidates_t<double, 3, 5>(p, rb, d, v);
+    if (ps == 4 && pa == 6) return mixed ? candidates_t<float, 4, 6>(p, rb, d, v) : candidates_t<double, 4, 6>(p, rb, d, v);
+    if (ps == 2 && pa == 3) return mixed ? candidates_t<float, 2, 3>(p, rb, d, v) : candidates_t<double, 2, 3>(p, rb, d, v);
+    return 0;
+}
+
+bool set_kernel_choice(DevicePlan& p, int nrhs, int d, int variant)
+{
+    const int rbi = rb_index(rb_for(std::min(kMaxRhsPass, nrhs)));
+    if (variant < 0) {
+        if (d >= 0 && d <= IFGF_MAX_LEVELS) p.c2p_choice[rbi][d] = -1;
+        return true;
+    }
+    int v[kC2PVariants];
+    const int n = kernel_candidates(p, nrhs, d, v);
+    for (int i = 0; i < n; ++i)
+        if (v[i] == variant) {
+            p.c2p_choice[rbi][d] = variant;
+            return true;
+        }
+    return false;
 }
 
 int kernel_choice(const DevicePlan& p, int nrhs, int d)

@@ -97,13 +97,16 @@ def lib() -> ctypes.CDLL:
         L.ifgf_plan_stage_times.argtypes = [P, P, P]
         L.ifgf_plan_autotune.argtypes = [P, I32, P]
         L.ifgf_plan_kernel_choice.argtypes = [P, I32, P]
+        L.ifgf_plan_set_kernel_choice.argtypes = [P, I32, P]
+        L.ifgf_plan_kernel_candidates.argtypes = [P, I32, P]
         L.ifgf_status_string.argtypes = [ctypes.c_int]
         L.ifgf_status_string.restype = ctypes.c_char_p
         L.ifgf_last_error.argtypes = []
         L.ifgf_last_error.restype = ctypes.c_char_p
         for f in (L.ifgf_plan_create, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
                   L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy, L.ifgf_plan_profile,
-                  L.ifgf_plan_stage_times, L.ifgf_plan_autotune, L.ifgf_plan_kernel_choice):
+                  L.ifgf_plan_stage_times, L.ifgf_plan_autotune, L.ifgf_plan_kernel_choice,
+                  L.ifgf_plan_set_kernel_choice, L.ifgf_plan_kernel_candidates):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -208,7 +211,7 @@ class Plan:
                                            cnt.ctypes.data_as(ctypes.c_void_p)))
         return {s: (float(ms[i]), int(cnt[i])) for i, s in enumerate(self.STAGES)}
 
-    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes")
+    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes", "quads")
 
     def autotune(self, nrhs: int = 1):
         """Time the child-to-parent kernel variants of every level for nrhs
@@ -223,6 +226,25 @@ class Plan:
         v = (ctypes.c_int32 * (MAX_LEVELS + 1))()
         _check(lib().ifgf_plan_kernel_choice(self._h, int(nrhs), ctypes.cast(v, ctypes.c_void_p)))
         return {d: self.C2P_VARIANTS[v[d]] for d in range(MAX_LEVELS + 1) if v[d] >= 0}
+
+    def set_kernel_choice(self, nrhs: int, choice: dict):
+        """Force {level d: variant name or None (default rule)} for nrhs
+        right-hand sides; levels not named keep their current setting."""
+        cur = self.kernel_choice(nrhs)
+        v = (ctypes.c_int32 * (MAX_LEVELS + 1))(*([-1] * (MAX_LEVELS + 1)))
+        tuned = {d: self.C2P_VARIANTS.index(x) for d, x in cur.items()}
+        for d, x in choice.items():
+            tuned[d] = -1 if x is None else self.C2P_VARIANTS.index(x)
+        for d, x in tuned.items():
+            v[d] = x
+        _check(lib().ifgf_plan_set_kernel_choice(self._h, int(nrhs), ctypes.cast(v, ctypes.c_void_p)))
+
+    def kernel_candidates(self, nrhs: int = 1) -> dict:
+        """{level d: [names of the variants that apply there]}."""
+        m = (ctypes.c_int32 * (MAX_LEVELS + 1))()
+        _check(lib().ifgf_plan_kernel_candidates(self._h, int(nrhs), ctypes.cast(m, ctypes.c_void_p)))
+        return {d: [x for i, x in enumerate(self.C2P_VARIANTS) if (m[d] >> i) & 1]
+                for d in range(MAX_LEVELS + 1) if m[d]}
 
     # -- operator
     @property

@@ -260,6 +260,41 @@ def test_autotune_and_kernel_choice(torch):
     assert rel(plan64.apply(dev(torch, a, "fp64")).cpu().numpy(), oracle.ifgf(p, a, k)["out"]) < FP64_TOL
 
 
+@pytest.mark.parametrize("prec,nrhs", [("mixed", 1), ("mixed", 4), ("mixed", 16), ("fp64", 1), ("fp64", 4)])
+def test_every_child_to_parent_variant(torch, prec, nrhs):
+    """Each child-to-parent kernel variant, forced at every level where it
+    applies, matches the oracle (forward and adjoint)."""
+    from paper_2010_02857_amd import ifgf
+    p = inputs.cube_sphere(20)
+    k = 5.0 * math.pi
+    a = inputs.densities(17, nrhs, p.shape[0])
+    ac = a if prec == "fp64" else as_c64(a)
+    ref = oracle.ifgf(p, ac, k)["out"]
+    ref_adj = np.conj(oracle.ifgf(p, np.conj(ac), k)["out"])
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    plan = make_plan(p, k, prec, max_nrhs=16)
+    cand = plan.kernel_candidates(nrhs)
+    assert cand
+    tested = set()
+    for name in ifgf.Plan.C2P_VARIANTS:
+        levels = {d: name for d, names in cand.items() if name in names}
+        if not levels:
+            continue
+        print(f"variant {name} at levels {sorted(levels)}", flush=True)
+        plan.set_kernel_choice(nrhs, {d: None for d in cand})
+        plan.set_kernel_choice(nrhs, levels)
+        assert all(plan.kernel_choice(nrhs)[d] == name for d in levels)
+        out = plan.apply(dev(torch, a, prec)).cpu().numpy()
+        adj = plan.adjoint(dev(torch, a, prec)).cpu().numpy()
+        assert rel(out, ref) < tol, name
+        assert rel(adj, ref_adj) < tol, name
+        tested.add(name)
+    assert plan.misses() == 0
+    assert {"geometry", "frames"} <= tested
+    with pytest.raises(ifgf.IFGFError):
+        plan.set_kernel_choice(nrhs, {2: "geometry"})
+
+
 @pytest.mark.parametrize("prec,nrhs", [("mixed", 1), ("mixed", 16), ("fp64", 4)])
 def test_graph_replay(torch, prec, nrhs):
     """use_graph: the first apply captures a graph, later ones replay it.
