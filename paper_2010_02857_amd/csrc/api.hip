@@ -181,6 +181,8 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
                 L.ntiles = (int)H.ntiles;
                 if ((e = upload(p, H.bt_slot, &L.bt_slot)) != hipSuccess) return e;
                 if ((e = upload(p, H.bt_frame, &L.bt_frame)) != hipSuccess) return e;
+                if ((int64_t)H.slot_order.size() == hp.L[d - 1].nslots && !H.slot_order.empty())
+                    if ((e = upload(p, H.slot_order, &L.slot_order)) != hipSuccess) return e;
             }
             // the host copies are no longer needed
             std::vector<double>().swap(H.fr_t);

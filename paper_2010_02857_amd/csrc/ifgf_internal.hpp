@@ -22,7 +22,7 @@ constexpr int kMaxFrameGroups = 32;  // distinct child cones one frame may touch
 constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone per box tile
 // child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)
 enum { kC2PGeometry = 0, kC2PFrames = 1, kC2PLds = 2, kC2PMfma = 3, kC2PMfmaGeometry = 4, kC2PBoxes = 5,
-       kC2PQuads = 6, kC2PVariants = 7 };
+       kC2PQuads = 6, kC2PLdsTiled = 7, kC2PVariants = 8 };
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).
@@ -161,6 +161,7 @@ struct HostLevel {
     int64_t ntiles = 0;
     std::vector<int32_t> bt_slot;             // [ntiles][kBoxTile] parent slot, -1 pad
     std::vector<int32_t> bt_frame;            // [ntiles][8] frame of octant o, -1 none
+    std::vector<int32_t> slot_order;          // [nslots_{d-1}] parent slots in tile order
     // Cousin-target pairs (levels d >= 3): for every target box T, cousin
     // c of T and target t of T, entry pair_base[T] + c * n_T + t holds the
     // slot of the cone of cousin c that contains t, t's local coordinates in
@@ -228,6 +229,7 @@ struct LevelDev {
     int ntiles;
     const int32_t* bt_slot;
     const int32_t* bt_frame;
+    const int32_t* slot_order;               // parent slots in tile order, or null
     // cousin-target pairs (float for mixed, double for FP64)
     int use_pairs;
     long long npairs_cou;

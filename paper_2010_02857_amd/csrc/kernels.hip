@@ -57,6 +57,17 @@ __device__ inline int xcd_block(int b, int nb)
     return x * per + (x < rem ? x : rem) + l;
 }
 
+// Parent slot visited at position i of a child-to-parent launch: with
+// ORDERED the box tiles' order (blocks of boxes, one parent cone after the
+// other), so that neighbouring work shares frames in cache; else slot order
+// (box-major), so that it shares child cones.
+template <bool ORDERED>
+__device__ inline int slot_at(const LevelDev& Lc, int i)
+{
+    if constexpr (ORDERED) return Lc.slot_order[i];
+    return i;
+}
+
 // Lagrange basis of the N first-kind Chebyshev nodes at t:
 // L_k(t) = prod_{j != k} (t - t_j) / (t_k - t_j).  Interpolating the node
 // values with it gives the same polynomial as the Chebyshev expansion whose
@@ -520,8 +531,9 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_frames(KernelConsts 
 // slots in parallel, copies each cone once from global memory into LDS, and
 // then every (slot, interpolation point) thread interpolates from LDS for all
 // eight octants.  A block whose cones exceed the LDS capacity GCAP stages
-// them in several rounds.
-template <typename T, int PS, int PA, int RB, int S, int GCAP>
+// them in several rounds.  With ORD the slots are visited in the box tiles'
+// order (see slot_at), else in slot order (box-major).
+template <typename T, int PS, int PA, int RB, int S, int GCAP, bool ORD>
 __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                    const cpx<T>* __restrict__ Fc,
                                                                    cpx<T>* __restrict__ Fp)
@@ -540,8 +552,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
     const int slot0 = xcd_block(blockIdx.x, gridDim.x) * S;
     const int s_me = tid / P;
     const int nu = tid - s_me * P;
-    const int sp = slot0 + s_me;
-    const bool active = s_me < S && sp < Lp.nslots;
+    const bool active = s_me < S && slot0 + s_me < Lp.nslots;
+    const int sp = active ? slot_at<ORD>(Lc, slot0 + s_me) : 0;
     const T* frt = (const T*)Lc.fr_t;
     const T* frr = (const T*)Lc.fr_ratio;
     const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
@@ -550,9 +562,9 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
     if (tid < 64) {
         int f = -1, ng = 0;
         if (tid < S * 8) {
-            const int q = slot0 + tid / 8;
-            if (q < Lp.nslots) {
-                f = Lc.pframe[(size_t)q * 8 + (tid & 7)];
+            const int qi = slot0 + tid / 8;
+            if (qi < Lp.nslots) {
+                f = Lc.pframe[(size_t)slot_at<ORD>(Lc, qi) * 8 + (tid & 7)];
                 if (f >= 0) ng = Lc.fr_ngrp[f];
             }
         }
@@ -576,7 +588,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
         while (soff[so + 1] <= i) ++so;
         const int f = sof[so];
         const int g = i - soff[so];
-        const int q = slot0 + so / 8, o = so & 7;
+        const int q = slot_at<ORD>(Lc, slot0 + so / 8), o = so & 7;
         const int k = Lc.child_of[(size_t)Lp.slot_box[q] * 8 + o];
         const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
         const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
@@ -597,11 +609,27 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
         }
         __syncthreads();
         if (active) {
+            // the frame data of octant o + 1 is loaded while octant o is computed
+            auto frame_of = [&](int o, int& grp, T& ta, T& tb, T& tc, T& ga, T& gb) {
+                const int f = sof[s_me * 8 + o];
+                const size_t e = (size_t)(f >= 0 ? f : 0) * P + nu;
+                grp = Lc.fr_grp[e];
+                ta = frt[3 * e];
+                tb = frt[3 * e + 1];
+                tc = frt[3 * e + 2];
+                ga = frr[2 * e];
+                gb = frr[2 * e + 1];
+            };
+            int grp_n;
+            T ta_n, tb_n, tc_n, ga_n, gb_n;
+            frame_of(0, grp_n, ta_n, tb_n, tc_n, ga_n, gb_n);
             for (int o = 0; o < 8; ++o) {
+                const int grp = grp_n;
+                const T t0 = ta_n, t1 = tb_n, t2 = tc_n, g0 = ga_n, g1 = gb_n;
+                if (o + 1 < 8) frame_of(o + 1, grp_n, ta_n, tb_n, tc_n, ga_n, gb_n);
                 const int f = sof[s_me * 8 + o];
                 if (f < 0) continue;
-                const size_t e = (size_t)f * P + nu;
-                const int ent = soff[s_me * 8 + o] + Lc.fr_grp[e];
+                const int ent = soff[s_me * 8 + o] + grp;
                 const int pos = ent - base;
                 if (pos < 0 || pos >= cnt) continue;
                 if (staged[ent] < 0) {
@@ -609,12 +637,12 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
                     continue;
                 }
                 T Ls[PS], Lt[PA], Lpp[PA];
-                lagrange<T, PS>((double)frt[3 * e], kc.cs, Ls);
-                lagrange<T, PA>((double)frt[3 * e + 1], kc.ca, Lt);
-                lagrange<T, PA>((double)frt[3 * e + 2], kc.ca, Lpp);
+                lagrange<T, PS>((double)t0, kc.cs, Ls);
+                lagrange<T, PA>((double)t1, kc.ca, Lt);
+                lagrange<T, PA>((double)t2, kc.ca, Lpp);
                 cpx<T> val[RB];
                 interp<T, PS, PA, RB>(&cone[pos * P * RB], Ls, Lt, Lpp, val);
-                const T gr = frr[2 * e], gim = conj_sign * frr[2 * e + 1];
+                const T gr = g0, gim = conj_sign * g1;
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     acc[r].x += val[r].x * gr - val[r].y * gim;
@@ -1701,6 +1729,7 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
     if (L.use_frames) v[n++] = kC2PFrames;
     if constexpr (GCAP >= S) {
         if (groups) v[n++] = kC2PLds;
+        if (groups && L.slot_order) v[n++] = kC2PLdsTiled;
     }
     if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
         v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
@@ -1777,7 +1806,14 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
         break;
     case kC2PLds:
         if constexpr (GCAP >= S) {
-            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP>
+            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, false>
+                <<<(unsigned)((nps + S - 1) / S), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            return;
+        }
+        break;
+    case kC2PLdsTiled:
+        if constexpr (GCAP >= S) {
+            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, true>
                 <<<(unsigned)((nps + S - 1) / S), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
             return;
         }

@@ -332,6 +332,10 @@ void build_frames(HostPlan& hp, int d)
             i = e;
         }
     }, 1);
+    L.slot_order.clear();
+    L.slot_order.reserve((size_t)Lp.nslots);
+    for (int32_t sl : L.bt_slot)
+        if (sl >= 0) L.slot_order.push_back(sl);
 }
 
 }  // namespace

@@ -211,7 +211,7 @@ class Plan:
                                            cnt.ctypes.data_as(ctypes.c_void_p)))
         return {s: (float(ms[i]), int(cnt[i])) for i, s in enumerate(self.STAGES)}
 
-    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes", "quads")
+    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes", "quads", "lds_tiled")
 
     def autotune(self, nrhs: int = 1):
         """Time the child-to-parent kernel variants of every level for nrhs
