@@ -533,15 +533,15 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_frames(KernelConsts 
 // eight octants.  A block whose cones exceed the LDS capacity GCAP stages
 // them in several rounds.  With ORD the slots are visited in the box tiles'
 // order (see slot_at), else in slot order (box-major).
-template <typename T, int PS, int PA, int RB, int S, int GCAP, bool ORD>
-__global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts kc, LevelDev Lc, LevelDev Lp,
-                                                                   const cpx<T>* __restrict__ Fc,
-                                                                   cpx<T>* __restrict__ Fp)
+template <typename T, int PS, int PA, int RB, int S, int GCAP, bool ORD, int NT>
+__global__ void __launch_bounds__(NT) k_child_to_parent_lds(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                            const cpx<T>* __restrict__ Fc,
+                                                            cpx<T>* __restrict__ Fp)
 {
     constexpr int P = PS * PA * PA;
     constexpr int G = kMaxFrameGroups;
     constexpr int MAXE = S * 8 * G;
-    static_assert(S * P <= kBlock, "block too small");
+    static_assert(S * P <= NT, "block too small");
     static_assert(S * 8 <= 64, "the (slot, octant) table must fit one wavefront");
     __shared__ cpx<T> cone[GCAP * P * RB];
     __shared__ int sof[S * 8];        // frame of (slot, octant), -1 none
@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
     __syncthreads();
     const int nent = soff[S * 8];
     // child slot of every entry
-    for (int i = tid; i < nent; i += kBlock) {
+    for (int i = tid; i < nent; i += NT) {
         int so = 0;
         while (soff[so + 1] <= i) ++so;
         const int f = sof[so];
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_child_to_parent_lds(KernelConsts 
     for (int base = 0; base < nent; base += GCAP) {
         const int cnt = nent - base < GCAP ? nent - base : GCAP;
         const int total = cnt * P * RB;
-        for (int i = tid; i < total; i += kBlock) {
+        for (int i = tid; i < total; i += NT) {
             const int q = i / (P * RB), off = i - q * (P * RB);
             const int gs = staged[base + q];
             if (gs >= 0) cone[i] = Fc[(size_t)gs * P * RB + off];
@@ -666,6 +666,21 @@ constexpr int lds_gcap()
     return (24576 / (P * RB * (int)sizeof(cpx<T>))) < S * kMaxFrameGroups
                ? (24576 / (P * RB * (int)sizeof(cpx<T>)))
                : S * kMaxFrameGroups;
+}
+
+// Parent slots and threads per block of the LDS kernel: as many slots as fit
+// 256 threads, at most 8.  (Blocks of 5 x 75 points in 384 threads, with
+// 48 KB of staged cones, idle fewer lanes but ran 10% slower.)
+template <int P, int RB>
+constexpr int lds_slots()
+{
+    return (kBlock / P) < 8 ? (kBlock / P) : 8;
+}
+
+template <int P, int RB>
+constexpr int lds_threads()
+{
+    return kBlock;
 }
 
 // Batched child-to-parent interpolation on the matrix cores (16 complex
@@ -1503,6 +1518,98 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
     }
 }
 
+// Interpolation at cousin targets for batched right-hand sides on the matrix
+// cores (FP32), through the tabulated pairs.  One wavefront takes a target
+// box and up to 16 of its targets as the rows of 16 x 16 x 4 MFMA tiles;
+// for every cousin box, the rows whose targets fall into the same cone form
+// one tile group: K = the cone's nodes (ordered as in mfma_tile), columns the
+// real and imaginary parts of the RB right-hand sides, rows of other cones
+// weighted zero.  Each row is multiplied by its centred factor G(x, x_k) and
+// accumulated in registers, so a target's output is updated once, by one
+// lane, after all cousins.
+template <int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_eval_mfma(KernelConsts kc, LevelDev L,
+                                                             const cpx<float>* __restrict__ F,
+                                                             cpx<float>* __restrict__ out)
+{
+    constexpr int NC = 2 * RB;
+    constexpr int NT = (NC + 15) / 16;
+    constexpr int W = kBlock / 64;
+    constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
+    constexpr int P = PS * PA * PA;
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int tb = xcd_block(blockIdx.x, gridDim.x) * W + wv;
+    if (tb >= L.nbox) return;                  // whole wavefront leaves
+    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int b0 = L.box_start[tb];
+    const int nT = L.box_start[tb + 1] - b0;
+    const long long base = L.pair_base[tb];
+    const int nc = L.cou_start[tb + 1] - L.cou_start[tb];
+    const long long np = L.npairs_cou;
+    const float* pt = (const float*)L.pr_t;
+    const float* pg = (const float*)L.pr_g;
+    const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
+    const float* Ff = (const float*)F;
+    float* outf = (float*)out;
+
+    for (int r0 = 0; r0 < nT; r0 += 16) {
+        const int tl = r0 + row;
+        const bool valid = tl < nT;
+        mf4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mf4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < nc; ++c) {
+            const long long e = base + (long long)c * nT + (valid ? tl : 0);
+            const int slot = valid ? L.pr_slot[e] : -1;
+            if (valid && slot < 0 && q == 0) atomicAdd(kc.miss, 1ull);
+            float Ls[PS], Lt[PA], Lpv[PA];
+            lagrange<float, PS>((double)pt[e], kc.cs, Ls);
+            lagrange<float, PA>((double)pt[np + e], kc.ca, Lt);
+            lagrange<float, PA>((double)pt[2 * np + e], kc.ca, Lpv);
+            const float gr = pg[e], gi = conj_sign * pg[np + e];
+            // rows grouped by cone (lanes 0..15 hold one row each)
+            unsigned long long todo = __ballot(lane < 16 && slot >= 0);
+            while (todo) {
+                const int leader = __ffsll((long long)todo) - 1;
+                const int key = __shfl(slot, leader, 64);
+                const bool in = slot == key;
+                todo &= ~__ballot(lane < 16 && in);
+                float Lsm[PS];
+#pragma unroll
+                for (int a = 0; a < PS; ++a) Lsm[a] = in ? Ls[a] : 0.f;
+                float b[NT][NK];
+                mfma_load_b<PS, PA, NC, NT>(Ff + (size_t)key * P * NC, q, col, b);
+                mf4 cm[NT];
+                mfma_tile<PS, PA, NT>(b, Lsm, Lt, Lpv, q, cm);
+                // rows 4q + i: times the row's centred factor (columns 2m, 2m + 1: re, im)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float rgr = __shfl(gr, 4 * q + i, 64), rgi = __shfl(gi, 4 * q + i, 64);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const float v = cm[t][i];
+                        const float pv = __shfl_xor(v, 1, 64);
+                        acc[t][i] += (col & 1) == 0 ? v * rgr - pv * rgi : pv * rgi + v * rgr;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + 4 * q + i;
+            if (r < nT) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int cg = 16 * t + col;
+                    if (cg < NC) outf[((size_t)(b0 + r) * RB) * 2 + cg] += acc[t][i];
+                }
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- gradients
 
 // d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
@@ -1720,7 +1827,7 @@ template <typename T, int PS, int PA, int RB>
 int c2p_candidates(const DevicePlan& p, int d, int* v)
 {
     constexpr int P = PS * PA * PA;
-    constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
+    constexpr int S = lds_slots<P, RB>();
     constexpr int GCAP = lds_gcap<T, P, RB, S>();
     const LevelDev& L = p.L[d];
     const bool groups = L.use_frames && L.frame_groups_ok;
@@ -1779,8 +1886,9 @@ template <typename T, int PS, int PA, int RB>
 void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipStream_t st)
 {
     constexpr int P = PS * PA * PA;
-    constexpr int S = (kBlock / P) < 8 ? (kBlock / P) : 8;
+    constexpr int S = lds_slots<P, RB>();
     constexpr int GCAP = lds_gcap<T, P, RB, S>();
+    constexpr int NT = lds_threads<P, RB>();
     using C = cpx<T>;
     const int64_t nps = p.hp.L[d - 1].nslots;
     const C* Fc = (const C*)p.F[d];
@@ -1806,15 +1914,15 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
         break;
     case kC2PLds:
         if constexpr (GCAP >= S) {
-            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, false>
-                <<<(unsigned)((nps + S - 1) / S), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, false, NT>
+                <<<(unsigned)((nps + S - 1) / S), NT, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
             return;
         }
         break;
     case kC2PLdsTiled:
         if constexpr (GCAP >= S) {
-            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, true>
-                <<<(unsigned)((nps + S - 1) / S), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, true, NT>
+                <<<(unsigned)((nps + S - 1) / S), NT, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
             return;
         }
         break;
@@ -1836,6 +1944,17 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
         break;
     }
     k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+}
+
+// The matrix-core cousin evaluation for batched right-hand sides runs only
+// with IFGF_COUSIN_MFMA=1: one target box per wavefront leaves it bound by
+// the latency of its sequential cousin loop (3.7x slower than the vector
+// kernel, which serves about ten boxes per wavefront, on the sphere
+// N = 393216 with 16 right-hand sides).
+inline bool cousin_mfma_enabled()
+{
+    const char* v = std::getenv("IFGF_COUSIN_MFMA");
+    return v && *v && std::atoi(v) != 0;
 }
 
 template <typename T, int PS, int PA, int RB>
@@ -1863,7 +1982,16 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
         else
             {
                 StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st);
-                if (p.L[d].use_pairs)
+                bool done = false;
+                if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4) {
+                    if (p.L[d].use_pairs && cousin_mfma_enabled()) {
+                        k_cousin_eval_mfma<PS, PA, RB><<<(unsigned)((hp.L[d].nbox + kBlock / 64 - 1) / (kBlock / 64)),
+                                                         kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.out_m);
+                        done = true;
+                    }
+                }
+                if (done) {
+                } else if (p.L[d].use_pairs)
                     k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
                                                                                        (C*)p.out_m);
                 else

@@ -326,6 +326,31 @@ def test_graph_replay(torch, prec, nrhs):
     assert graph.misses() == 0
 
 
+@pytest.mark.parametrize("nrhs", [4, 16])
+def test_cousin_eval_mfma_on_off(torch, monkeypatch, nrhs):
+    """Cousin-target interpolation for batched right-hand sides on the
+    matrix cores (IFGF_COUSIN_MFMA=1) and on the vector units (default):
+    both match the oracle, forward and adjoint, on a sphere and on a ragged
+    cloud with more than 16 points in some boxes."""
+    pts_cases = ((inputs.cube_sphere(20), 5.0 * math.pi),
+                 (np.concatenate([inputs.random_box_points(3000, 8), 0.05 * inputs.random_box_points(300, 9)]), 7.0))
+    for pts, k in pts_cases:
+        a = as_c64(inputs.densities(18, nrhs, pts.shape[0]))
+        ref = oracle.ifgf(pts, a, k)["out"]
+        ref_adj = np.conj(oracle.ifgf(pts, np.conj(a), k)["out"])
+        outs = {}
+        for flag in ("1", "0"):
+            monkeypatch.setenv("IFGF_COUSIN_MFMA", flag)
+            plan = make_plan(pts, k, "mixed", max_nrhs=16)
+            outs[flag] = plan.apply(dev(torch, a, "mixed")).cpu().numpy()
+            adj = plan.adjoint(dev(torch, a, "mixed")).cpu().numpy()
+            assert rel(outs[flag], ref) < MIXED_TOL
+            assert rel(adj, ref_adj) < MIXED_TOL
+            assert plan.misses() == 0
+        assert rel(outs["1"], outs["0"]) < 1e-6
+    monkeypatch.delenv("IFGF_COUSIN_MFMA")
+
+
 def test_argument_errors(torch):
     from paper_2010_02857_amd import ifgf
     p = inputs.cube_sphere(8)
