@@ -1,4 +1,5 @@
 // C ABI of the IFGF library (declared in include/ifgf.h).
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -133,6 +134,26 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
             std::vector<long long> pb(H.pair_base.begin(), H.pair_base.end());
             if ((e = upload(p, pb, &L.pair_base)) != hipSuccess) return e;
             if ((e = upload(p, H.pr_slot, &L.pr_slot)) != hipSuccess) return e;
+            L.npairs_ord = (long long)H.pr_order.size();
+            if (L.npairs_ord > 0) {
+                if ((e = upload(p, H.pr_order, &L.pr_order)) != hipSuccess) return e;
+                if ((e = upload(p, H.pro_slot, &L.pro_slot)) != hipSuccess) return e;
+                if (p.precision == IFGF_MIXED) {
+                    std::vector<float> t(H.pro_t.begin(), H.pro_t.end()), g(H.pro_g.begin(), H.pro_g.end());
+                    const float* dt = nullptr;
+                    if ((e = upload(p, t, &dt)) != hipSuccess) return e;
+                    L.pro_t = dt;
+                    if ((e = upload(p, g, &dt)) != hipSuccess) return e;
+                    L.pro_g = dt;
+                } else {
+                    const double* dt = nullptr;
+                    if ((e = upload(p, H.pro_t, &dt)) != hipSuccess) return e;
+                    L.pro_t = dt;
+                    if ((e = upload(p, H.pro_g, &dt)) != hipSuccess) return e;
+                    L.pro_g = dt;
+                }
+            }
+            p.max_pairs = std::max<int64_t>(p.max_pairs, (int64_t)H.pr_slot.size());
             if (p.precision == IFGF_MIXED) {
                 std::vector<float> t(H.pr_t.begin(), H.pr_t.end()), g(H.pr_g.begin(), H.pr_g.end());
                 const float* dt = nullptr;
@@ -150,6 +171,10 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
             std::vector<double>().swap(H.pr_t);
             std::vector<double>().swap(H.pr_g);
             std::vector<int32_t>().swap(H.pr_slot);
+            std::vector<int32_t>().swap(H.pr_order);
+            std::vector<int32_t>().swap(H.pro_slot);
+            std::vector<double>().swap(H.pro_t);
+            std::vector<double>().swap(H.pro_g);
         }
         L.use_frames = H.use_frames ? 1 : 0;
         if (d >= 4)
@@ -248,7 +273,8 @@ ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t 
     try {
         // a tabulated cousin-target pair: slot, 3 local coordinates, complex G
         double pair_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 24.0 : 44.0);
-        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes,
+        double ord_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 28.0 : 48.0);
+        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes, ord_bytes,
                                     p.hp, code);
     } catch (const std::bad_alloc&) {
         delete pl;

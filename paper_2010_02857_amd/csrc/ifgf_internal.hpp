@@ -171,6 +171,10 @@ struct HostLevel {
     std::vector<int32_t> pr_slot;             // [npairs]
     std::vector<double> pr_t;                 // [3][npairs] (structure of arrays)
     std::vector<double> pr_g;                 // [2][npairs]
+    std::vector<int32_t> pr_order;            // pairs with a cone, ordered by slot
+    std::vector<int32_t> pro_slot;            // their slots, in that order
+    std::vector<double> pro_t;                // [3][npairs with a cone], in that order
+    std::vector<double> pro_g;                // [2][npairs with a cone], in that order
 };
 
 struct HostPlan {
@@ -186,10 +190,11 @@ struct HostPlan {
 
 // Builds the hierarchy; returns an empty string on success, else a message.
 // `code` receives the ifgf_status on failure.
-// tab_elem_bytes: device bytes of one tabulated cousin-target pair (0: none).
+// tab_elem_bytes: device bytes of one tabulated cousin-target pair (0: none);
+// ord_elem_bytes: device bytes of its cone-ordered copy (0: none).
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
-                            int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, HostPlan& hp,
-                            ifgf_status& code);
+                            int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
+                            HostPlan& hp, ifgf_status& code);
 
 // ---------------------------------------------------------- device mirror
 
@@ -237,6 +242,11 @@ struct LevelDev {
     const int32_t* pr_slot;
     const void* pr_t;
     const void* pr_g;
+    long long npairs_ord;                     // entries of pr_order (0: no ordered copy)
+    const int32_t* pr_order;
+    const int32_t* pro_slot;
+    const void* pro_t;
+    const void* pro_g;
 };
 
 struct KernelConsts {
@@ -262,6 +272,7 @@ struct DevicePlan {
     std::vector<LevelDev> L;
     unsigned long long* miss = nullptr;
     void* zero_cone = nullptr;  // [P][kMaxRhsPass] complex zeros (FP32 view)
+    int64_t max_pairs = 0;      // largest cousin-pair table of a level (0: none)
     std::vector<void*> allocs;
     size_t tree_bytes = 0;
     // workspaces, sized for `ws_rb` right-hand sides per pass
@@ -271,6 +282,7 @@ struct DevicePlan {
     void* out_m = nullptr;      // [n][rb] complex, Morton order
     void* gout_m = nullptr;     // [n][rb] complex, Morton order (gradient input)
     double* grad_m = nullptr;   // [n][3] FP64, Morton order (gradient output)
+    void* pval = nullptr;       // [max_pairs] complex: value of every cousin pair (one RHS)
     bool ws_store_pref = false; // keep the cone values of every level
     void* F[IFGF_MAX_LEVELS + 1] = {};  // cone values per level [nslots][P][rb]
     std::vector<void*> ws_allocs;

@@ -412,6 +412,64 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval_pairs(KernelConsts kc, L
     }
 }
 
+// Two-phase interpolation at cousin targets (one right-hand side), through
+// the tabulated pairs.  Phase 1 takes the pairs in cone-slot order, from a
+// copy of the pair table in that order, so the threads of a wavefront read
+// consecutive pair data and one or two cones, served from cache; each pair's
+// interpolated value times its centred factor is stored at the pair's place
+// in target order.  Phase 2 adds, for every target, the values of its
+// pairs in cousin order.  No atomics: the sums have a fixed order.
+template <typename T, int PS, int PA>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_values(KernelConsts kc, LevelDev L,
+                                                                const cpx<T>* __restrict__ F,
+                                                                cpx<T>* __restrict__ pval)
+{
+    constexpr int P = PS * PA * PA;
+    const long long i = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const long long no = L.npairs_ord;
+    if (i >= no) return;
+    const int slot = L.pro_slot[i];
+    const T* pt = (const T*)L.pro_t;
+    const T* pg = (const T*)L.pro_g;
+    T Ls[PS], Lt[PA], Lp[PA];
+    lagrange<T, PS>((double)pt[i], kc.cs, Ls);
+    lagrange<T, PA>((double)pt[no + i], kc.ca, Lt);
+    lagrange<T, PA>((double)pt[2 * no + i], kc.ca, Lp);
+    cpx<T> v[1];
+    interp<T, PS, PA, 1>(F + (size_t)slot * P, Ls, Lt, Lp, v);
+    const T gr = pg[i], gi = (kc.kappa < 0.0 ? (T)-1 : (T)1) * pg[no + i];
+    pval[L.pr_order[i]] = cpx<T>{v[0].x * gr - v[0].y * gi, v[0].x * gi + v[0].y * gr};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_sum(KernelConsts kc, LevelDev L,
+                                                             const cpx<T>* __restrict__ pval,
+                                                             cpx<T>* __restrict__ out)
+{
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int tb = L.pt_box[i];
+    const int b0 = L.box_start[tb];
+    const long long nT = L.box_start[tb + 1] - b0;
+    const long long base = L.pair_base[tb] + (i - b0);
+    const int nc = L.cou_start[tb + 1] - L.cou_start[tb];
+    T ar = (T)0, ai = (T)0;
+    for (int c = 0; c < nc; ++c) {
+        const long long e = base + c * nT;
+        if (L.pr_slot[e] < 0) {
+            atomicAdd(kc.miss, 1ull);
+            continue;
+        }
+        const cpx<T> v = pval[e];
+        ar += v.x;
+        ai += v.y;
+    }
+    cpx<T> o = out[i];
+    o.x += ar;
+    o.y += ai;
+    out[i] = o;
+}
+
 // Child-to-parent interpolation, children at level d (Algorithm 1, second
 // inner loop): for every interpolation point x of every relevant cone of a
 // level-(d-1) box j,
@@ -1779,7 +1837,7 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
         maxs = std::max(maxs, (size_t)hp.L[d].nslots);
         tot += (size_t)hp.L[d].nslots;
     }
-    need += (store ? tot : 2 * maxs) * hp.P * rb * ce;
+    need += (store ? tot : 2 * maxs) * hp.P * rb * ce + (size_t)p.max_pairs * ce;
     if (p.ws_limit && p.tree_bytes + need > p.ws_limit) return hipErrorOutOfMemory;
     auto alloc = [&](size_t bytes, void** out) -> hipError_t {
         if (bytes == 0) bytes = 16;
@@ -1796,6 +1854,8 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     void* gm = nullptr;
     if ((e = alloc((size_t)hp.n * 3 * sizeof(double), &gm)) != hipSuccess) return e;
     p.grad_m = (double*)gm;
+    p.pval = nullptr;
+    if (p.max_pairs > 0 && (e = alloc((size_t)p.max_pairs * ce, &p.pval)) != hipSuccess) return e;
     if (store) {
         for (int d = 3; d <= D; ++d)
             if ((e = alloc((size_t)hp.L[d].nslots * hp.P * rb * ce, &p.F[d])) != hipSuccess) return e;
@@ -1957,6 +2017,14 @@ inline bool cousin_mfma_enabled()
     return v && *v && std::atoi(v) != 0;
 }
 
+// Two-phase cousin evaluation for one right-hand side: on unless
+// IFGF_COUSIN_TWO_PHASE=0.
+inline bool cousin_two_phase_enabled()
+{
+    const char* v = std::getenv("IFGF_COUSIN_TWO_PHASE");
+    return !(v && *v && std::atoi(v) == 0);
+}
+
 template <typename T, int PS, int PA, int RB>
 hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st, bool grad, bool reuse)
 {
@@ -1987,6 +2055,15 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                     if (p.L[d].use_pairs && cousin_mfma_enabled()) {
                         k_cousin_eval_mfma<PS, PA, RB><<<(unsigned)((hp.L[d].nbox + kBlock / 64 - 1) / (kBlock / 64)),
                                                          kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.out_m);
+                        done = true;
+                    }
+                }
+                if constexpr (RB == 1) {
+                    if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
+                        k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord), kBlock, 0, st>>>(
+                            kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+                        k_cousin_pairs_sum<T><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval,
+                                                                               (C*)p.out_m);
                         done = true;
                     }
                 }

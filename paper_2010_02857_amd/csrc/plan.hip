@@ -147,9 +147,31 @@ void build_pairs(HostPlan& hp, int d)
     L.use_pairs = true;
 }
 
-// Device bytes a level's frame table may take when its frames are not shared
-// (IFGF_FRAME_BUDGET_MB, default 3072).  IFGF_NO_FRAMES=1 disables the
-// tables (the kernels then compute every geometry themselves).
+// The pairs with a cone, ordered by cone slot (stable: by target box, cousin
+// and target), with a copy of their slot, local coordinates and centred
+// factor in that order, for the two-phase evaluation.
+void build_pair_order(HostLevel& L)
+{
+    const int64_t np = (int64_t)L.pr_slot.size();
+    std::vector<int64_t> start((size_t)L.nslots + 1, 0);
+    for (int64_t e = 0; e < np; ++e)
+        if (L.pr_slot[e] >= 0) start[(size_t)L.pr_slot[e] + 1]++;
+    for (int64_t s = 0; s < L.nslots; ++s) start[(size_t)s + 1] += start[(size_t)s];
+    const int64_t no = start[(size_t)L.nslots];
+    L.pr_order.assign((size_t)no, 0);
+    for (int64_t e = 0; e < np; ++e)
+        if (L.pr_slot[e] >= 0) L.pr_order[(size_t)start[(size_t)L.pr_slot[e]]++] = (int32_t)e;
+    L.pro_slot.resize((size_t)no);
+    L.pro_t.resize((size_t)3 * no);
+    L.pro_g.resize((size_t)2 * no);
+    parallel_for(no, [&](int64_t i) {
+        const int64_t e = L.pr_order[(size_t)i];
+        L.pro_slot[(size_t)i] = L.pr_slot[(size_t)e];
+        for (int c = 0; c < 3; ++c) L.pro_t[(size_t)c * no + i] = L.pr_t[(size_t)c * np + e];
+        for (int c = 0; c < 2; ++c) L.pro_g[(size_t)c * no + i] = L.pr_g[(size_t)c * np + e];
+    }, 4096);
+}
+
 // Parent boxes per block of the box tiles (IFGF_TILE_BLOCK overrides).
 int64_t tile_box_block()
 {
@@ -158,6 +180,9 @@ int64_t tile_box_block()
     return v < 1 ? 1 : v;
 }
 
+// Device bytes a level's frame table may take when its frames are not shared
+// (IFGF_FRAME_BUDGET_MB, default 3072).  IFGF_NO_FRAMES=1 disables the
+// tables (the kernels then compute every geometry themselves).
 double frame_budget_bytes()
 {
     const char* e = std::getenv("IFGF_FRAME_BUDGET_MB");
@@ -341,7 +366,8 @@ void build_frames(HostPlan& hp, int d)
 }  // namespace
 
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
-                            int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, HostPlan& hp,
+                            int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
+                            HostPlan& hp,
                             ifgf_status& code)
 {
     auto t0 = std::chrono::steady_clock::now();
@@ -745,6 +771,15 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
             if (used + npairs * per > pair_budget_bytes()) break;
             used += npairs * per;
             build_pairs(hp, d);
+        }
+        // cone-ordered copies for the two-phase evaluation, in what is left
+        for (int d = 3; d <= D && ord_elem_bytes > 0.0; ++d) {
+            HostLevel& L = hp.L[d];
+            if (!L.use_pairs) break;
+            const double extra = (double)L.pr_slot.size() * ord_elem_bytes;
+            if (used + extra > pair_budget_bytes()) continue;
+            used += extra;
+            build_pair_order(L);
         }
     }
 
