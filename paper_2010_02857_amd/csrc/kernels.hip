@@ -716,13 +716,15 @@ __global__ void __launch_bounds__(NT) k_child_to_parent_lds(KernelConsts kc, Lev
     }
 }
 
-// Capacity (cones) of the LDS stage for ~24 KB of cone values, at most
+// Capacity (cones) of the LDS stage: ~24 KB of cone values (48 KB for FP64
+// with one right-hand side, whose cones are twice as large), at most
 // S * kMaxFrameGroups.
 template <typename T, int P, int RB, int S>
 constexpr int lds_gcap()
 {
-    return (24576 / (P * RB * (int)sizeof(cpx<T>))) < S * kMaxFrameGroups
-               ? (24576 / (P * RB * (int)sizeof(cpx<T>)))
+    constexpr int bytes = (sizeof(T) == 8 && RB == 1) ? 49152 : 24576;
+    return (bytes / (P * RB * (int)sizeof(cpx<T>))) < S * kMaxFrameGroups
+               ? (bytes / (P * RB * (int)sizeof(cpx<T>)))
                : S * kMaxFrameGroups;
 }
 
