@@ -1874,13 +1874,14 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
 }
 
 // Least average number of slots per box tile (as a fraction of kBoxTile) for
-// which the box-batched child-to-parent kernel is used; IFGF_BOX_FILL
-// overrides it (a value above 1 disables the kernel).
+// which the default rule picks the box-batched child-to-parent kernel (never
+// for 16 right-hand sides, where the autotuner decides); IFGF_BOX_FILL
+// overrides it (a value above 1 disables it in the default rule).
 inline double box_fill_min(int rb)
 {
     const char* v = std::getenv("IFGF_BOX_FILL");
     if (v && *v) return std::atof(v);
-    return rb == 1 ? 0.5 : 0.25;
+    return rb == 1 ? 0.5 : (rb == 4 ? 0.25 : 2.0);
 }
 
 // Child-to-parent kernel variants of level d (children at d).  Every
@@ -1903,7 +1904,7 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
     if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
         v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
     }
-    if constexpr (std::is_same<T, float>::value && (RB == 1 || RB == 4) && PA >= 4 && P <= 128) {
+    if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
         if (groups && L.ntiles > 0) v[n++] = kC2PBoxes;
     }
     if constexpr (RB == 1 && P <= 255) {
@@ -1957,7 +1958,7 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
     C* Fp = (C*)p.F[d - 1];
     switch (variant) {
     case kC2PBoxes:
-        if constexpr (std::is_same<T, float>::value && (RB == 1 || RB == 4) && PA >= 4 && P <= 128) {
+        if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
             k_child_to_parent_boxes<PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
                 kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
             return;

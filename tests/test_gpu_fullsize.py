@@ -41,7 +41,8 @@ def test_batched_workload_eps(torch, cfg):
     plan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=w.nrhs, store_levels=0)
     out = plan.apply(torch.from_numpy(a).to(torch.complex64).cuda()).cpu().numpy()
     assert plan.misses() == 0
-    idx = inputs.error_subset(cfg, p.shape[0], 1000)
+    # the paper's eps_M protocol on M random targets (10000 for the largest workload)
+    idx = inputs.error_subset(cfg, p.shape[0], 10000 if cfg == 5 else 1000)
     for r in (0, w.nrhs - 1):
         d = oracle.direct(p, a[r], w.kappa, targets=p[idx], skip=idx)[0]
         e = rel(out[r, idx], d)
@@ -74,6 +75,17 @@ def test_gradient_workload(torch):
         del plan
     I, ga, gx = grads[1]
     assert rel(grads[0][1], ga) < 1e-6 and rel(grads[0][2], gx) < 1e-6
+    # the FP64 path's gradients on the same (complex64-valued) densities
+    plan64 = ifgf.Plan(p, w.kappa, precision="fp64", max_nrhs=1, store_levels=1)
+    x64 = torch.from_numpy(a.astype(np.complex128)).cuda().requires_grad_(True)
+    t64 = torch.from_numpy(p).cuda().requires_grad_(True)
+    I64 = ifgf.apply(plan64, x64, t64)
+    (I64.abs() ** 2).sum().backward()
+    e64_a = rel(ga.astype(np.complex128), x64.grad.cpu().numpy())
+    e64_x = rel(gx, t64.grad.cpu().numpy())
+    print(f"mixed vs FP64 gradient: density {e64_a:.3e}, coordinates {e64_x:.3e}", flush=True)
+    assert e64_a < 1e-5 and e64_x < 1e-4
+    del plan64
     g = 2.0 * I.astype(np.complex128)
     aa = a.astype(np.complex128)
     ga_exact = np.conj(oracle.direct(p, np.conj(g), w.kappa, targets=p[idx], skip=idx))[0]
