@@ -123,6 +123,8 @@ typedef struct {
                                                 of level d is tabulated        */
     int64_t device_bytes;                    /* device memory held by the plan  */
     double t_plan_s;                         /* host seconds to build the plan  */
+    int64_t n_sources;                       /* densities per right-hand side   */
+    int64_t n_targets;                       /* outputs per right-hand side     */
 } ifgf_stats;
 
 /* Create a plan for the points (Sec. 3.3.2: box octree, relevant boxes,
@@ -143,12 +145,28 @@ typedef struct {
 ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t levels,
                              const int32_t* degrees, const ifgf_options* opt, ifgf_plan_t* plan);
 
+/* Create a plan with distinct sources and targets (the field of Sec. 2,
+ * eq. field1, evaluated at points other than the sources).  The hierarchy is
+ * built over the n + m points together, the targets carrying zero density,
+ * so the result is the IFGF approximation of sum_m a(x_m) G(y, x_m) at every
+ * target y.  All points (sources and targets) must be pairwise different.
+ *   sources  host, n x 3 FP64 (copied); targets  host, m x 3 FP64 (copied).
+ * With such a plan ifgf_apply maps densities [nrhs][n] to out [nrhs][m],
+ * ifgf_apply_adjoint maps [nrhs][m] to [nrhs][n], and ifgf_grad_targets
+ * takes densities [nrhs][n] and grad_out [nrhs][m] and writes grad_xyz [m][3]
+ * (target coordinates).  Other arguments as for ifgf_plan_create.          */
+ifgf_status ifgf_plan_create_targets(const double* sources, int64_t n, const double* targets, int64_t m, double k,
+                                     int32_t levels, const int32_t* degrees, const ifgf_options* opt,
+                                     ifgf_plan_t* plan);
+
 /* out = IFGF approximation of the operator applied to the densities
  * (Algorithm 1).
- *   densities  device, [nrhs][n] complex (dtype by precision); read only.
+ *   densities  device, [nrhs][n_sources] complex (dtype by precision); read
+ *              only.
  *   nrhs       1 .. max_nrhs.
- *   out        device, [nrhs][n] complex, overwritten; must not alias the
- *              densities.                                                  */
+ *   out        device, [nrhs][n_targets] complex, overwritten; must not
+ *              alias the densities.  (n_sources = n_targets = n unless the
+ *              plan has distinct targets; ifgf_plan_stats reports both.)   */
 ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, int32_t nrhs, void* out, void* stream);
 
 /* out = adjoint operator applied to v:

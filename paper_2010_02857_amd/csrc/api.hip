@@ -3,6 +3,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ifgf_internal.hpp"
 
@@ -245,8 +246,8 @@ struct DeviceGuard {
 
 extern "C" {
 
-ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t levels, const int32_t* degrees,
-                             const ifgf_options* opt, ifgf_plan_t* plan)
+static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt, double k, int32_t levels,
+                                 const int32_t* degrees, const ifgf_options* opt, ifgf_plan_t* plan)
 {
     if (!plan) return fail(IFGF_E_INVALID_ARG, "plan output pointer is NULL");
     *plan = nullptr;
@@ -268,6 +269,8 @@ ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t 
     p.host_only = o.host_only != 0;
     p.use_graph = o.use_graph != 0;
     p.ws_limit = o.workspace_limit;
+    p.n_tgt = n_tgt;
+    p.n_src = n - n_tgt;
     ifgf_status code = IFGF_OK;
     std::string msg;
     try {
@@ -321,8 +324,36 @@ ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t 
         }
     }
     p.hp.stats.device_bytes = (int64_t)p.tree_bytes;
+    p.hp.stats.n_sources = p.n_tgt > 0 ? p.n_src : n;
+    p.hp.stats.n_targets = p.n_tgt > 0 ? p.n_tgt : n;
     *plan = pl;
     return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t levels, const int32_t* degrees,
+                             const ifgf_options* opt, ifgf_plan_t* plan)
+{
+    return create_common(points, n, 0, k, levels, degrees, opt, plan);
+}
+
+ifgf_status ifgf_plan_create_targets(const double* sources, int64_t n, const double* targets, int64_t m, double k,
+                                     int32_t levels, const int32_t* degrees, const ifgf_options* opt,
+                                     ifgf_plan_t* plan)
+{
+    if (!plan) return fail(IFGF_E_INVALID_ARG, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (!sources || !targets) return fail(IFGF_E_INVALID_ARG, "sources or targets is NULL");
+    if (n < 1 || m < 1) return fail(IFGF_E_INVALID_ARG, "need at least one source and one target");
+    if (n + m > (int64_t)INT32_MAX / 2) return fail(IFGF_E_INVALID_ARG, "too many points for 32-bit indexing");
+    std::vector<double> all;
+    try {
+        all.resize((size_t)3 * (n + m));
+    } catch (const std::bad_alloc&) {
+        return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed");
+    }
+    std::memcpy(all.data(), sources, sizeof(double) * 3 * (size_t)n);
+    std::memcpy(all.data() + 3 * n, targets, sizeof(double) * 3 * (size_t)m);
+    return create_common(all.data(), n + m, m, k, levels, degrees, opt, plan);
 }
 
 // The apply as a captured graph: captured on the plan's own stream the first

@@ -262,6 +262,9 @@ struct DevicePlan {
     int device = -1;
     int precision = IFGF_FP64;
     int max_nrhs = 16;
+    // distinct targets: points [0, n_src) are the sources, [n_src, n_src +
+    // n_tgt) the targets (densities zero there); n_tgt = 0: every point is both
+    int64_t n_src = 0, n_tgt = 0;
     int store_levels = -1;
     bool host_only = false;
     size_t ws_limit = 0;

@@ -193,36 +193,46 @@ __device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T
 
 // ------------------------------------------------------------------ kernels
 
-// densities [nrhs][n] (input order) -> [n][RB] (Morton order), zero padded.
+// A window [w0, w0 + wn) of the plan's point indices (input order): all
+// points, or with distinct targets the sources [0, n_src) or the targets
+// [n_src, n_src + n_tgt).
+struct Window {
+    int w0, wn;
+};
+
+// values on a window, [nrhs][wn] (input order) -> [n][RB] (Morton order),
+// zero outside the window and for right-hand sides beyond nrhs.
 template <typename T, int RB>
 __global__ void __launch_bounds__(kBlock) k_permute_in(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                                       const int32_t* __restrict__ perm, int n, int nrhs, int r0)
+                                                       const int32_t* __restrict__ perm, int n, Window w, int nrhs,
+                                                       int r0)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int src = perm[i];
+    const int src = perm[i] - w.w0;
+    const bool inside = src >= 0 && src < w.wn;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         int rr = r0 + r;
         cpx<T> v;
         v.x = v.y = (T)0;
-        if (rr < nrhs) v = in[(size_t)rr * n + src];
+        if (rr < nrhs && inside) v = in[(size_t)rr * w.wn + src];
         out[(size_t)i * RB + r] = v;
     }
 }
 
-// [n][RB] (Morton order) -> out [nrhs][n] (input order).
+// [n][RB] (Morton order) -> out [nrhs][wn], the window's points (input order).
 template <typename T, int RB>
 __global__ void __launch_bounds__(kBlock) k_permute_out(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                                        const int32_t* __restrict__ iperm, int n, int nrhs, int r0)
+                                                        const int32_t* __restrict__ iperm, Window w, int nrhs, int r0)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int i = iperm[j];
+    if (j >= w.wn) return;
+    int i = iperm[w.w0 + j];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         int rr = r0 + r;
-        if (rr < nrhs) out[(size_t)rr * n + j] = in[(size_t)i * RB + r];
+        if (rr < nrhs) out[(size_t)rr * w.wn + j] = in[(size_t)i * RB + r];
     }
 }
 
@@ -1793,13 +1803,13 @@ __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDe
     grad[3 * i + 2] += acc2;
 }
 
-// [n][3] (Morton order) -> grad [n][3] (input order).
+// [n][3] (Morton order) -> grad [wn][3], the window's points (input order).
 __global__ void __launch_bounds__(kBlock) k_permute_grad(const double* __restrict__ in, double* __restrict__ out,
-                                                         const int32_t* __restrict__ iperm, int n)
+                                                         const int32_t* __restrict__ iperm, Window w)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int i = iperm[j];
+    if (j >= w.wn) return;
+    int i = iperm[w.w0 + j];
     out[3 * j] = in[3 * i];
     out[3 * j + 1] = in[3 * i + 1];
     out[3 * j + 2] = in[3 * i + 2];
@@ -1808,6 +1818,17 @@ __global__ void __launch_bounds__(kBlock) k_permute_grad(const double* __restric
 // ------------------------------------------------------------- host side
 
 inline unsigned grid_for(size_t items) { return (unsigned)((items + kBlock - 1) / kBlock); }
+
+// Source and target windows of a plan: every point is both unless the plan
+// was created with distinct targets.
+inline Window source_window(const DevicePlan& p)
+{
+    return p.n_tgt > 0 ? Window{0, (int)p.n_src} : Window{0, (int)p.hp.n};
+}
+inline Window target_window(const DevicePlan& p)
+{
+    return p.n_tgt > 0 ? Window{(int)p.n_src, (int)p.n_tgt} : Window{0, (int)p.hp.n};
+}
 
 inline int rb_for(int nrhs) { return nrhs >= 5 ? 16 : (nrhs >= 2 ? 4 : 1); }
 
@@ -2095,7 +2116,9 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), kappa, n, p.miss};
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
-        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, r0);
+        // forward: sources -> targets; adjoint (kappa < 0): targets -> sources
+        const Window w = kappa < 0.0 ? target_window(p) : source_window(p);
+        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, w, nrhs, r0);
     }
     {
         StageTimer tm_(p, IFGF_STAGE_NEARFIELD, st);
@@ -2105,7 +2128,9 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     if (e != hipSuccess) return e;
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_OUT, st);
-        k_permute_out<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)p.out_m, (C*)out, p.iperm, n, nrhs, r0);
+        const Window w = kappa < 0.0 ? source_window(p) : target_window(p);
+        k_permute_out<T, RB><<<grid_for((size_t)w.wn), kBlock, 0, st>>>((const C*)p.out_m, (C*)out, p.iperm, w, nrhs,
+                                                                        r0);
     }
     return hipGetLastError();
 }
@@ -2120,11 +2145,13 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
     if (!reuse)
         {
             StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
-            k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, nrhs, 0);
+            k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n,
+                                                                source_window(p), nrhs, 0);
         }
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
-        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n, nrhs, 0);
+        k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n,
+                                                            target_window(p), nrhs, 0);
     }
     {
         StageTimer tm_(p, IFGF_STAGE_NEAR_GRAD, st);
@@ -2135,7 +2162,8 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
     if (e != hipSuccess) return e;
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_GRAD, st);
-        k_permute_grad<<<grid_for(n), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, n);
+        const Window w = target_window(p);
+        k_permute_grad<<<grid_for((size_t)w.wn), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, w);
     }
     return hipGetLastError();
 }

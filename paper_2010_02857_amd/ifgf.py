@@ -71,6 +71,8 @@ class Stats(ctypes.Structure):
         ("pairs_tabulated", ctypes.c_int32 * _L),
         ("device_bytes", ctypes.c_int64),
         ("t_plan_s", ctypes.c_double),
+        ("n_sources", ctypes.c_int64),
+        ("n_targets", ctypes.c_int64),
     ]
 
 
@@ -87,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.ifgf_plan_create.argtypes = [P, I64, ctypes.c_double, I32, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+        L.ifgf_plan_create_targets.argtypes = [P, I64, P, I64, ctypes.c_double, I32, P, ctypes.POINTER(Options),
+                                               ctypes.POINTER(P)]
         L.ifgf_apply.argtypes = [P, P, I32, P, P]
         L.ifgf_apply_adjoint.argtypes = [P, P, I32, P, P]
         L.ifgf_grad_targets.argtypes = [P, P, P, I32, P, P]
@@ -103,7 +107,7 @@ def lib() -> ctypes.CDLL:
         L.ifgf_status_string.restype = ctypes.c_char_p
         L.ifgf_last_error.argtypes = []
         L.ifgf_last_error.restype = ctypes.c_char_p
-        for f in (L.ifgf_plan_create, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
+        for f in (L.ifgf_plan_create, L.ifgf_plan_create_targets, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
                   L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy, L.ifgf_plan_profile,
                   L.ifgf_plan_stage_times, L.ifgf_plan_autotune, L.ifgf_plan_kernel_choice,
                   L.ifgf_plan_set_kernel_choice, L.ifgf_plan_kernel_candidates):
@@ -125,9 +129,12 @@ def _check(rc: int):
 
 
 class Plan:
-    """An IFGF plan over a fixed point set (sources = targets).
+    """An IFGF plan over a fixed point set: the points are both sources and
+    targets, or with `targets` given, the field of the sources `points` is
+    evaluated at the distinct `targets`.
 
     points     (n, 3) float64 array-like (host); copied.
+    targets    None, or (m, 3) float64 array-like (host); copied.
     k          wavenumber >= 0.
     levels     D, or 0 for H_D about a quarter wavelength.
     degrees    (P_s, P_ang) Chebyshev nodes per cone direction.
@@ -137,11 +144,17 @@ class Plan:
 
     def __init__(self, points, k: float, levels: int = 0, degrees=(3, 5), precision: str = "fp64",
                  leaf=(1, 2), max_nrhs: int = 16, store_levels: int = -1, host_only: bool = False,
-                 dilate: bool = True, workspace_limit: int = 0, use_graph: bool = False, device=None):
-        if hasattr(points, "detach"):
-            points = points.detach().cpu().numpy()
-        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
-        self.n = pts.shape[0]
+                 dilate: bool = True, workspace_limit: int = 0, use_graph: bool = False, targets=None,
+                 device=None):
+        def host(x):
+            if hasattr(x, "detach"):
+                x = x.detach().cpu().numpy()
+            return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, 3))
+
+        pts = host(points)
+        tgt = None if targets is None else host(targets)
+        self.n = pts.shape[0]                     # sources
+        self.m = self.n if tgt is None else tgt.shape[0]   # targets
         self.k = float(k)
         self.precision = precision
         if precision not in ("fp64", "mixed"):
@@ -154,16 +167,25 @@ class Plan:
         self._h = None
         self.host_only = host_only
         self.device = None
+
+        def create():
+            if tgt is None:
+                _check(lib().ifgf_plan_create(pts.ctypes.data_as(ctypes.c_void_p), self.n, self.k, int(levels),
+                                              ctypes.cast(deg, ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(h)))
+            else:
+                _check(lib().ifgf_plan_create_targets(pts.ctypes.data_as(ctypes.c_void_p), self.n,
+                                                      tgt.ctypes.data_as(ctypes.c_void_p), self.m, self.k,
+                                                      int(levels), ctypes.cast(deg, ctypes.c_void_p),
+                                                      ctypes.byref(opt), ctypes.byref(h)))
+
         if not host_only:
             import torch
             self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                        else torch.device(device).index or 0)
             with torch.cuda.device(self.device):
-                _check(lib().ifgf_plan_create(pts.ctypes.data_as(ctypes.c_void_p), self.n, self.k, int(levels),
-                                              ctypes.cast(deg, ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(h)))
+                create()
         else:
-            _check(lib().ifgf_plan_create(pts.ctypes.data_as(ctypes.c_void_p), self.n, self.k, int(levels),
-                                          ctypes.cast(deg, ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(h)))
+            create()
         self._h = h
 
     # -- housekeeping
@@ -184,7 +206,8 @@ class Plan:
         D = st.D
         out = {"D": D, "n_points": st.n_points, "H1": st.H1, "x1": list(st.x1), "kappa": st.kappa,
                "ps": st.ps, "pang": st.pang, "n_leaf_pairs": st.n_leaf_pairs, "n_near_pairs": st.n_near_pairs,
-               "n_dilated": st.n_dilated, "device_bytes": st.device_bytes, "t_plan_s": st.t_plan_s}
+               "n_dilated": st.n_dilated, "device_bytes": st.device_bytes, "t_plan_s": st.t_plan_s,
+               "n_sources": st.n_sources, "n_targets": st.n_targets}
         for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
                     "n_parent_evals", "n_frames", "pairs_tabulated"):
             arr = getattr(st, key)
@@ -252,16 +275,17 @@ class Plan:
         import torch
         return torch.complex128 if self.precision == "fp64" else torch.complex64
 
-    def _prep(self, a):
+    def _prep(self, a, npts=None):
         import torch
+        npts = self.n if npts is None else npts
         if not isinstance(a, torch.Tensor) or not a.is_cuda:
             raise TypeError("expected a CUDA (HIP) tensor")
         if a.dtype != self.dtype:
             raise TypeError(f"expected {self.dtype}, got {a.dtype}")
         squeeze = a.dim() == 1
         a2 = a.reshape(1, -1) if squeeze else a
-        if a2.dim() != 2 or a2.shape[1] != self.n:
-            raise ValueError(f"expected shape (nrhs, {self.n}) or ({self.n},)")
+        if a2.dim() != 2 or a2.shape[1] != npts:
+            raise ValueError(f"expected shape (nrhs, {npts}) or ({npts},)")
         return a2.contiguous(), squeeze
 
     def _stream(self, t):
@@ -274,31 +298,33 @@ class Plan:
         result (with use_graph, reusing the same a and out replays the
         captured graph)."""
         import torch
-        a2, squeeze = self._prep(a)
+        nin, nout = (self.m, self.n) if adjoint else (self.n, self.m)
+        a2, squeeze = self._prep(a, nin)
+        shape = (a2.shape[0], nout)
         if out is None:
-            out = torch.empty_like(a2)
+            out = torch.empty(shape, dtype=a2.dtype, device=a2.device)
         else:
-            if out.dtype != a2.dtype or out.device != a2.device or out.numel() != a2.numel() \
+            if out.dtype != a2.dtype or out.device != a2.device or out.numel() != shape[0] * shape[1] \
                     or not out.is_contiguous():
-                raise ValueError("out must be a contiguous tensor like the densities")
+                raise ValueError("out must be a contiguous tensor of the output's shape and dtype")
             if out.data_ptr() == a2.data_ptr():
                 raise ValueError("out must not alias the densities")
         f = lib().ifgf_apply_adjoint if adjoint else lib().ifgf_apply
         _check(f(self._h, ctypes.c_void_p(a2.data_ptr()), a2.shape[0], ctypes.c_void_p(out.data_ptr()),
                  self._stream(a2)))
-        return out.reshape(-1) if squeeze else out.reshape(a2.shape)
+        return out.reshape(-1) if squeeze else out.reshape(shape)
 
     def adjoint(self, v):
         return self.apply(v, adjoint=True)
 
     def grad_targets(self, a, g):
-        """sum_r Re(conj(g_r) dI_r/dx) for every point, (n, 3) float64."""
+        """sum_r Re(conj(g_r) dI_r/dx) for every target, (m, 3) float64."""
         import torch
-        a2, _ = self._prep(a)
-        g2, _ = self._prep(g)
-        if g2.shape != a2.shape:
-            raise ValueError("grad_out must match the densities' shape")
-        out = torch.empty((self.n, 3), dtype=torch.float64, device=a2.device)
+        a2, _ = self._prep(a, self.n)
+        g2, _ = self._prep(g, self.m)
+        if g2.shape[0] != a2.shape[0]:
+            raise ValueError("grad_out must have as many right-hand sides as the densities")
+        out = torch.empty((self.m, 3), dtype=torch.float64, device=a2.device)
         _check(lib().ifgf_grad_targets(self._h, ctypes.c_void_p(a2.data_ptr()), ctypes.c_void_p(g2.data_ptr()),
                                        a2.shape[0], ctypes.c_void_p(out.data_ptr()), self._stream(a2)))
         return out
@@ -337,8 +363,9 @@ _FN = None
 
 
 def apply(plan: Plan, a, targets=None):
-    """Differentiable IFGF matvec.  `targets` is the plan's (n, 3) point
-    tensor, passed so that a gradient with respect to it can flow."""
+    """Differentiable IFGF matvec.  `targets` is the plan's (m, 3) target
+    point tensor (the points themselves when sources = targets), passed so
+    that a gradient with respect to it can flow."""
     global _FN
     if _FN is None:
         _FN = _function()

@@ -126,3 +126,32 @@ def test_two_points_single_level():
     p = np.array([[0.0, 0.0, 0.0], [0.5, 0.0, 0.0]])
     st = ifgf.Plan(p, 3.0, host_only=True).stats()
     assert st["D"] == 2 and st["n_near_pairs"] == 2 and sum(st["n_cones"]) == 0
+
+
+def test_distinct_targets_host_plan():
+    """A plan with distinct targets is the plan over sources and targets
+    together (the same hierarchy counts), with the source and target counts
+    reported; coinciding source and target points and empty sets are
+    rejected."""
+    src = inputs.cube_sphere(8)
+    tgt = 1.25 * inputs.cube_sphere(6)
+    plan = ifgf.Plan(src, 4.0, host_only=True, targets=tgt)
+    st = plan.stats()
+    assert st["n_sources"] == src.shape[0] and st["n_targets"] == tgt.shape[0]
+    assert st["n_points"] == src.shape[0] + tgt.shape[0]
+    union = ifgf.Plan(np.concatenate([src, tgt]), 4.0, host_only=True).stats()
+    for key in ("D", "n_boxes", "n_cones", "n_cousin_evals", "n_parent_evals", "n_near_pairs"):
+        assert st[key] == union[key], key
+    same = ifgf.Plan(src, 4.0, host_only=True).stats()
+    assert same["n_sources"] == same["n_targets"] == src.shape[0]
+    with pytest.raises(ifgf.IFGFError) as e:
+        ifgf.Plan(src, 4.0, host_only=True, targets=np.concatenate([tgt, src[:1]]))
+    assert e.value.status == 1
+    lib = ifgf.lib()
+    h = ctypes.c_void_p()
+    buf = np.zeros((4, 3))
+    assert lib.ifgf_plan_create_targets(buf.ctypes.data_as(ctypes.c_void_p), 4, None, 3, 1.0, 0, None, None,
+                                        ctypes.byref(h)) == 1
+    assert lib.ifgf_plan_create_targets(buf.ctypes.data_as(ctypes.c_void_p), 4,
+                                        buf.ctypes.data_as(ctypes.c_void_p), 0, 1.0, 0, None, None,
+                                        ctypes.byref(h)) == 1
