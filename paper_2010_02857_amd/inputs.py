@@ -13,7 +13,9 @@ here:
 * faces in the order +x, -x, +y, -y, +z, -z, the points (+-1, u_i, u_j),
   (u_i, +-1, u_j), (u_i, u_j, +-1) with i outer and j inner;
 * every point is projected onto the unit sphere; an oblate spheroid with
-  semi-axes (1, 1, c) scales z by c afterwards.
+  semi-axes (1, 1, c) scales z by c afterwards, a general spheroid scales
+  every axis, and the rough sphere moves each point to the radius of eq.
+  defbumpysphere along its direction.
 
 Densities are complex Gaussians a = (N(0,1) + i N(0,1)) / sqrt(2) drawn from
 ``numpy.random.default_rng(1000 + cfg)`` as ``standard_normal((R, N, 2))``;
@@ -51,6 +53,26 @@ def cube_sphere(n: int, zscale: float = 1.0) -> np.ndarray:
     if zscale != 1.0:
         p[:, 2] *= zscale
     return np.ascontiguousarray(p)
+
+
+def spheroid(n: int, axes=(1.0, 1.0, 0.1)) -> np.ndarray:
+    """The spheroid x^2/alpha^2 + y^2/beta^2 + z^2/gamma^2 = 1 of eq.
+    defspheroid, as the cube-sphere scaled by (alpha, beta, gamma): oblate
+    (1, 1, 0.1) and prolate (0.1, 0.1, 1) in Sec. 4."""
+    p = cube_sphere(n)
+    p *= np.asarray(axes, dtype=np.float64)[None, :]
+    return np.ascontiguousarray(p)
+
+
+def rough_sphere(n: int, amplitude: float = 0.05, frequency: float = 40.0) -> np.ndarray:
+    """The rough sphere of eq. defbumpysphere: the cube-sphere directions at
+    radius 1 + amplitude sin(frequency theta) sin(frequency phi), with theta
+    the polar angle in [0, pi] and phi the azimuth in [0, 2 pi)."""
+    d = cube_sphere(n)
+    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    phi = np.mod(np.arctan2(d[:, 1], d[:, 0]), 2.0 * math.pi)
+    r = 1.0 + amplitude * np.sin(frequency * theta) * np.sin(frequency * phi)
+    return np.ascontiguousarray(d * r[:, None])
 
 
 @dataclass(frozen=True)

@@ -419,6 +419,32 @@ def test_distinct_targets(torch, prec, nrhs):
     assert plan.misses() == 0
 
 
+@pytest.mark.parametrize("geom", ["prolate", "oblate", "rough"])
+def test_paper_geometries(torch, geom):
+    """The other surfaces of Sec. 4 (eqs. defspheroid, defbumpysphere): the
+    prolate (0.1, 0.1, 1) and oblate (1, 1, 0.1) spheroids and the rough
+    sphere, N = 6144, diameter 4 wavelengths: FP64 equals the oracle, mixed
+    within its bar, both within the method's accuracy of the direct sum."""
+    pts = {"prolate": lambda: inputs.spheroid(32, (0.1, 0.1, 1.0)),
+           "oblate": lambda: inputs.spheroid(32, (1.0, 1.0, 0.1)),
+           "rough": lambda: inputs.rough_sphere(32)}[geom]()
+    k = 4.0 * math.pi
+    a = inputs.densities(26, 1, pts.shape[0])
+    ref = oracle.ifgf(pts, a, k)["out"]
+    direct = oracle.direct(pts, a, k)
+    eps = rel(ref, direct)
+    print(f"{geom}: eps_M of the method = {eps:.2e}", flush=True)
+    assert eps < 1e-3
+    out = make_plan(pts, k, "fp64").apply(dev(torch, a, "fp64")).cpu().numpy()
+    assert rel(out, ref) < FP64_TOL
+    ac = as_c64(a)
+    ref32 = oracle.ifgf(pts, ac, k)["out"]
+    plan = make_plan(pts, k, "mixed")
+    out32 = plan.apply(dev(torch, a, "mixed")).cpu().numpy()
+    assert rel(out32, ref32) < MIXED_TOL
+    assert plan.misses() == 0
+
+
 def test_argument_errors(torch):
     from paper_2010_02857_amd import ifgf
     p = inputs.cube_sphere(8)
