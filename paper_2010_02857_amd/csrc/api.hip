@@ -1,5 +1,6 @@
 // C ABI of the IFGF library (declared in include/ifgf.h).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -277,8 +278,17 @@ static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt,
         // a tabulated cousin-target pair: slot, 3 local coordinates, complex G
         double pair_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 24.0 : 44.0);
         double ord_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 28.0 : 48.0);
-        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes, ord_bytes,
-                                    p.hp, code);
+        // pair tables: IFGF_PAIR_BUDGET_MB, else a quarter of the free device
+        // memory, at most 64 GiB
+        double budget = 0.0;
+        if (const char* env = std::getenv("IFGF_PAIR_BUDGET_MB")) {
+            budget = std::atof(env) * 1024.0 * 1024.0;
+        } else if (!p.host_only) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min(0.25 * (double)fr, 64.0 * (1ull << 30));
+        }
+        msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes,
+                                    ord_bytes, budget, p.hp, code);
     } catch (const std::bad_alloc&) {
         delete pl;
         return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed while building the plan");

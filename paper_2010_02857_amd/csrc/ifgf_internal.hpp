@@ -191,10 +191,11 @@ struct HostPlan {
 // Builds the hierarchy; returns an empty string on success, else a message.
 // `code` receives the ifgf_status on failure.
 // tab_elem_bytes: device bytes of one tabulated cousin-target pair (0: none);
-// ord_elem_bytes: device bytes of its cone-ordered copy (0: none).
+// ord_elem_bytes: device bytes of its cone-ordered copy (0: none);
+// pair_budget: device bytes the pair tables may take.
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
                             int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
-                            HostPlan& hp, ifgf_status& code);
+                            double pair_budget, HostPlan& hp, ifgf_status& code);
 
 // ---------------------------------------------------------- device mirror
 

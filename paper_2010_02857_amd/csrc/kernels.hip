@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values(KernelConsts kc,
     pval[L.pr_order[i]] = cpx<T>{v[0].x * gr - v[0].y * gi, v[0].x * gi + v[0].y * gr};
 }
 
-template <typename T>
+template <typename T, int RB>
 __global__ void __launch_bounds__(kBlock) k_cousin_pairs_sum(KernelConsts kc, LevelDev L,
                                                              const cpx<T>* __restrict__ pval,
                                                              cpx<T>* __restrict__ out)
@@ -463,22 +463,31 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_sum(KernelConsts kc, Le
     const long long nT = L.box_start[tb + 1] - b0;
     const long long base = L.pair_base[tb] + (i - b0);
     const int nc = L.cou_start[tb + 1] - L.cou_start[tb];
-    T ar = (T)0, ai = (T)0;
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
     for (int c = 0; c < nc; ++c) {
         const long long e = base + c * nT;
         if (L.pr_slot[e] < 0) {
             atomicAdd(kc.miss, 1ull);
             continue;
         }
-        const cpx<T> v = pval[e];
-        ar += v.x;
-        ai += v.y;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cpx<T> v = pval[e * RB + r];
+            acc[r].x += v.x;
+            acc[r].y += v.y;
+        }
     }
-    cpx<T> o = out[i];
-    o.x += ar;
-    o.y += ai;
-    out[i] = o;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        cpx<T> o = out[(size_t)i * RB + r];
+        o.x += acc[r].x;
+        o.y += acc[r].y;
+        out[(size_t)i * RB + r] = o;
+    }
 }
+
 
 // Child-to-parent interpolation, children at level d (Algorithm 1, second
 // inner loop): for every interpolation point x of every relevant cone of a
@@ -1680,6 +1689,74 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval_mfma(KernelConsts kc, Le
     }
 }
 
+// Phase 1 for batched right-hand sides on the matrix cores (FP32): a
+// wavefront takes 16 consecutive pairs in cone order as the rows of 16 x 16
+// x 4 MFMA tiles; the rows that share a cone (usually all) form one tile
+// group with that cone's values as the B operand (K = its nodes, columns the
+// real and imaginary parts of the RB right-hand sides).  Each row is
+// multiplied by its centred factor and stored once, at the pair's place.
+template <int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConsts kc, LevelDev L,
+                                                                     const cpx<float>* __restrict__ F,
+                                                                     cpx<float>* __restrict__ pval)
+{
+    constexpr int NC = 2 * RB;
+    constexpr int NT = (NC + 15) / 16;
+    constexpr int W = kBlock / 64;
+    constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
+    constexpr int P = PS * PA * PA;
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long no = L.npairs_ord;
+    const long long i0 = ((long long)xcd_block(blockIdx.x, gridDim.x) * W + wv) * 16;
+    if (i0 >= no) return;                      // whole wavefront leaves
+    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const long long i = i0 + row;
+    const bool valid = i < no;
+    const long long ic = valid ? i : i0;
+    const int slot = valid ? L.pro_slot[ic] : -1;
+    const float* pt = (const float*)L.pro_t;
+    const float* pg = (const float*)L.pro_g;
+    float Ls[PS], Lt[PA], Lpv[PA];
+    lagrange<float, PS>((double)pt[ic], kc.cs, Ls);
+    lagrange<float, PA>((double)pt[no + ic], kc.ca, Lt);
+    lagrange<float, PA>((double)pt[2 * no + ic], kc.ca, Lpv);
+    const float gr = pg[ic], gi = (kc.kappa < 0.0 ? -1.f : 1.f) * pg[no + ic];
+    const long long e = L.pr_order[ic];
+    const float* Ff = (const float*)F;
+    float* pf = (float*)pval;
+    unsigned long long todo = __ballot(lane < 16 && valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int key = __shfl(slot, leader, 64);
+        const bool in = valid && slot == key;
+        todo &= ~__ballot(lane < 16 && in);
+        float Lsm[PS];
+#pragma unroll
+        for (int a = 0; a < PS; ++a) Lsm[a] = in ? Ls[a] : 0.f;
+        float b[NT][NK];
+        mfma_load_b<PS, PA, NC, NT>(Ff + (size_t)key * P * NC, q, col, b);
+        mf4 cm[NT];
+        mfma_tile<PS, PA, NT>(b, Lsm, Lt, Lpv, q, cm);
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+            const int r = 4 * q + ii;
+            const float rgr = __shfl(gr, r, 64), rgi = __shfl(gi, r, 64);
+            const int rin = __shfl((int)in, r, 64);
+            const long long re = __shfl(e, r, 64);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const float v = cm[t][ii];
+                const float pv = __shfl_xor(v, 1, 64);
+                const int cg = 16 * t + col;
+                if (rin && cg < NC)
+                    pf[(size_t)re * NC + cg] = (col & 1) == 0 ? v * rgr - pv * rgi : pv * rgi + v * rgr;
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- gradients
 
 // d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
@@ -1860,7 +1937,7 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
         maxs = std::max(maxs, (size_t)hp.L[d].nslots);
         tot += (size_t)hp.L[d].nslots;
     }
-    need += (store ? tot : 2 * maxs) * hp.P * rb * ce + (size_t)p.max_pairs * ce;
+    need += (store ? tot : 2 * maxs) * hp.P * rb * ce + (size_t)p.max_pairs * rb * ce;
     if (p.ws_limit && p.tree_bytes + need > p.ws_limit) return hipErrorOutOfMemory;
     auto alloc = [&](size_t bytes, void** out) -> hipError_t {
         if (bytes == 0) bytes = 16;
@@ -1878,7 +1955,7 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     if ((e = alloc((size_t)hp.n * 3 * sizeof(double), &gm)) != hipSuccess) return e;
     p.grad_m = (double*)gm;
     p.pval = nullptr;
-    if (p.max_pairs > 0 && (e = alloc((size_t)p.max_pairs * ce, &p.pval)) != hipSuccess) return e;
+    if (p.max_pairs > 0 && (e = alloc((size_t)p.max_pairs * rb * ce, &p.pval)) != hipSuccess) return e;
     if (store) {
         for (int d = 3; d <= D; ++d)
             if ((e = alloc((size_t)hp.L[d].nslots * hp.P * rb * ce, &p.F[d])) != hipSuccess) return e;
@@ -2082,14 +2159,21 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                         done = true;
                     }
                 }
-                if constexpr (RB == 1) {
-                    if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
+                if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
+                    if constexpr (RB == 1) {
                         k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord), kBlock, 0, st>>>(
                             kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
-                        k_cousin_pairs_sum<T><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval,
-                                                                               (C*)p.out_m);
+                        done = true;
+                    } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
+                        const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;
+                        k_cousin_pairs_values_mfma<PS, PA, RB>
+                            <<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
+                                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
                         done = true;
                     }
+                    if (done)
+                        k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval,
+                                                                                   (C*)p.out_m);
                 }
                 if (done) {
                 } else if (p.L[d].use_pairs)

@@ -86,14 +86,7 @@ int64_t find_prefix(const std::vector<uint64_t>& v, uint64_t key)
     return (int64_t)(it - v.begin());
 }
 
-// Device bytes all cousin-target pair tables together may take
-// (IFGF_PAIR_BUDGET_MB, default 6144).
-double pair_budget_bytes()
-{
-    const char* e = std::getenv("IFGF_PAIR_BUDGET_MB");
-    double mb = e ? std::atof(e) : 6144.0;
-    return mb * 1024.0 * 1024.0;
-}
+
 
 // Slot of cone (cell, is) of box b, or -1 (host twin of the device lookup).
 int32_t host_lookup(const HostLevel& L, int64_t b, int cell, int is)
@@ -367,7 +360,7 @@ void build_frames(HostPlan& hp, int d)
 
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
                             int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
-                            HostPlan& hp,
+                            double pair_budget, HostPlan& hp,
                             ifgf_status& code)
 {
     auto t0 = std::chrono::steady_clock::now();
@@ -768,18 +761,13 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
             double npairs = 0.0;
             for (int64_t T = 0; T < L.nbox; ++T)
                 npairs += (double)(L.box_start[T + 1] - L.box_start[T]) * (L.cou_start[T + 1] - L.cou_start[T]);
-            if (used + npairs * per > pair_budget_bytes()) break;
-            used += npairs * per;
+            // the table with its cone-ordered copy (two-phase evaluation) if
+            // both fit, else the table alone, else no further levels
+            const bool both = ord_elem_bytes > 0.0 && used + npairs * (per + ord_elem_bytes) <= pair_budget;
+            if (!both && used + npairs * per > pair_budget) break;
+            used += npairs * (both ? per + ord_elem_bytes : per);
             build_pairs(hp, d);
-        }
-        // cone-ordered copies for the two-phase evaluation, in what is left
-        for (int d = 3; d <= D && ord_elem_bytes > 0.0; ++d) {
-            HostLevel& L = hp.L[d];
-            if (!L.use_pairs) break;
-            const double extra = (double)L.pr_slot.size() * ord_elem_bytes;
-            if (used + extra > pair_budget_bytes()) continue;
-            used += extra;
-            build_pair_order(L);
+            if (both) build_pair_order(L);
         }
     }
 

@@ -351,24 +351,24 @@ def test_cousin_eval_mfma_on_off(torch, monkeypatch, nrhs):
     monkeypatch.delenv("IFGF_COUSIN_MFMA")
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_cousin_two_phase_on_off(torch, monkeypatch, prec):
-    """One right-hand side: cousin-target interpolation in two phases (pairs
-    in cone order, then per-target sums; default) and in one
-    (IFGF_COUSIN_TWO_PHASE=0) both match the oracle, forward and adjoint,
-    including boxes with more than 16 points."""
+@pytest.mark.parametrize("prec,nrhs", [("mixed", 1), ("fp64", 1), ("mixed", 4), ("mixed", 16), ("fp64", 4)])
+def test_cousin_two_phase_on_off(torch, monkeypatch, prec, nrhs):
+    """Cousin-target interpolation in two phases (pairs in cone order --
+    on the matrix cores for batched FP32 -- then per-target sums; default)
+    and in one (IFGF_COUSIN_TWO_PHASE=0) both match the oracle, forward and
+    adjoint, including boxes with more than 16 points."""
     pts_cases = ((inputs.cube_sphere(20), 5.0 * math.pi),
                  (np.concatenate([inputs.random_box_points(3000, 8), 0.05 * inputs.random_box_points(300, 9)]), 7.0))
     tol = FP64_TOL if prec == "fp64" else MIXED_TOL
     for pts, k in pts_cases:
-        a = inputs.densities(19, 1, pts.shape[0])
+        a = inputs.densities(19, nrhs, pts.shape[0])
         ac = a if prec == "fp64" else as_c64(a)
         ref = oracle.ifgf(pts, ac, k)["out"]
         ref_adj = np.conj(oracle.ifgf(pts, np.conj(ac), k)["out"])
         outs = {}
         for flag in ("1", "0"):
             monkeypatch.setenv("IFGF_COUSIN_TWO_PHASE", flag)
-            plan = make_plan(pts, k, prec, max_nrhs=1)
+            plan = make_plan(pts, k, prec, max_nrhs=16)
             assert sum(plan.stats()["pairs_tabulated"]) > 0
             outs[flag] = plan.apply(dev(torch, a, prec)).cpu().numpy()
             adj = plan.adjoint(dev(torch, a, prec)).cpu().numpy()
