@@ -57,6 +57,16 @@ __device__ inline int xcd_block(int b, int nb)
     return x * per + (x < rem ? x : rem) + l;
 }
 
+// Orders the LDS accesses of one wavefront (which the LDS executes in issue
+// order) without waiting for outstanding global loads, so prefetches stay in
+// flight across it.
+__device__ inline void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Parent slot visited at position i of a child-to-parent launch: with
 // ORDERED the box tiles' order (blocks of boxes, one parent cone after the
 // other), so that neighbouring work shares frames in cache; else slot order
@@ -883,7 +893,8 @@ __device__ inline void mfma_epilogue(const mf4* c, int q, int col, int t0, int c
 }
 
 template <int PS, int PA, int RB>
-__global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RB >= 16 ? 3 : 4)))
+k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                  const cpx<float>* __restrict__ Fc,
                                                                  cpx<float>* __restrict__ Fp)
 {
@@ -895,10 +906,14 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
     __shared__ float accs[W][P * NC];
-    __shared__ int ents[W][8 * G];             // (octant << 8) | group
-    __shared__ int entcs[W][8 * G];            // child slot of the entry, -1 missing
+    constexpr int ME = 64;                     // entries looked up at once
+    __shared__ int sgo[W][9];                  // first entry of each octant
+    __shared__ int entcs[W][ME];               // child slot of the entry, -1 missing
+    __shared__ int entf[W][ME];                // its frame
+    __shared__ int entr[W][ME];                // its rows: first | count << 8 (group order)
     __shared__ int rown[W][P];                 // point of each row of the current group
     __shared__ float rre[W][P], rim[W][P];     // its ratio
+    __shared__ float rts[W][P], rtt[W][P], rtp[W][P];  // its local coordinates
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -927,60 +942,100 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma(KernelConsts kc
         if (lane >= dd) incl += y;
     }
     const int nent = __shfl(incl, 7, 64);
-    if (lane < 8)
-        for (int g = 0; g < ngo; ++g) ents[wv][incl - ngo + g] = (lane << 8) | g;
-    __threadfence_block();
-    for (int e = lane; e < nent; e += 64) {
-        const int o = ents[wv][e] >> 8, g = ents[wv][e] & 255;
+    if (lane < 8) sgo[wv][lane] = incl - ngo;
+    if (lane == 0) sgo[wv][8] = nent;
+    wave_lds_fence();
+
+    // loads of entry e: B operands (raw) and its rows' point data; those of
+    // the next entry are issued while the current entry's tiles run
+    constexpr int RPL = (P + 63) / 64;
+    float bn[NT][NK];
+    int pn[RPL];
+    float pt[RPL][3], pg[RPL][2];
+    auto fetch = [&](int e) {
+        const int f = entf[wv][e];
+        const int cs = entcs[wv][e];
+        mfma_load_b<PS, PA, NC, NT>(F + (size_t)(cs >= 0 ? cs : 0) * P * NC, q, col, bn);
+        const uint8_t* ord = Lc.fr_order + (size_t)f * P;
+        const int g0 = entr[wv][e] & 255, cnt = entr[wv][e] >> 8;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+            int r = lane + 64 * h;
+            r = r < cnt ? r : 0;
+            const int nu = ord[g0 + r];
+            const size_t ee = (size_t)f * P + nu;
+            pn[h] = nu;
+            pt[h][0] = frt[3 * ee];
+            pt[h][1] = frt[3 * ee + 1];
+            pt[h][2] = frt[3 * ee + 2];
+            pg[h][0] = frr[2 * ee];
+            pg[h][1] = frr[2 * ee + 1];
+        }
+    };
+    for (int e0 = 0; e0 < nent; e0 += ME) {
+    const int ne = nent - e0 < ME ? nent - e0 : ME;
+    for (int e = lane; e < ne; e += 64) {
+        const int E = e0 + e;
+        int o = 0;
+#pragma unroll
+        for (int oo = 1; oo < 8; ++oo) o = sgo[wv][oo] <= E ? oo : o;
+        const int g = E - sgo[wv][o];
         const int f = Lc.pframe[(size_t)sp * 8 + o];
         const int k = Lc.child_of[(size_t)j * 8 + o];
         const unsigned key = Lc.fr_gkey[(size_t)f * G + g];
         const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
         entcs[wv][e] = lookup(Lc, k, cell, is);
-    }
-    __threadfence_block();
-
-    for (int e = 0; e < nent; ++e) {
-        const int o = ents[wv][e] >> 8, g = ents[wv][e] & 255;
-        const int f = Lc.pframe[(size_t)sp * 8 + o];
-        const int cs = entcs[wv][e];
-        const uint8_t* ord = Lc.fr_order + (size_t)f * P;
+        entf[wv][e] = f;
         const int g0 = Lc.fr_goff[(size_t)f * (G + 1) + g], g1 = Lc.fr_goff[(size_t)f * (G + 1) + g + 1];
-        const int cnt = g1 - g0;
+        entr[wv][e] = g0 | ((g1 - g0) << 8);
+    }
+    wave_lds_fence();
+    fetch(0);
+    for (int e = 0; e < ne; ++e) {
+        const int cs = entcs[wv][e];
+        const int cnt = entr[wv][e] >> 8;
+        float b[NT][NK];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int k = 0; k < NK; ++k) b[t][k] = bn[t][k];
+        // rows of the group: their points, local coordinates and ratios
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+            const int r = lane + 64 * h;
+            if (r < cnt) {
+                rown[wv][r] = pn[h];
+                rts[wv][r] = pt[h][0];
+                rtt[wv][r] = pt[h][1];
+                rtp[wv][r] = pt[h][2];
+                rre[wv][r] = pg[h][0];
+                rim[wv][r] = conj_sign * pg[h][1];
+            }
+        }
+        if (e + 1 < ne) fetch(e + 1);
         if (cs < 0) {
             if (lane == 0) atomicAdd(kc.miss, (unsigned long long)cnt);
+            wave_lds_fence();
             continue;
         }
-        // rows of the group: their points and ratios
-        for (int r = lane; r < cnt; r += 64) {
-            const int nu = ord[g0 + r];
-            const size_t ee = (size_t)f * P + nu;
-            rown[wv][r] = nu;
-            rre[wv][r] = frr[2 * ee];
-            rim[wv][r] = conj_sign * frr[2 * ee + 1];
-        }
-        float b[NT][NK];
-        mfma_load_b<PS, PA, NC, NT>(F + (size_t)cs * P * NC, q, col, b);
-        __threadfence_block();
+        wave_lds_fence();
         for (int t0 = 0; t0 < cnt; t0 += 16) {
             float Ls[PS], Lt[PA], Lpv[PA];
             const int rr = t0 + row;
-            if (rr < cnt) {
-                const size_t ee = (size_t)f * P + rown[wv][rr];
-                lagrange<float, PS>((double)frt[3 * ee], kc.cs, Ls);
-                lagrange<float, PA>((double)frt[3 * ee + 1], kc.ca, Lt);
-                lagrange<float, PA>((double)frt[3 * ee + 2], kc.ca, Lpv);
-            } else {
+            const int rc = rr < cnt ? rr : 0;
+            lagrange<float, PS>((double)rts[wv][rc], kc.cs, Ls);
+            lagrange<float, PA>((double)rtt[wv][rc], kc.ca, Lt);
+            lagrange<float, PA>((double)rtp[wv][rc], kc.ca, Lpv);
+            if (rr >= cnt) {
 #pragma unroll
                 for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
-#pragma unroll
-                for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
             }
             mf4 c[NT];
             mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
             mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
-            __threadfence_block();
         }
+        wave_lds_fence();
+    }
     }
     float* out = (float*)(Fp + (size_t)sp * P * RB);
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
@@ -1297,15 +1352,6 @@ k_child_to_parent_quads(KernelConsts kc, LevelDev Lc, LevelDev Lp,
     }
 }
 
-// Orders the LDS accesses of one wavefront (which the LDS executes in issue
-// order) without waiting for outstanding global loads, so prefetches stay in
-// flight across it.
-__device__ inline void wave_lds_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Child-to-parent interpolation batched over boxes on the matrix cores
 // (FP32).  A frame depends only on the parent cone and the octant, so the
