@@ -20,6 +20,7 @@ constexpr int kMaxRhsPass = 16;    // right-hand sides handled by one kernel pas
 constexpr double kDilateTol = 1e-9;
 constexpr int kMaxFrameGroups = 32;  // distinct child cones one frame may touch
 constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone per box tile
+constexpr int kPairQuad = 4;        // cone-ordered cousin pairs share a cone in runs of this length
 // child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)
 enum { kC2PGeometry = 0, kC2PFrames = 1, kC2PLds = 2, kC2PMfma = 3, kC2PMfmaGeometry = 4, kC2PBoxes = 5,
        kC2PQuads = 6, kC2PLdsTiled = 7, kC2PVariants = 8 };
@@ -171,7 +172,7 @@ struct HostLevel {
     std::vector<int32_t> pr_slot;             // [npairs]
     std::vector<double> pr_t;                 // [3][npairs] (structure of arrays)
     std::vector<double> pr_g;                 // [2][npairs]
-    std::vector<int32_t> pr_order;            // pairs with a cone, ordered by slot
+    std::vector<int32_t> pr_order;            // pairs with a cone, ordered by slot (-1: padding)
     std::vector<int32_t> pro_slot;            // their slots, in that order
     std::vector<double> pro_t;                // [3][npairs with a cone], in that order
     std::vector<double> pro_g;                // [2][npairs with a cone], in that order

@@ -444,21 +444,74 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values(KernelConsts kc,
                                                                 const cpx<T>* __restrict__ F,
                                                                 cpx<T>* __restrict__ pval)
 {
+    // kPairQuad consecutive entries share a cone: one thread interpolates them
+    // together, reading each cone value once (phi, then theta, then s)
     constexpr int P = PS * PA * PA;
-    const long long i = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    constexpr int QR = kPairQuad;
+    const long long i0 = ((long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) * QR;
     const long long no = L.npairs_ord;
-    if (i >= no) return;
-    const int slot = L.pro_slot[i];
+    if (i0 >= no) return;
+    const int slot = L.pro_slot[i0];
     const T* pt = (const T*)L.pro_t;
     const T* pg = (const T*)L.pro_g;
-    T Ls[PS], Lt[PA], Lp[PA];
-    lagrange<T, PS>((double)pt[i], kc.cs, Ls);
-    lagrange<T, PA>((double)pt[no + i], kc.ca, Lt);
-    lagrange<T, PA>((double)pt[2 * no + i], kc.ca, Lp);
-    cpx<T> v[1];
-    interp<T, PS, PA, 1>(F + (size_t)slot * P, Ls, Lt, Lp, v);
-    const T gr = pg[i], gi = (kc.kappa < 0.0 ? (T)-1 : (T)1) * pg[no + i];
-    pval[L.pr_order[i]] = cpx<T>{v[0].x * gr - v[0].y * gi, v[0].x * gi + v[0].y * gr};
+    T Ls[QR][PS], Lt[QR][PA], Lq[QR][PA];
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+        lagrange<T, PS>((double)pt[i0 + r], kc.cs, Ls[r]);
+        lagrange<T, PA>((double)pt[no + i0 + r], kc.ca, Lt[r]);
+        lagrange<T, PA>((double)pt[2 * no + i0 + r], kc.ca, Lq[r]);
+    }
+    const cpx<T>* Fs = F + (size_t)slot * P;
+    cpx<T> U[QR][PS];
+#pragma unroll
+    for (int r = 0; r < QR; ++r)
+#pragma unroll
+        for (int a = 0; a < PS; ++a) U[r][a] = cpx<T>{(T)0, (T)0};
+    // one phi-row of the cone per step; the theta loop stays rolled (its
+    // weights shift through registers) so that the loads are issued row by
+    // row instead of all at once
+#pragma unroll
+    for (int a = 0; a < PS; ++a) {
+        T lt[QR][PA];
+#pragma unroll
+        for (int r = 0; r < QR; ++r)
+#pragma unroll
+            for (int c = 0; c < PA; ++c) lt[r][c] = Lt[r][c];
+        const cpx<T>* Fa = Fs + a * PA * PA;
+#pragma unroll 1
+        for (int b = 0; b < PA; ++b) {
+            cpx<T> fv[PA];
+#pragma unroll
+            for (int c = 0; c < PA; ++c) fv[c] = Fa[b * PA + c];
+#pragma unroll
+            for (int r = 0; r < QR; ++r) {
+                T sr = (T)0, si = (T)0;
+#pragma unroll
+                for (int c = 0; c < PA; ++c) {
+                    sr += fv[c].x * Lq[r][c];
+                    si += fv[c].y * Lq[r][c];
+                }
+                U[r][a].x += sr * lt[r][0];
+                U[r][a].y += si * lt[r][0];
+#pragma unroll
+                for (int c = 0; c + 1 < PA; ++c) lt[r][c] = lt[r][c + 1];
+            }
+        }
+    }
+    const T sg = kc.kappa < 0.0 ? (T)-1 : (T)1;
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+        const int e = L.pr_order[i0 + r];
+        if (e < 0) continue;
+        T vr = (T)0, vi = (T)0;
+#pragma unroll
+        for (int a = 0; a < PS; ++a) {
+            vr += U[r][a].x * Ls[r][a];
+            vi += U[r][a].y * Ls[r][a];
+        }
+        const T gr = pg[i0 + r], gi = sg * pg[no + i0 + r];
+        pval[e] = cpx<T>{vr * gr - vi * gi, vr * gi + vi * gr};
+    }
 }
 
 template <typename T, int RB>
@@ -1769,7 +1822,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConst
     lagrange<float, PA>((double)pt[no + ic], kc.ca, Lt);
     lagrange<float, PA>((double)pt[2 * no + ic], kc.ca, Lpv);
     const float gr = pg[ic], gi = (kc.kappa < 0.0 ? -1.f : 1.f) * pg[no + ic];
-    const long long e = L.pr_order[ic];
+    const long long e = L.pr_order[ic];       // -1: a placeholder, not stored
     const float* Ff = (const float*)F;
     float* pf = (float*)pval;
     unsigned long long todo = __ballot(lane < 16 && valid);
@@ -1796,7 +1849,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConst
                 const float v = cm[t][ii];
                 const float pv = __shfl_xor(v, 1, 64);
                 const int cg = 16 * t + col;
-                if (rin && cg < NC)
+                if (rin && re >= 0 && cg < NC)
                     pf[(size_t)re * NC + cg] = (col & 1) == 0 ? v * rgr - pv * rgi : pv * rgi + v * rgr;
             }
         }
@@ -2207,8 +2260,9 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                 }
                 if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
                     if constexpr (RB == 1) {
-                        k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord), kBlock, 0, st>>>(
-                            kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+                        k_cousin_pairs_values<T, PS, PA>
+                            <<<grid_for((size_t)p.L[d].npairs_ord / kPairQuad), kBlock, 0, st>>>(
+                                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
                         done = true;
                     } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
                         const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;

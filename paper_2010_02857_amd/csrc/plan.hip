@@ -142,24 +142,34 @@ void build_pairs(HostPlan& hp, int d)
 
 // The pairs with a cone, ordered by cone slot (stable: by target box, cousin
 // and target), with a copy of their slot, local coordinates and centred
-// factor in that order, for the two-phase evaluation.
+// factor in that order, for the two-phase evaluation.  Each slot's run is
+// padded to a multiple of kPairQuad with placeholder entries (place -1, the
+// slot's own cone, coordinates 0, factor 0), so that kPairQuad consecutive
+// entries always share a cone.
 void build_pair_order(HostLevel& L)
 {
     const int64_t np = (int64_t)L.pr_slot.size();
+    std::vector<int64_t> cnt((size_t)L.nslots, 0);
+    for (int64_t e = 0; e < np; ++e)
+        if (L.pr_slot[e] >= 0) cnt[(size_t)L.pr_slot[e]]++;
     std::vector<int64_t> start((size_t)L.nslots + 1, 0);
-    for (int64_t e = 0; e < np; ++e)
-        if (L.pr_slot[e] >= 0) start[(size_t)L.pr_slot[e] + 1]++;
-    for (int64_t s = 0; s < L.nslots; ++s) start[(size_t)s + 1] += start[(size_t)s];
+    for (int64_t s = 0; s < L.nslots; ++s)
+        start[(size_t)s + 1] = start[(size_t)s] + (cnt[(size_t)s] + kPairQuad - 1) / kPairQuad * kPairQuad;
     const int64_t no = start[(size_t)L.nslots];
-    L.pr_order.assign((size_t)no, 0);
-    for (int64_t e = 0; e < np; ++e)
-        if (L.pr_slot[e] >= 0) L.pr_order[(size_t)start[(size_t)L.pr_slot[e]]++] = (int32_t)e;
-    L.pro_slot.resize((size_t)no);
-    L.pro_t.resize((size_t)3 * no);
-    L.pro_g.resize((size_t)2 * no);
+    L.pr_order.assign((size_t)no, -1);
+    L.pro_slot.assign((size_t)no, 0);
+    for (int64_t s = 0; s < L.nslots; ++s)
+        for (int64_t i = start[(size_t)s]; i < start[(size_t)s + 1]; ++i) L.pro_slot[(size_t)i] = (int32_t)s;
+    {
+        std::vector<int64_t> pos(start.begin(), start.end() - 1);
+        for (int64_t e = 0; e < np; ++e)
+            if (L.pr_slot[e] >= 0) L.pr_order[(size_t)pos[(size_t)L.pr_slot[e]]++] = (int32_t)e;
+    }
+    L.pro_t.assign((size_t)3 * no, 0.0);
+    L.pro_g.assign((size_t)2 * no, 0.0);
     parallel_for(no, [&](int64_t i) {
         const int64_t e = L.pr_order[(size_t)i];
-        L.pro_slot[(size_t)i] = L.pr_slot[(size_t)e];
+        if (e < 0) return;
         for (int c = 0; c < 3; ++c) L.pro_t[(size_t)c * no + i] = L.pr_t[(size_t)c * np + e];
         for (int c = 0; c < 2; ++c) L.pro_g[(size_t)c * no + i] = L.pr_g[(size_t)c * np + e];
     }, 4096);
