@@ -179,8 +179,16 @@ void build_pair_order(HostLevel& L)
 int64_t tile_box_block()
 {
     const char* e = std::getenv("IFGF_TILE_BLOCK");
-    const int64_t v = e ? std::atoll(e) : 64;
+    const int64_t v = e ? std::atoll(e) : 16384;
     return v < 1 ? 1 : v;
+}
+
+// Whether the boxes of one cone are ordered by child mask before they are cut
+// into tiles (IFGF_TILE_SORT=0 keeps Morton order).
+int tile_sort()
+{
+    const char* e = std::getenv("IFGF_TILE_SORT");
+    return e ? std::atoi(e) : 1;
 }
 
 // Device bytes a level's frame table may take when its frames are not shared
@@ -314,11 +322,14 @@ void build_frames(HostPlan& hp, int d)
         for (int nu = 0; nu < P; ++nu) ord[cnt[grp[nu]]++] = (uint8_t)nu;
     }, 256);
     // box tiles.  The parent boxes are cut into blocks of consecutive
-    // (Morton-ordered) boxes; within a block the slots are sorted by cone
-    // (boxes in order) and every run of one cone is cut into tiles.  Tiles of
-    // one block run close together in time and share the block's child cone
-    // values in cache; the block size trades that locality against the fill
-    // of the tiles.
+    // (Morton-ordered) boxes; within a block the slots are sorted by cone,
+    // then by the mask of children their box has, and every run of one cone
+    // is cut into tiles.  A tile runs one pass per octant that any of its
+    // boxes has a child in, so boxes with the same children in one tile
+    // leave fewer columns of those passes empty (near a surface a box has 3-4
+    // of its 8 children).  Large blocks give long runs, hence full tiles of
+    // like masks; small blocks keep the child cones a block reads together
+    // in cache.
     const int64_t blk = tile_box_block();
     const int64_t nblk = (Lp.nbox + blk - 1) / blk;
     std::vector<std::vector<int32_t>> bslots(nblk);
@@ -327,8 +338,18 @@ void build_frames(HostPlan& hp, int d)
         const int64_t j0 = b * blk, j1 = std::min<int64_t>(Lp.nbox, j0 + blk);
         std::vector<int32_t>& v = bslots[b];
         for (int64_t sl = Lp.slot_start[j0]; sl < Lp.slot_start[j1]; ++sl) v.push_back((int32_t)sl);
-        std::stable_sort(v.begin(), v.end(),
-                         [&](int32_t x, int32_t y) { return Lp.slot_cone[x] < Lp.slot_cone[y]; });
+        auto mask = [&](int32_t sl) {
+            int m = 0;
+            for (int o = 0; o < 8; ++o) m |= (L.child_of[(size_t)Lp.slot_box[sl] * 8 + o] >= 0) << o;
+            return m;
+        };
+        if (tile_sort())
+            std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
+                return Lp.slot_cone[x] != Lp.slot_cone[y] ? Lp.slot_cone[x] < Lp.slot_cone[y] : mask(x) < mask(y);
+            });
+        else
+            std::stable_sort(v.begin(), v.end(),
+                             [&](int32_t x, int32_t y) { return Lp.slot_cone[x] < Lp.slot_cone[y]; });
         int64_t nt = 0;
         for (size_t i = 0; i < v.size();) {
             size_t e = i;
