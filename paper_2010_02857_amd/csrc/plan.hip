@@ -188,7 +188,7 @@ int64_t tile_box_block()
 int tile_sort()
 {
     const char* e = std::getenv("IFGF_TILE_SORT");
-    return e ? std::atoi(e) : 1;
+    return e ? std::atoi(e) : 2;
 }
 
 // Device bytes a level's frame table may take when its frames are not shared
@@ -332,54 +332,113 @@ void build_frames(HostPlan& hp, int d)
     // in cache.
     const int64_t blk = tile_box_block();
     const int64_t nblk = (Lp.nbox + blk - 1) / blk;
-    std::vector<std::vector<int32_t>> bslots(nblk);
+    const int mode = tile_sort();
+    std::vector<std::vector<int32_t>> btiles(nblk);   // kBoxTile entries per tile, -1 padded
     std::vector<int64_t> bt(nblk + 1, 0);
     parallel_for(nblk, [&](int64_t b) {
         const int64_t j0 = b * blk, j1 = std::min<int64_t>(Lp.nbox, j0 + blk);
-        std::vector<int32_t>& v = bslots[b];
+        std::vector<int32_t> v;
         for (int64_t sl = Lp.slot_start[j0]; sl < Lp.slot_start[j1]; ++sl) v.push_back((int32_t)sl);
         auto mask = [&](int32_t sl) {
             int m = 0;
             for (int o = 0; o < 8; ++o) m |= (L.child_of[(size_t)Lp.slot_box[sl] * 8 + o] >= 0) << o;
             return m;
         };
-        if (tile_sort())
-            std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
-                return Lp.slot_cone[x] != Lp.slot_cone[y] ? Lp.slot_cone[x] < Lp.slot_cone[y] : mask(x) < mask(y);
-            });
-        else
-            std::stable_sort(v.begin(), v.end(),
-                             [&](int32_t x, int32_t y) { return Lp.slot_cone[x] < Lp.slot_cone[y]; });
-        int64_t nt = 0;
+        std::vector<int> mk(v.size());
+        std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
+            if (Lp.slot_cone[x] != Lp.slot_cone[y]) return Lp.slot_cone[x] < Lp.slot_cone[y];
+            return mode != 0 && mask(x) < mask(y);
+        });
+        for (size_t k = 0; k < v.size(); ++k) mk[k] = mask(v[k]);
+        std::vector<int32_t>& out = btiles[b];
+        // a run's tiles as kBoxTile entries each (-1 padded); cost = the
+        // octant passes they run
+        auto emit = [&](std::vector<int32_t>& dst, const int32_t* sl, int n) {
+            for (int k = 0; k < kBoxTile; ++k) dst.push_back(k < n ? sl[k] : -1);
+        };
+        auto cost = [&](const std::vector<int32_t>& w) {
+            int64_t c = 0;
+            for (size_t t = 0; t < w.size(); t += kBoxTile) {
+                int m = 0;
+                for (int k = 0; k < kBoxTile; ++k)
+                    if (w[t + k] >= 0) m |= mask(w[t + k]);
+                c += __builtin_popcount(m);
+            }
+            return c;
+        };
+        struct Open {
+            int m, n;
+            int32_t s[kBoxTile];
+        };
+        std::vector<Open> open;
+        std::vector<size_t> rem;
+        std::vector<int32_t> cut, grp;
         for (size_t i = 0; i < v.size();) {
             size_t e = i;
             while (e < v.size() && Lp.slot_cone[v[e]] == Lp.slot_cone[v[i]]) ++e;
-            nt += (int64_t)((e - i + kBoxTile - 1) / kBoxTile);
+            // the run cut in order (by child mask unless mode 0)
+            cut.clear();
+            for (size_t k0 = i; k0 < e; k0 += kBoxTile) emit(cut, &v[k0], (int)std::min<size_t>(kBoxTile, e - k0));
+            if (mode != 2 || e - i <= (size_t)kBoxTile) {
+                out.insert(out.end(), cut.begin(), cut.end());
+                i = e;
+                continue;
+            }
+            // or: full tiles of one child mask, then the rest, largest masks
+            // first, each to the open tile whose octants it widens least;
+            // the run keeps whichever of the two runs fewer passes
+            grp.clear();
+            rem.clear();
+            for (size_t a = i; a < e;) {
+                size_t z = a;
+                while (z < e && mk[z] == mk[a]) ++z;
+                size_t a1 = a;
+                for (; a1 + kBoxTile <= z; a1 += kBoxTile) emit(grp, &v[a1], kBoxTile);
+                for (; a1 < z; ++a1) rem.push_back(a1);
+                a = z;
+            }
+            std::stable_sort(rem.begin(), rem.end(), [&](size_t x, size_t y) {
+                return __builtin_popcount(mk[x]) > __builtin_popcount(mk[y]);
+            });
+            open.clear();
+            for (size_t x : rem) {
+                int best = -1, bg = 9;
+                for (int t = 0; t < (int)open.size(); ++t) {
+                    if (open[t].n == kBoxTile) continue;
+                    const int g = __builtin_popcount(open[t].m | mk[x]) - __builtin_popcount(open[t].m);
+                    if (g < bg || (g == bg && open[t].n > open[best].n)) {
+                        best = t;
+                        bg = g;
+                    }
+                }
+                if (best < 0) {
+                    open.push_back(Open{0, 0, {}});
+                    best = (int)open.size() - 1;
+                }
+                open[best].m |= mk[x];
+                open[best].s[open[best].n++] = v[x];
+            }
+            for (const Open& t : open) emit(grp, t.s, t.n);
+            const std::vector<int32_t>& pick = cost(grp) < cost(cut) ? grp : cut;
+            out.insert(out.end(), pick.begin(), pick.end());
             i = e;
         }
-        bt[b + 1] = nt;
+        bt[b + 1] = (int64_t)(out.size() / kBoxTile);
     }, 1);
     for (int64_t b = 0; b < nblk; ++b) bt[b + 1] += bt[b];
     L.ntiles = bt[nblk];
     L.bt_slot.assign((size_t)L.ntiles * kBoxTile, -1);
     L.bt_frame.assign((size_t)L.ntiles * 8, -1);
     parallel_for(nblk, [&](int64_t b) {
-        const std::vector<int32_t>& v = bslots[b];
-        int64_t t = bt[b];
-        for (size_t i = 0; i < v.size();) {
-            size_t e = i;
-            while (e < v.size() && Lp.slot_cone[v[e]] == Lp.slot_cone[v[i]]) ++e;
-            for (size_t k0 = i; k0 < e; k0 += kBoxTile, ++t) {
-                const size_t k1 = std::min(e, k0 + kBoxTile);
-                for (size_t k = k0; k < k1; ++k) {
-                    const int32_t sl = v[k];
-                    L.bt_slot[(size_t)t * kBoxTile + (k - k0)] = sl;
-                    for (int o = 0; o < 8; ++o)
-                        if (L.pframe[(size_t)sl * 8 + o] >= 0) L.bt_frame[(size_t)t * 8 + o] = L.pframe[(size_t)sl * 8 + o];
-                }
+        const std::vector<int32_t>& w = btiles[b];
+        std::copy(w.begin(), w.end(), L.bt_slot.begin() + bt[b] * kBoxTile);
+        for (int64_t t = bt[b]; t < bt[b + 1]; ++t)
+            for (int k = 0; k < kBoxTile; ++k) {
+                const int32_t sl = L.bt_slot[(size_t)t * kBoxTile + k];
+                if (sl < 0) continue;
+                for (int o = 0; o < 8; ++o)
+                    if (L.pframe[(size_t)sl * 8 + o] >= 0) L.bt_frame[(size_t)t * 8 + o] = L.pframe[(size_t)sl * 8 + o];
             }
-            i = e;
-        }
     }, 1);
     L.slot_order.clear();
     L.slot_order.reserve((size_t)Lp.nslots);
