@@ -1551,6 +1551,19 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
         float accr[KC], acci[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) accr[k] = acci[k] = 0.f;
+        // octants in which a box of the pass has a child: the others would
+        // only add products with the zero cone
+        int pm = 0;
+        if constexpr (BX == 16) {
+            pm = 255;
+        } else {
+            const int bl = lane >> 3, o = lane & 7;
+            const bool has = lane < BX * 8 && b0 + bl < kBoxTile && kch[(b0 + bl) * 8 + o] >= 0;
+            const unsigned long long bal = __ballot(has);
+#pragma unroll
+            for (int k = 0; k < BX; ++k) pm |= (int)((bal >> (8 * k)) & 255ull);
+        }
+        auto live = [&](int o) { return sfr[o] >= 0 && ((pm >> o) & 1); };
         int o0 = 0;
         while (o0 < 8) {
             // a chunk of whole octants with at most ME entries
@@ -1583,13 +1596,20 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
                 ecs[i] = cs;
             }
             wave_lds_fence();
-            if (ne > 0) fetch_b(0);
             int o_pts = o0;
-            while (o_pts < o1 && sfr[o_pts] < 0) ++o_pts;
-            if (o_pts < o1) fetch_points(o_pts);
+            while (o_pts < o1 && !live(o_pts)) ++o_pts;
+            if (o_pts < o1) {
+                // (with all boxes in the pass, octants without entries are
+                // the only ones skipped, so the first live entry is 0)
+                fetch_b(BX == 16 ? 0 : sgo[o_pts] - e0);
+                fetch_points(o_pts);
+            }
             int ei = 0;
             for (int o = o0; o < o1; ++o) {
-                if (sfr[o] < 0) continue;
+                if (!live(o)) {
+                    if constexpr (BX < 16) ei = sgo[o + 1] - e0;
+                    continue;
+                }
                 // stage the frame's points: weights by group position, ratio and position by point
 #pragma unroll
                 for (int h = 0; h < RPL; ++h) {
@@ -1611,13 +1631,13 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
                         spos[pn[h]] = (uint8_t)r;
                     }
                 }
-                {
-                    int on = o + 1;
-                    while (on < o1 && sfr[on] < 0) ++on;
-                    if (on < o1) fetch_points(on);
-                }
+                int on = o + 1;
+                while (on < o1 && !live(on)) ++on;
+                if (on < o1) fetch_points(on);
                 wave_lds_fence();
                 const int e_end = sgo[o + 1] - e0;
+                // the entry after the octant's last: the next live octant's first
+                const int e_next = on < o1 ? sgo[on] - e0 : ne;
                 for (; ei < e_end; ++ei) {
                     const int info = einfo[ei];
                     const int g0 = info & 255, cnt = (info >> 8) & 255;
@@ -1626,7 +1646,8 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
                     for (int t = 0; t < NT; ++t)
 #pragma unroll
                         for (int k = 0; k < NK; ++k) b[t][k] = bn[t][k];
-                    if (ei + 1 < ne) fetch_b(ei + 1);
+                    const int en = (BX == 16 || ei + 1 < e_end) ? ei + 1 : e_next;
+                    if (en < ne) fetch_b(en);
                     for (int t0 = 0; t0 < cnt; t0 += 16) {
                         const int rr = t0 + row;
                         const int r = g0 + (rr < cnt ? rr : 0);
