@@ -11,8 +11,9 @@ reported separately (as the paper reports T_pre apart from T_acc).
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 Prints one JSON line.
 
-Profiling: `python bench.py --profile-commands DIR` prints the three
-rocprofv3 commands (kernel trace with stats; FETCH_SIZE; WRITE_SIZE) whose
+Profiling: `python bench.py --profile-commands DIR` prints the four
+rocprofv3 commands (kernel trace with stats; FETCH_SIZE; WRITE_SIZE; SQ
+instruction counters) whose
 outputs `python bench.py --summarize DIR` turns into the summaries under
 profiles/.  The counter runs also time a plain copy kernel of known size
 (--copy-calibration), whose counter readings give the bytes-per-KiB scale
@@ -54,6 +55,11 @@ def kernel_source_hash() -> str:
 WORKLOAD_TAG = "sphere393216"
 TRACE_ARGS = "--steps 5 --warmup 1 --no-extras --no-cpu-baseline"
 PMC_ARGS = "--steps 2 --warmup 1 --no-extras --no-cpu-baseline --copy-calibration"
+SQ_ARGS = "--steps 1 --warmup 1 --no-extras --no-cpu-baseline"
+SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VALU_MFMA_F32 SQ_VALU_MFMA_BUSY_CYCLES "
+               "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_INST_LDS")
+SIMDS = 1024                   # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9
 COPY_NUMEL = 64 << 20          # float32 elements read and written by the calibration copy
 
 
@@ -62,6 +68,7 @@ def profile_commands(d: str) -> list[str]:
         f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- python3 bench.py {TRACE_ARGS}",
         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- python3 bench.py {PMC_ARGS}",
         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- python3 bench.py {PMC_ARGS}",
+        f"rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d {d}/sq -o run -- python3 bench.py {SQ_ARGS}",
     ]
 
 
@@ -163,7 +170,54 @@ def summarize(d: str) -> int:
     with open(os.path.join(out_dir, f"traffic_{stage}_{WORKLOAD_TAG}.md"), "w") as fh:
         fh.write("\n".join(md))
     print(json.dumps(rec))
+    summarize_sq(d, cmds[3], rows)
     return 0
+
+
+def summarize_sq(d: str, cmd: str, trace_rows: list) -> None:
+    """profiles/sq_child_to_parent_<workload>.md: instruction counts of each
+    child-to-parent launch of one timed matvec (SQ counters, summed over the
+    chip), per evaluation and as a fraction of the chip's issue capacity over
+    the launch's duration in the kernel trace (a wave64 VALU instruction
+    occupies a SIMD for 4 cycles, a 16x16x4 FP32 MFMA for 32)."""
+    import collections
+    import csv
+    from paper_2010_02857_amd import ifgf, inputs
+    w = inputs.WORKLOADS[2]
+    st = ifgf.Plan(w.points(), w.kappa, host_only=True).stats()
+    evals = st["n_parent_evals"]
+    D = st["D"]
+    rows = _timed(list(csv.DictReader(open(_find(os.path.join(d, "sq"), "counter_collection.csv")))),
+                  _steps(SQ_ARGS))
+    per = collections.OrderedDict()
+    for r in rows:
+        if "k_child_to_parent" not in r["Kernel_Name"]:
+            continue
+        e = per.setdefault(int(r["Dispatch_Id"]), {"name": _short(r["Kernel_Name"])})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    # durations of the same launches in the trace run (its first timed matvec)
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+           for r in sorted(trace_rows, key=lambda r: int(r["Dispatch_Id"])) if "k_child_to_parent" in r["Kernel_Name"]]
+    lines = [f"# Instruction mix of `child_to_parent`, {WORKLOAD_TAG} (mixed, 1 RHS)", "",
+             "Command (repository root):", "", "    " + cmd, "",
+             "One timed matvec; launches in order of the child level.  Per evaluation: lane instructions "
+             "(wave instructions x 64) per (parent interpolation point, child) evaluation.  Issue fractions: "
+             f"VALU = 4 x wave VALU instructions, MFMA = busy cycles, over {SIMDS} SIMDs x "
+             f"{CLOCK_HZ / 1e9:.1f} GHz x the launch's duration in the kernel trace.", "",
+             "| child level | kernel | ms | VALU / eval | LDS / eval | VALU issue | MFMA busy |",
+             "|---|---|---|---|---|---|---|"]
+    for i, (k, e) in enumerate(per.items()):
+        lvl = D - i
+        t = dur[i] if i < len(dur) else float("nan")
+        cap = SIMDS * CLOCK_HZ * t
+        ev = max(evals[lvl], 1)
+        lines.append(f"| {lvl} | `{e['name']}` | {t * 1e3:.3f} | {e.get('SQ_INSTS_VALU', 0) * 64 / ev:.0f} | "
+                     f"{e.get('SQ_INSTS_LDS', 0) * 64 / ev:.0f} | {4 * e.get('SQ_INSTS_VALU', 0) / cap:.2f} | "
+                     f"{e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / cap:.2f} |")
+    lines.append("")
+    with open(os.path.join(ROOT, "profiles", f"sq_child_to_parent_{WORKLOAD_TAG}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
 
 
 def stage_work(stats: dict, stage: str, nrhs: int, P: int, elem_bytes: int) -> tuple[float, float]:

@@ -1641,13 +1641,22 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
                 for (; ei < e_end; ++ei) {
                     const int info = einfo[ei];
                     const int g0 = info & 255, cnt = (info >> 8) & 255;
+                    // the entry's operands, taken over from the prefetch (the
+                    // empty asm makes them values of their own, so the wait
+                    // for their loads falls here and not before every tile),
+                    // then the loads of the next live entry (this entry's
+                    // again after the last: a load on every path keeps the
+                    // registers of both in place)
                     float b[NT][NK];
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
 #pragma unroll
-                        for (int k = 0; k < NK; ++k) b[t][k] = bn[t][k];
+                        for (int k = 0; k < NK; ++k) {
+                            b[t][k] = bn[t][k];
+                            asm volatile("" : "+v"(b[t][k]));
+                        }
                     const int en = (BX == 16 || ei + 1 < e_end) ? ei + 1 : e_next;
-                    if (en < ne) fetch_b(en);
+                    fetch_b(en < ne ? en : ei);
                     for (int t0 = 0; t0 < cnt; t0 += 16) {
                         const int rr = t0 + row;
                         const int r = g0 + (rr < cnt ? rr : 0);
