@@ -210,6 +210,15 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
                 if ((e = upload(p, H.bt_frame, &L.bt_frame)) != hipSuccess) return e;
                 if ((int64_t)H.slot_order.size() == hp.L[d - 1].nslots && !H.slot_order.empty())
                     if ((e = upload(p, H.slot_order, &L.slot_order)) != hipSuccess) return e;
+                if (!H.te_start.empty() && !H.te_info.empty()) {
+                    if ((e = upload(p, H.te_start, &L.te_start)) != hipSuccess) return e;
+                    if ((e = upload(p, H.te_go, &L.te_go)) != hipSuccess) return e;
+                    if ((e = upload(p, H.te_info, &L.te_info)) != hipSuccess) return e;
+                    if ((e = upload(p, H.te_cs, &L.te_cs)) != hipSuccess) return e;
+                    if ((e = upload(p, H.te_mask, &L.te_mask)) != hipSuccess) return e;
+                }
+                std::vector<int32_t>().swap(H.te_cs);
+                std::vector<int32_t>().swap(H.te_info);
             }
             // the host copies are no longer needed
             std::vector<double>().swap(H.fr_t);

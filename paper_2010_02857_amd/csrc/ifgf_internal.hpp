@@ -163,6 +163,13 @@ struct HostLevel {
     std::vector<int32_t> bt_slot;             // [ntiles][kBoxTile] parent slot, -1 pad
     std::vector<int32_t> bt_frame;            // [ntiles][8] frame of octant o, -1 none
     std::vector<int32_t> slot_order;          // [nslots_{d-1}] parent slots in tile order
+    // entries of the box tiles: (octant, group) pairs of the tile's frames in
+    // octant order, with their child slot in each of the tile's boxes
+    std::vector<int32_t> te_start;            // [ntiles + 1] first entry of the tile
+    std::vector<uint16_t> te_go;              // [ntiles][9] first entry of octant o, relative; [8] = count
+    std::vector<int32_t> te_info;             // [entries] g0 | cnt << 8 | o << 16
+    std::vector<int32_t> te_cs;               // [entries][kBoxTile] child slot, -1 no child, -2 cone missing
+    std::vector<uint8_t> te_mask;             // [ntiles][kBoxTile] children of the box (bit o)
     // Cousin-target pairs (levels d >= 3): for every target box T, cousin
     // c of T and target t of T, entry pair_base[T] + c * n_T + t holds the
     // slot of the cone of cousin c that contains t, t's local coordinates in
@@ -237,6 +244,11 @@ struct LevelDev {
     const int32_t* bt_slot;
     const int32_t* bt_frame;
     const int32_t* slot_order;               // parent slots in tile order, or null
+    const int32_t* te_start;                 // tile entries (see HostLevel), or null
+    const uint16_t* te_go;
+    const int32_t* te_info;
+    const int32_t* te_cs;
+    const uint8_t* te_mask;
     // cousin-target pairs (float for mixed, double for FP64)
     int use_pairs;
     long long npairs_cou;

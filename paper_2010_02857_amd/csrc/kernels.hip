@@ -1453,9 +1453,8 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
     __shared__ int sfr[8];                     // frame of each octant, -1
     __shared__ int sgo[9];                     // first entry of each octant
     __shared__ int bslot[kBoxTile];
-    __shared__ int kch[kBoxTile * 8];          // child box of (tile box, octant), -1
+    __shared__ uint8_t smask[kBoxTile];        // children of each tile box (bit o)
     __shared__ int einfo[ME];                  // g0 | cnt << 8 | o << 16
-    __shared__ unsigned ekey[ME];              // child cone key of the entry
     __shared__ int ecs[ME * BX];               // child slot of (entry, box of the pass), -1
 
     const int lane = threadIdx.x;
@@ -1467,34 +1466,18 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
     const int cc = lane & 15, ph = lane >> 4;  // combine: complex column, point phase
 
-    // the tile's slots, their boxes' children, the octants' frames
-    int my_slot = -1, fo = -1, ng = 0;
+    // the tile's slots, their boxes' children, the octants' frames and the
+    // tile's entries (tabulated by the plan)
+    int my_slot = -1;
     if (lane < kBoxTile) {
         my_slot = Lc.bt_slot[(size_t)tile * kBoxTile + lane];
         bslot[lane] = my_slot;
+        smask[lane] = Lc.te_mask[(size_t)tile * kBoxTile + lane];
     }
-    if (lane < 8) {
-        fo = Lc.bt_frame[(size_t)tile * 8 + lane];
-        ng = fo >= 0 ? Lc.fr_ngrp[fo] : 0;
-    }
+    if (lane < 8) sfr[lane] = Lc.bt_frame[(size_t)tile * 8 + lane];
+    if (lane < 9) sgo[lane] = Lc.te_go[(size_t)tile * 9 + lane];
+    const int64_t ebase = Lc.te_start[tile];
     const int nbt = __popcll(__ballot(my_slot >= 0));
-    int incl = ng;
-#pragma unroll
-    for (int dd = 1; dd < 8; dd <<= 1) {
-        const int y = __shfl_up(incl, dd, 64);
-        if (lane >= dd) incl += y;
-    }
-    const int nent = __shfl(incl, 7, 64);
-    if (lane < 8) {
-        sfr[lane] = fo;
-        sgo[lane] = incl - ng;
-    }
-    if (lane == 0) sgo[8] = nent;
-    const int my_box = my_slot >= 0 ? Lp.slot_box[my_slot] : -1;
-    for (int i = lane; i < kBoxTile * 8; i += 64) {
-        const int b = __shfl(my_box, i >> 3, 64);
-        kch[i] = b >= 0 ? Lc.child_of[(size_t)b * 8 + (i & 7)] : -1;
-    }
     wave_lds_fence();
     for (int i = lane; i < 8 * P; i += 64) {
         const int o = i / P, r = i - o * P;
@@ -1558,7 +1541,7 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
             pm = 255;
         } else {
             const int bl = lane >> 3, o = lane & 7;
-            const bool has = lane < BX * 8 && b0 + bl < kBoxTile && kch[(b0 + bl) * 8 + o] >= 0;
+            const bool has = lane < BX * 8 && b0 + bl < kBoxTile && ((smask[b0 + bl] >> o) & 1);
             const unsigned long long bal = __ballot(has);
 #pragma unroll
             for (int k = 0; k < BX; ++k) pm |= (int)((bal >> (8 * k)) & 255ull);
@@ -1570,28 +1553,15 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
             int o1 = o0 + 1;
             while (o1 < 8 && sgo[o1 + 1] - sgo[o0] <= ME) ++o1;
             const int e0 = sgo[o0], ne = sgo[o1] - e0;
-            for (int i = lane; i < ne; i += 64) {
-                const int e = e0 + i;
-                int o = o0;
-                for (int oo = o0 + 1; oo < o1; ++oo) o = sgo[oo] <= e ? oo : o;
-                const int g = e - sgo[o], f = sfr[o];
-                const int g0 = Lc.fr_goff[(size_t)f * (G + 1) + g], g1 = Lc.fr_goff[(size_t)f * (G + 1) + g + 1];
-                einfo[i] = g0 | ((g1 - g0) << 8) | (o << 16);
-                ekey[i] = Lc.fr_gkey[(size_t)f * G + g];
-            }
-            wave_lds_fence();
+            const int64_t eb = ebase + e0;
+            for (int i = lane; i < ne; i += 64) einfo[i] = Lc.te_info[eb + i];
             for (int i = lane; i < ne * BX; i += 64) {
                 const int ei = i / BX, bl = i - ei * BX;
                 const int bi = b0 + bl;
-                const int info = einfo[ei];
-                const int o = info >> 16;
-                const int k = bi < kBoxTile ? kch[bi * 8 + o] : -1;
-                int cs = -1;
-                if (k >= 0) {
-                    const unsigned key = ekey[ei];
-                    const int cell = (int)(key / (unsigned)Lc.ns), is = (int)(key - (unsigned)cell * Lc.ns);
-                    cs = lookup(Lc, k, cell, is);
-                    if (cs < 0) atomicAdd(kc.miss, (unsigned long long)((info >> 8) & 255));
+                int cs = bi < kBoxTile ? Lc.te_cs[(size_t)(eb + ei) * kBoxTile + bi] : -1;
+                if (cs == -2) {
+                    atomicAdd(kc.miss, (unsigned long long)((Lc.te_info[eb + ei] >> 8) & 255));
+                    cs = -1;
                 }
                 ecs[i] = cs;
             }
@@ -2132,7 +2102,7 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
         v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
     }
     if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
-        if (groups && L.ntiles > 0) v[n++] = kC2PBoxes;
+        if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxes;
     }
     if constexpr (RB == 1 && P <= 255) {
         if (groups) v[n++] = kC2PQuads;

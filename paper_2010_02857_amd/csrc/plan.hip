@@ -446,6 +446,66 @@ void build_frames(HostPlan& hp, int d)
         if (sl >= 0) L.slot_order.push_back(sl);
 }
 
+// The entries of level d's box tiles: for every tile, its frames' (octant,
+// group) pairs in octant order, each with the child slot it reads in each of
+// the tile's boxes, so that a tile's kernel reads them in one step instead of
+// looking up frames, children and cones one after the other.
+void build_tile_entries(HostPlan& hp, int d)
+{
+    HostLevel& L = hp.L[d];
+    const HostLevel& Lp = hp.L[d - 1];
+    constexpr int G = kMaxFrameGroups;
+    const int64_t nt = L.ntiles;
+    L.te_start.assign(nt + 1, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        int n = 0;
+        for (int o = 0; o < 8; ++o) {
+            const int32_t f = L.bt_frame[(size_t)t * 8 + o];
+            if (f >= 0) n += L.fr_ngrp[f];
+        }
+        L.te_start[t + 1] = L.te_start[t] + n;
+    }
+    const int64_t ne = L.te_start[nt];
+    L.te_go.assign((size_t)nt * 9, 0);
+    L.te_mask.assign((size_t)nt * kBoxTile, 0);
+    L.te_info.assign((size_t)ne, 0);
+    L.te_cs.assign((size_t)ne * kBoxTile, -1);
+    parallel_for(nt, [&](int64_t t) {
+        int32_t kid[kBoxTile][8];
+        for (int bi = 0; bi < kBoxTile; ++bi) {
+            const int32_t sl = L.bt_slot[(size_t)t * kBoxTile + bi];
+            int m = 0;
+            for (int o = 0; o < 8; ++o) {
+                kid[bi][o] = sl >= 0 ? L.child_of[(size_t)Lp.slot_box[sl] * 8 + o] : -1;
+                m |= (kid[bi][o] >= 0) << o;
+            }
+            L.te_mask[(size_t)t * kBoxTile + bi] = (uint8_t)m;
+        }
+        int64_t e = L.te_start[t];
+        for (int o = 0; o < 8; ++o) {
+            L.te_go[(size_t)t * 9 + o] = (uint16_t)(e - L.te_start[t]);
+            const int32_t f = L.bt_frame[(size_t)t * 8 + o];
+            if (f < 0) continue;
+            for (int g = 0; g < L.fr_ngrp[f]; ++g, ++e) {
+                const int g0 = L.fr_goff[(size_t)f * (G + 1) + g], g1 = L.fr_goff[(size_t)f * (G + 1) + g + 1];
+                L.te_info[e] = g0 | ((g1 - g0) << 8) | (o << 16);
+                const uint32_t key = L.fr_gkey[(size_t)f * G + g];
+                const int cell = (int)(key / (uint32_t)L.ns), is = (int)(key - (uint32_t)cell * L.ns);
+                for (int bi = 0; bi < kBoxTile; ++bi) {
+                    const int32_t k = kid[bi][o];
+                    int32_t cs = -1;
+                    if (k >= 0) {
+                        cs = host_lookup(L, k, cell, is);
+                        if (cs < 0) cs = -2;
+                    }
+                    L.te_cs[(size_t)e * kBoxTile + bi] = cs;
+                }
+            }
+        }
+        L.te_go[(size_t)t * 9 + 8] = (uint16_t)(e - L.te_start[t]);
+    }, 64);
+}
+
 }  // namespace
 
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
@@ -841,6 +901,8 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         HostLevel& L = hp.L[d];
         L.slot_start.assign(L.nbox + 1, 0);
     }
+    for (int d = 4; d <= D; ++d)
+        if (hp.L[d].use_frames && hp.L[d].frame_groups_ok && hp.L[d].ntiles > 0) build_tile_entries(hp, d);
 
     // Cousin-target pair tables, coarse levels first, while the budget lasts.
     {
