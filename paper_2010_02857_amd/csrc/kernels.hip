@@ -1419,11 +1419,12 @@ k_child_to_parent_quads(KernelConsts kc, LevelDev Lc, LevelDev Lp,
 // Ls[a] Lt[b] and Lp[c] of every point, its re-centring ratio), the tiles
 // store their raw results in LDS, and one combine step multiplies them by the
 // ratio into accumulators held in registers: lane (ph, cc) owns complex
-// column cc and the points nu = ph + 4k.  All child slots of a pass are
-// looked up first, in parallel, and the B operands of the next entry and the
+// column cc and the points nu = ph + 4k.  The tile's entries and the child
+// slot each reads in each box come from tables the plan built, so a chunk of
+// entries is read in one step; the B operands of the next entry and the
 // points of the next octant are loaded while the current tiles run.  Each
 // parent slot is written by exactly one wavefront.
-constexpr int kBoxMaxEnt = 32;    // (octant, group) entries looked up at once
+constexpr int kBoxMaxEnt = 32;    // (octant, group) entries read at once
 
 template <int PS, int PA, int RB>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
