@@ -54,12 +54,16 @@ void release(ifgf::DevicePlan& p)
         for (void* q : p.ws_allocs) (void)hipFree(q);
         for (void* q : p.allocs) (void)hipFree(q);
         for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
+        for (hipEvent_t ev : p.sync_ev) (void)hipEventDestroy(ev);
         for (auto& g : p.graphs) (void)hipGraphExecDestroy(g.exec);
         if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
+        if (p.side) (void)hipStreamDestroy(p.side);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     p.graphs.clear();
     p.cap_stream = nullptr;
+    p.side = nullptr;
+    p.sync_ev.clear();
     p.ws_allocs.clear();
     p.allocs.clear();
     p.events.clear();
@@ -393,7 +397,9 @@ static hipError_t apply_graph(ifgf::DevicePlan& p, const void* a, int nrhs, void
         if (!p.cap_stream && (e = hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking)) != hipSuccess)
             return e;
         if ((e = hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+        p.capturing = true;
         hipError_t ea = ifgf::run_apply(p, a, nrhs, out, kappa, p.cap_stream);
+        p.capturing = false;
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(p.cap_stream, &graph);
         if (ea != hipSuccess || e != hipSuccess) {

@@ -322,6 +322,12 @@ struct DevicePlan {
     }
     int tune_gen = 0;            // bumped when the choices change
     int ws_gen = 0;              // bumped when the workspaces are reallocated
+    // second stream of an eager apply: the near field and the cousin
+    // evaluations run on it beside the chain of child-to-parent steps,
+    // ordered by events (created on first use)
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> sync_ev;   // [0] inputs permuted, [1] side done, then cone levels ready / read
+    bool capturing = false;            // an apply graph is being captured: one stream
     // captured apply graphs (use_graph)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;

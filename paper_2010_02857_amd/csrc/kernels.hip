@@ -2226,14 +2226,94 @@ inline bool cousin_two_phase_enabled()
     return !(v && *v && std::atoi(v) == 0);
 }
 
+// The second stream of an eager apply (IFGF_SIDE_STREAM=0: one stream).
+inline bool side_stream_enabled()
+{
+    const char* v = std::getenv("IFGF_SIDE_STREAM");
+    return !(v && *v && std::atoi(v) == 0);
+}
+
+// Creates the side stream (default priority) and its events once.
+inline hipError_t ensure_side(DevicePlan& p)
+{
+    hipError_t e;
+    if (!p.side && (e = hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking)) != hipSuccess) return e;
+    const size_t need = 2 + 2 * (IFGF_MAX_LEVELS + 1);
+    while (p.sync_ev.size() < need) {
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+        p.sync_ev.push_back(ev);
+    }
+    return hipSuccess;
+}
+
+// Events of the two-stream apply: cone values of level d ready (main
+// stream), and level d's cousin evaluation done (side stream).
+inline hipEvent_t ev_ready(DevicePlan& p, int d) { return p.sync_ev[2 + d]; }
+inline hipEvent_t ev_read(DevicePlan& p, int d) { return p.sync_ev[2 + IFGF_MAX_LEVELS + 1 + d]; }
+
+// The cousin-target interpolation of level d (Algorithm 1, first inner
+// loop) on stream st, or its gradient.
 template <typename T, int PS, int PA, int RB>
-hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st, bool grad, bool reuse)
+void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipStream_t st)
+{
+    const HostPlan& hp = p.hp;
+    const int n = (int)hp.n;
+    using C = cpx<T>;
+    if (grad) {
+        StageTimer tm_(p, IFGF_STAGE_COUSIN_GRAD, st);
+        k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                     (const C*)p.gout_m, p.grad_m);
+        return;
+    }
+    StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st);
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4) {
+        if (p.L[d].use_pairs && cousin_mfma_enabled()) {
+            k_cousin_eval_mfma<PS, PA, RB><<<(unsigned)((hp.L[d].nbox + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0,
+                                             st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.out_m);
+            done = true;
+        }
+    }
+    if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
+        if constexpr (RB == 1) {
+            k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord / kPairQuad), kBlock, 0, st>>>(
+                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+            done = true;
+        } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
+            const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;
+            k_cousin_pairs_values_mfma<PS, PA, RB><<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock,
+                                                     0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+            done = true;
+        }
+        if (done)
+            k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
+    }
+    if (done) {
+    } else if (p.L[d].use_pairs)
+        k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
+                                                                           (C*)p.out_m);
+    else
+        k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                     (C*)p.out_m);
+}
+
+// Leaf values, then for d = D..3 the cousin evaluation of level d and the
+// child-to-parent step d -> d - 1 (Algorithm 1).  With a side stream sd
+// distinct from st, the cousin evaluations run on sd: level d's waits for
+// its cone values, and a child-to-parent step whose output buffer held
+// level d + 1 (ping-pong buffers) waits for that level's cousin evaluation.
+// The caller joins sd back into st.
+template <typename T, int PS, int PA, int RB>
+hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st, bool grad, bool reuse,
+                           hipStream_t sd = nullptr)
 {
     const HostPlan& hp = p.hp;
     const int D = hp.D;
-    const int n = (int)hp.n;
     constexpr int P = PS * PA * PA;
     using C = cpx<T>;
+    const bool two = sd && sd != st;
+    if (!sd) sd = st;
     if (D < 3) return hipSuccess;
     if (!reuse && hp.L[D].nslots > 0)
         {
@@ -2241,54 +2321,21 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
             k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
                 kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
         }
+    hipError_t e;
+    if (two && (e = hipEventRecord(ev_ready(p, D), st)) != hipSuccess) return e;
     for (int d = D; d >= 3; --d) {
-        if (grad)
-            {
-                StageTimer tm_(p, IFGF_STAGE_COUSIN_GRAD, st);
-                k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
-                                                                             (const C*)p.gout_m, p.grad_m);
-            }
-        else
-            {
-                StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st);
-                bool done = false;
-                if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4) {
-                    if (p.L[d].use_pairs && cousin_mfma_enabled()) {
-                        k_cousin_eval_mfma<PS, PA, RB><<<(unsigned)((hp.L[d].nbox + kBlock / 64 - 1) / (kBlock / 64)),
-                                                         kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.out_m);
-                        done = true;
-                    }
-                }
-                if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
-                    if constexpr (RB == 1) {
-                        k_cousin_pairs_values<T, PS, PA>
-                            <<<grid_for((size_t)p.L[d].npairs_ord / kPairQuad), kBlock, 0, st>>>(
-                                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
-                        done = true;
-                    } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
-                        const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;
-                        k_cousin_pairs_values_mfma<PS, PA, RB>
-                            <<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
-                                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
-                        done = true;
-                    }
-                    if (done)
-                        k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval,
-                                                                                   (C*)p.out_m);
-                }
-                if (done) {
-                } else if (p.L[d].use_pairs)
-                    k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
-                                                                                       (C*)p.out_m);
-                else
-                    k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
-                                                                                 (C*)p.out_m);
-            }
+        if (two && (e = hipStreamWaitEvent(sd, ev_ready(p, d), 0)) != hipSuccess) return e;
+        cousin_stage<T, PS, PA, RB>(p, kc, d, grad, sd);
+        if (two && (e = hipEventRecord(ev_read(p, d), sd)) != hipSuccess) return e;
         if (d > 3 && !reuse && hp.L[d - 1].nslots > 0)
             {
+                if (two && d + 1 <= D && p.F[d - 1] == p.F[d + 1] &&
+                    (e = hipStreamWaitEvent(st, ev_read(p, d + 1), 0)) != hipSuccess)
+                    return e;
                 StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st);
                 c2p_launch<T, PS, PA, RB>(p, kc, d, c2p_variant<T, PS, PA, RB>(p, d), st);
             }
+        if (two && d > 3 && (e = hipEventRecord(ev_ready(p, d - 1), st)) != hipSuccess) return e;
     }
     return hipGetLastError();
 }
@@ -2299,18 +2346,29 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     const int n = (int)p.hp.n;
     using C = cpx<T>;
     KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), kappa, n, p.miss};
+    hipError_t e;
+    const bool two = !p.capturing && side_stream_enabled() && ensure_side(p) == hipSuccess;
+    hipStream_t sd = two ? p.side : st;
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
         // forward: sources -> targets; adjoint (kappa < 0): targets -> sources
         const Window w = kappa < 0.0 ? target_window(p) : source_window(p);
         k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, w, nrhs, r0);
     }
-    {
-        StageTimer tm_(p, IFGF_STAGE_NEARFIELD, st);
-        k_nearfield<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m, (C*)p.out_m);
+    if (two) {
+        if ((e = hipEventRecord(p.sync_ev[0], st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(sd, p.sync_ev[0], 0)) != hipSuccess) return e;
     }
-    hipError_t e = upward_and_eval<T, PS, PA, RB>(p, kc, st, false, false);
+    {
+        StageTimer tm_(p, IFGF_STAGE_NEARFIELD, sd);
+        k_nearfield<T, RB><<<grid_for(n), kBlock, 0, sd>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m, (C*)p.out_m);
+    }
+    e = upward_and_eval<T, PS, PA, RB>(p, kc, st, false, false, sd);
     if (e != hipSuccess) return e;
+    if (two) {
+        if ((e = hipEventRecord(p.sync_ev[1], sd)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, p.sync_ev[1], 0)) != hipSuccess) return e;
+    }
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_OUT, st);
         const Window w = kappa < 0.0 ? source_window(p) : target_window(p);
