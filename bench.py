@@ -136,7 +136,8 @@ def summarize(d: str) -> int:
     st_ns = sum(ns for name, (c, ns) in agg.items() if "k_child_to_parent" in name)
     lines += ["", f"Stage `{stage}` (all k_child_to_parent* kernels): {st_calls} launches, "
               f"average {st_ns / max(st_calls, 1) / 1e6:.4f} ms per launch; "
-              f"{total / steps / 1e6:.3f} ms of kernel time per matvec.", ""]
+              f"{total / steps / 1e6:.3f} ms of kernel time per matvec (summed over both streams, whose "
+              f"kernels overlap).", ""]
     with open(os.path.join(out_dir, f"{stage}_{WORKLOAD_TAG}_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(lines))
     # HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
