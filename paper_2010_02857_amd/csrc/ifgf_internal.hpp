@@ -327,7 +327,7 @@ struct DevicePlan {
     // ordered by events (created on first use)
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> sync_ev;   // [0] inputs permuted, [1] side done, then cone levels ready / read
-    bool capturing = false;            // an apply graph is being captured: one stream
+    bool capturing = false;            // an apply graph is being captured
     // captured apply graphs (use_graph)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;

@@ -2347,7 +2347,10 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     using C = cpx<T>;
     KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), kappa, n, p.miss};
     hipError_t e;
-    const bool two = !p.capturing && side_stream_enabled() && ensure_side(p) == hipSuccess;
+    // (a capture records the side stream's work too: it joins the capture
+    // through the first event wait and leaves it through the last; the side
+    // stream and its events exist by then, made by run_prepare)
+    const bool two = side_stream_enabled() && (p.capturing ? p.side != nullptr : ensure_side(p) == hipSuccess);
     hipStream_t sd = two ? p.side : st;
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
@@ -2530,6 +2533,10 @@ hipError_t run_prepare(DevicePlan& p, int nrhs)
 {
     const int rb = rb_for(std::min(kMaxRhsPass, nrhs));
     const bool store = p.ws_store_pref && nrhs <= kMaxRhsPass;
+    if (side_stream_enabled()) {
+        hipError_t e = ensure_side(p);
+        if (e != hipSuccess) return e;
+    }
     return p.precision == IFGF_MIXED ? ensure_workspace<float>(p, rb, store, nullptr)
                                      : ensure_workspace<double>(p, rb, store, nullptr);
 }
