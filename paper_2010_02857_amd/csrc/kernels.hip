@@ -2399,13 +2399,25 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
         k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n,
                                                             target_window(p), nrhs, 0);
     }
+    // the near-field and cousin gradients on the side stream, as in apply_pass
+    hipError_t e;
+    const bool two = side_stream_enabled() && (p.capturing ? p.side != nullptr : ensure_side(p) == hipSuccess);
+    hipStream_t sd = two ? p.side : st;
+    if (two) {
+        if ((e = hipEventRecord(p.sync_ev[0], st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(sd, p.sync_ev[0], 0)) != hipSuccess) return e;
+    }
     {
-        StageTimer tm_(p, IFGF_STAGE_NEAR_GRAD, st);
-        k_near_grad<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m,
+        StageTimer tm_(p, IFGF_STAGE_NEAR_GRAD, sd);
+        k_near_grad<T, RB><<<grid_for(n), kBlock, 0, sd>>>(kc, p.L[p.hp.D], p.pts, (const C*)p.dens_m,
                                                             (const C*)p.gout_m, p.grad_m);
     }
-    hipError_t e = upward_and_eval<T, PS, PA, RB>(p, kc, st, true, reuse);
+    e = upward_and_eval<T, PS, PA, RB>(p, kc, st, true, reuse, sd);
     if (e != hipSuccess) return e;
+    if (two) {
+        if ((e = hipEventRecord(p.sync_ev[1], sd)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, p.sync_ev[1], 0)) != hipSuccess) return e;
+    }
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_GRAD, st);
         const Window w = target_window(p);
