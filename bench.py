@@ -166,6 +166,27 @@ def summarize(d: str) -> int:
     rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     md += ["", f"HBM bytes per launch (fetch + write): {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB. "
            f"Kernel source hash {rec['kernel_source_hash']}.", ""]
+    # every kernel of the matvec: scaled HBM bytes per matvec over its time per
+    # matvec in the kernel trace (kernels on the two streams overlap, so each
+    # runs beside others)
+    per_k = collections.defaultdict(lambda: [0.0, 0.0])
+    for ctr, sub, k in (("FETCH_SIZE", "fetch", 0), ("WRITE_SIZE", "write", 1)):
+        allrows = list(csv.DictReader(open(_find(os.path.join(d, sub), "counter_collection.csv"))))
+        for r in _timed(allrows, psteps):
+            if r["Counter_Name"] == ctr and r["Kernel_Name"].startswith("void ifgf"):
+                per_k[_short(r["Kernel_Name"])][k] += float(r["Counter_Value"]) * 1024.0 * rec[f"{sub}_copy_scale"] / psteps
+    dur = collections.defaultdict(float)
+    for r in rows:
+        dur[_short(r["Kernel_Name"])] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 / steps
+    md += ["Every kernel of one matvec (HBM bytes from the counter runs, time from the kernel trace):", "",
+           "| kernel | ms | fetch MB | write MB | HBM GB/s | of 8000 |", "|---|---|---|---|---|---|"]
+    for name, (fb, wb) in sorted(per_k.items(), key=lambda kv: -dur.get(kv[0], 0.0)):
+        t = dur.get(name, 0.0)
+        if t <= 0.0:
+            continue
+        gbs = (fb + wb) / t / 1e9
+        md.append(f"| `{name}` | {t * 1e3:.3f} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {gbs:.0f} | {gbs / 8000.0:.3f} |")
+    md.append("")
     with open(os.path.join(out_dir, f"traffic_{stage}_{WORKLOAD_TAG}.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
     with open(os.path.join(out_dir, f"traffic_{stage}_{WORKLOAD_TAG}.md"), "w") as fh:
@@ -214,6 +235,28 @@ def summarize_sq(d: str, cmd: str, trace_rows: list) -> None:
         ev = max(evals[lvl], 1)
         lines.append(f"| {lvl} | `{e['name']}` | {t * 1e3:.3f} | {e.get('SQ_INSTS_VALU', 0) * 64 / ev:.0f} | "
                      f"{e.get('SQ_INSTS_LDS', 0) * 64 / ev:.0f} | {4 * e.get('SQ_INSTS_VALU', 0) / cap:.2f} | "
+                     f"{e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / cap:.2f} |")
+    lines.append("")
+    # the other stages, per kernel over the matvec: VALU issue (transcendentals
+    # included) and MFMA busy against the same capacity
+    agg = collections.OrderedDict()
+    for r in rows:
+        if "k_child_to_parent" in r["Kernel_Name"] or not r["Kernel_Name"].startswith("void ifgf"):
+            continue
+        e = agg.setdefault(_short(r["Kernel_Name"]), {})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    tdur = collections.defaultdict(float)
+    nsteps = _steps(TRACE_ARGS)
+    for r in trace_rows:
+        tdur[_short(r["Kernel_Name"])] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 / nsteps
+    lines += ["The other stages (all launches of one matvec):", "",
+              "| kernel | ms | VALU issue | MFMA busy |", "|---|---|---|---|"]
+    for name, e in agg.items():
+        t = tdur.get(name, 0.0)
+        if t <= 0.0:
+            continue
+        cap = SIMDS * CLOCK_HZ * t
+        lines.append(f"| `{name}` | {t * 1e3:.3f} | {4 * e.get('SQ_INSTS_VALU', 0) / cap:.2f} | "
                      f"{e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / cap:.2f} |")
     lines.append("")
     with open(os.path.join(ROOT, "profiles", f"sq_child_to_parent_{WORKLOAD_TAG}.md"), "w") as fh:
