@@ -25,7 +25,13 @@
  *     elements r*n .. r*n + n - 1, in the order the points were given.
  *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).  The
  *     apply calls are asynchronous on it; argument errors are reported
- *     synchronously, kernel launch failures as IFGF_E_HIP.
+ *     synchronously, kernel launch failures as IFGF_E_HIP.  An apply or
+ *     gradient call also runs part of its work (near field, cousin
+ *     evaluations) on a second stream the plan owns, at default priority:
+ *     that stream waits on `stream` for the call's inputs, touches only the
+ *     plan's workspaces, and `stream` waits on it before the call's last
+ *     kernel, so the call as a whole is ordered on `stream`.
+ *     IFGF_SIDE_STREAM=0 in the environment keeps everything on `stream`.
  *   - A plan owns all device memory it allocates (tree, cone tables, cone
  *     value buffers).  It may be used by one stream at a time: its
  *     workspaces are shared, and concurrent calls on one plan race.
@@ -261,8 +267,8 @@ typedef enum {
     IFGF_NUM_STAGES = 9
 } ifgf_stage;
 
-/* Stage timing with HIP events recorded on the caller's stream around every
- * kernel launch.  enable = 1 starts recording (and clears the totals),
+/* Stage timing with HIP events recorded around every kernel launch, on the
+ * stream it runs on (the caller's or the plan's second stream).  enable = 1 starts recording (and clears the totals),
  * enable = 0 stops.  Off by default; recording adds two events per launch. */
 ifgf_status ifgf_plan_profile(ifgf_plan_t plan, int32_t enable);
 
