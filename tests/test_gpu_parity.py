@@ -295,6 +295,33 @@ def test_every_child_to_parent_variant(torch, prec, nrhs):
         plan.set_kernel_choice(nrhs, {2: "geometry"})
 
 
+@pytest.mark.parametrize("prec,nrhs,store", [("mixed", 1, 0), ("mixed", 1, 1), ("fp64", 1, 0), ("mixed", 16, 0),
+                                              ("fp64", 4, 1)])
+def test_side_stream_matches_one_stream(torch, prec, nrhs, store, monkeypatch):
+    """The near field and the cousin evaluations on the plan's second stream,
+    ordered by events against the chain of child-to-parent steps (whose
+    output buffer held level d + 1 with two ping-pong buffers, store = 0; a
+    buffer per level with store = 1), give bitwise the one-stream results:
+    forward, adjoint and target gradient, launched back to back with no
+    synchronisation in between."""
+    p = inputs.cube_sphere(64)                     # N = 24576, D = 7
+    n = p.shape[0]
+    k = 16.0 * math.pi
+    plan = make_plan(p, k, prec, max_nrhs=16, store_levels=store)
+    x = dev(torch, inputs.densities(5, nrhs, n), prec)
+    g = dev(torch, inputs.densities(6, nrhs, n), prec)
+    res = {}
+    for side in ("0", "1"):
+        monkeypatch.setenv("IFGF_SIDE_STREAM", side)
+        outs = [plan.apply(x), plan.apply(x, adjoint=True), plan.grad_targets(x, g), plan.apply(x)]
+        torch.cuda.synchronize()
+        res[side] = [o.cpu() for o in outs]
+    for a, b in zip(res["0"], res["1"]):
+        assert torch.equal(a, b)
+    assert torch.equal(res["1"][0], res["1"][3])
+    assert plan.misses() == 0
+
+
 @pytest.mark.parametrize("prec,nrhs", [("mixed", 1), ("mixed", 16), ("fp64", 4)])
 def test_graph_replay(torch, prec, nrhs):
     """use_graph: the first apply captures a graph, later ones replay it.
