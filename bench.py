@@ -463,6 +463,16 @@ def main() -> int:
         st16 = plan.stage_times()
         plan.profile(False)
         result["stage_ms_per_step_16rhs"] = {k: round(v[0] / 4, 4) for k, v in st16.items() if v[1]}
+        # the child-to-parent roofline at 16 right-hand sides (matrix cores),
+        # from the same stage timers: 4 applies were recorded
+        c16 = st16.get("child_to_parent")
+        if c16 and c16[1]:
+            fl16, _ = stage_work(st, "child_to_parent", 16, P, 8)
+            avg16 = c16[0] / c16[1] / 1e3
+            ach16 = fl16 / (c16[1] / 4) / avg16 / 1e12
+            result["roofline_16rhs"] = {"bound": "mfma", "kernel": "child_to_parent", "achieved": round(ach16, 3),
+                                        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": round(ach16 / PEAK_FP32_TFLOPS, 5), "avg_launch_ms": round(avg16 * 1e3, 4)}
         plan_choice16 = plan.kernel_choice(16)
         del plan
         torch.cuda.empty_cache()
