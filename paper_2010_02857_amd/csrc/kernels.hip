@@ -2329,9 +2329,14 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
         if (two && (e = hipEventRecord(ev_read(p, d), sd)) != hipSuccess) return e;
         if (d > 3 && !reuse && hp.L[d - 1].nslots > 0)
             {
-                if (two && d + 1 <= D && p.F[d - 1] == p.F[d + 1] &&
-                    (e = hipStreamWaitEvent(st, ev_read(p, d + 1), 0)) != hipSuccess)
-                    return e;
+                // the nearest finer level whose buffer this step overwrites
+                // (its cousin evaluation is the last reader on the side stream)
+                if (two)
+                    for (int dd = d + 1; dd <= D; ++dd)
+                        if (p.F[dd] == p.F[d - 1]) {
+                            if ((e = hipStreamWaitEvent(st, ev_read(p, dd), 0)) != hipSuccess) return e;
+                            break;
+                        }
                 StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st);
                 c2p_launch<T, PS, PA, RB>(p, kc, d, c2p_variant<T, PS, PA, RB>(p, d), st);
             }
