@@ -881,13 +881,32 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
                             /* grad [G(x, x_k) P(s, theta, phi)] = P grad G + G grad P, with
                              * grad s = -(s/r) v/r, grad theta = theta_hat / r,
                              * grad phi = phi_hat / (r sin theta), and d loc / d(s, theta, phi)
-                             * = 2 / (interval length). */
+                             * = 2 / (interval length).
+                             * On the polar axis of the box's frame (rho = 0) phi is undefined
+                             * and the interpolant in (s, theta, phi) is differentiable along
+                             * the axis but not across it.  There the gradient is the
+                             * derivative along the axis plus, across it, the one-sided
+                             * derivative into the half-plane phi = 0 to which the axis belongs
+                             * (atan2(0, 0) = 0): grad theta = theta_hat(theta, phi = 0) / r =
+                             * (cos theta, 0, 0) / r, and no phi term (phi is constant on that
+                             * half-plane). */
                             double v[3] = {xt[0] - ctr[0], xt[1] - ctr[1], xt[2] - ctr[2]};
                             double rho = sqrt(v[0] * v[0] + v[1] * v[1]);
                             double r2 = r0 * r0;
                             double gs[3] = {-sth[0] * v[0] / r2, -sth[0] * v[1] / r2, -sth[0] * v[2] / r2};
-                            double gt[3] = {v[0] * v[2] / (rho * r2), v[1] * v[2] / (rho * r2), -rho / r2};
-                            double gp[3] = {-v[1] / (rho * rho), v[0] / (rho * rho), 0.0};
+                            double gt[3], gp[3];
+                            if (rho > 0.0) {
+                                gt[0] = v[0] * v[2] / (rho * r2);
+                                gt[1] = v[1] * v[2] / (rho * r2);
+                                gt[2] = -rho / r2;
+                                gp[0] = -v[1] / (rho * rho);
+                                gp[1] = v[0] / (rho * rho);
+                                gp[2] = 0.0;
+                            } else {
+                                gt[0] = v[2] / r2;
+                                gt[1] = gt[2] = 0.0;
+                                gp[0] = gp[1] = gp[2] = 0.0;
+                            }
                             double ds = eta_const() / Ld->ns, dth = PI / Ld->nc;
                             cplx gG[3];
                             green_grad(kappa, xt, ctr, gG);

@@ -127,6 +127,15 @@ def fd_entries(cfg: int, n: int, m: int) -> tuple[np.ndarray, np.ndarray]:
     return idx, comp
 
 
+def lattice(n: int) -> np.ndarray:
+    """n^3 points of a regular grid filling [-1/2, 1/2]^3 (spacing 1/(n-1)).
+    With n = 2^j + 1 the points lie on box faces and on the polar axes of box
+    centres at every level: a case of ties for the box and cone maps."""
+    g = np.arange(n) / (n - 1) - 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return np.ascontiguousarray(np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1))
+
+
 def random_box_points(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """n points uniform in [-scale/2, scale/2)^3 (tests of small cases)."""
     rng = np.random.default_rng(seed)

@@ -25,7 +25,7 @@ def test_status_strings():
         assert lib.ifgf_status_string(code).decode() == name
 
 
-@pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46"])
+@pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46", "lattice"])
 def test_host_plan_matches_oracle_counts(case):
     """Relevant boxes, cousins, relevant cones, child-to-parent and near-field
     work per level equal those of the CPU oracle (Sec. 3.3.2)."""
@@ -39,6 +39,10 @@ def test_host_plan_matches_oracle_counts(case):
         kw = okw = {"levels": 5}
     elif case == "laplace":
         p, k = inputs.cube_sphere(20), 0.0
+    elif case == "lattice":
+        # points on box faces and cone faces and on the polar axes of box centres
+        p, k = inputs.lattice(17), 8.0
+        kw = okw = {"levels": 4}
     elif case == "leaf23":
         p, k = inputs.cube_sphere(20, 0.25), 15.0
         kw = {"leaf": (2, 3)}

@@ -406,3 +406,43 @@ def test_ifgf_gradient_matches_differences(cfg1):
     # and the analytic IFGF gradient is close to the exact one
     gd = oracle.direct_grad(p, a, w.kappa, targets=t0, skip=idx)[0]
     assert rel(g[2 * m:], gd) < 1e-2
+
+
+def test_ifgf_gradient_on_lattice_pole_reading():
+    """17^3 lattice, D = 4: every lattice point with odd indices lies on the
+    polar axis (rho = 0) of the level-4 boxes of its column, where phi is
+    undefined.  The gradient is finite everywhere.  At such points its z
+    component matches differences along the axis, and its x component the
+    one-sided derivative into the half-plane phi = 0 to which the axis belongs
+    (the pole reading), wherever the moved targets took the same discrete
+    branch.  Lattice points also lie on cone faces of other boxes (theta =
+    pi/2, phi = pi/2, ...), which belong to the interval above them, so the
+    differences are one-sided: along -z (which keeps theta = pi/2 in the upper
+    interval) and along +x (the phi = 0 side of the axis)."""
+    p = inputs.lattice(17)
+    n, k = p.shape[0], 8.0
+    a = inputs.densities(9, 1, n)
+    r = oracle.ifgf(p, a, k, levels=4, grad=True)
+    assert np.isfinite(r["out"]).all() and np.isfinite(r["grad"]).all()
+    ijk = np.indices((17, 17, 17)).reshape(3, -1).T
+    sel = np.nonzero(np.all(ijk % 2 == 1, axis=1))[0]
+    m, h = sel.shape[0], 1e-6
+    ex, ez = np.array([1.0, 0, 0]), np.array([0, 0, 1.0])
+    t0 = p[sel]
+    tg = np.concatenate([t0, t0 - h * ez, t0 - 2 * h * ez, t0 + h * ex, t0 + 2 * h * ex])
+    rr = oracle.ifgf(p, a, k, levels=4, targets=tg, skip=np.tile(sel, 5), grad=True, sig=True)
+    f, sg, g = rr["out"][0].reshape(5, m), rr["sig"].reshape(5, m), rr["grad"][0][:m]
+    assert np.isfinite(g).all()
+    assert np.abs(g - r["grad"][0][sel]).max() < 1e-12 * np.abs(g).max()   # the override changes nothing
+    scale = np.max(np.abs(g))
+    okz = (sg[1] == sg[0]) & (sg[2] == sg[0])
+    okx = (sg[3] == sg[0]) & (sg[4] == sg[0])
+    print(f"lattice: {m} on-axis targets, z branch kept {okz.sum()}, x branch kept {okx.sum()}")
+    assert okz.sum() >= 20 and okx.sum() >= 20, (okz.sum(), okx.sum())
+    fdz = (3 * f[0] - 4 * f[1] + f[2]) / (2 * h)
+    fdx = (-3 * f[0] + 4 * f[3] - f[4]) / (2 * h)
+    assert np.max(np.abs(fdz - g[:, 2])[okz]) < 1e-5 * scale
+    assert np.max(np.abs(fdx - g[:, 0])[okx]) < 1e-5 * scale
+    # the x derivative on the axis is not trivially small: the theta term of
+    # the reading carries it (dropping that term would fail the comparison)
+    assert np.max(np.abs(g[:, 0])[okx]) > 1e-2 * scale
