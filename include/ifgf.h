@@ -175,34 +175,54 @@ ifgf_status ifgf_plan_create_targets(const double* sources, int64_t n, const dou
  *              plan has distinct targets; ifgf_plan_stats reports both.)   */
 ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, int32_t nrhs, void* out, void* stream);
 
-/* out = adjoint operator applied to v:
+/* out = adjoint operator applied to v: the conjugate transpose of the
+ * discrete operator of Sec. 2, eq. (field1),
  *   out_r(x_m) = sum_{l != m} conj(G(x_l, x_m)) v_r(x_l),
  * evaluated by the same hierarchy with the conjugated kernel (k -> -k, which
  * conjugates every factor e^{i k .} while the real interpolation weights are
- * unchanged).  Same layouts and rules as ifgf_apply.                       */
+ * unchanged).  The direction is an explicit argument of the pipeline, never
+ * read from the sign of k (at k = 0 the windows still swap).  With distinct
+ * targets v is [nrhs][n_targets] and out [nrhs][n_sources].  Otherwise the
+ * same layouts and rules as ifgf_apply.                                    */
 ifgf_status ifgf_apply_adjoint(ifgf_plan_t plan, const void* v, int32_t nrhs, void* out, void* stream);
 
 /* Gradient of a real loss L(I) with respect to the target coordinates, the
  * sources held fixed:
  *   grad_xyz[l][c] = sum_r Re( conj(g_r(x_l)) * dI_r(x_l)/dx_{l,c} ),
  * where g = dL/dRe(I) + i dL/dIm(I) (PyTorch's convention for complex
- * gradients) and dI/dx differentiates the IFGF approximation: the near-field
- * kernels and, at every level, the centred factor times the Chebyshev
- * interpolant in (s, theta, phi).
- *   densities  device [nrhs][n] complex, the forward input.
- *   grad_out   device [nrhs][n] complex, g.
- *   grad_xyz   device [n][3] FP64, overwritten.
- * If the plan keeps the cone values of every level (store_levels) and the
- * last ifgf_apply used the same densities, they are reused; otherwise they
- * are recomputed.                                                           */
+ * gradients) and dI/dx differentiates the IFGF approximation: the gradient
+ * of the Helmholtz kernel of eq. (greensfunction) in the near field and, at
+ * every level, of the centred factor times the Chebyshev interpolant in
+ * (s, theta, phi) of Sec. 3.2 (eq. defparametrizationr).  On the polar axis
+ * of a box's frame, where phi is undefined, the derivative across the axis
+ * is the one-sided one into the half-plane phi = 0 that holds the axis.
+ *   densities  device [nrhs][n_sources] complex, the forward input.
+ *   grad_out   device [nrhs][n_targets] complex, g.
+ *   nrhs       1 .. max_nrhs (passes of 16 right-hand sides are summed).
+ *   grad_xyz   device [n_targets][3] FP64, overwritten.
+ * The cone values are recomputed from the densities (see
+ * ifgf_grad_targets_stored for reusing those of the last apply).           */
 ifgf_status ifgf_grad_targets(ifgf_plan_t plan, const void* densities, const void* grad_out,
                               int32_t nrhs, double* grad_xyz, void* stream);
+
+/* As ifgf_grad_targets, but reuses the cone values of every level that the
+ * last ifgf_apply of this plan stored (store_levels), when that apply took
+ * the same densities pointer and nrhs <= 16.  The caller guarantees that the
+ * contents of `densities` have not changed since that apply (the autograd
+ * Function of the Python binding does, through PyTorch's version check of
+ * saved tensors); the plan compares only pointers and sizes.  Otherwise, or
+ * when nothing is stored, the cone values are recomputed as by
+ * ifgf_grad_targets.                                                        */
+ifgf_status ifgf_grad_targets_stored(ifgf_plan_t plan, const void* densities, const void* grad_out,
+                                     int32_t nrhs, double* grad_xyz, void* stream);
 
 /* Per-level counts of the hierarchy (host, no GPU work). */
 ifgf_status ifgf_plan_stats(ifgf_plan_t plan, ifgf_stats* out);
 
-/* Synchronises the plan's last stream and reports how many interpolation
- * queries found no computed cone since the plan was created (must be 0). */
+/* Synchronises the stream of the plan's last apply or gradient call (and the
+ * plan's second stream), not the whole device, and reports how many
+ * interpolation queries found no computed cone since the plan was created
+ * (must be 0). */
 ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses);
 
 /* Child-to-parent kernel variants (the interpolation from child to parent

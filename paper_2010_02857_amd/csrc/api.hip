@@ -383,7 +383,7 @@ ifgf_status ifgf_plan_create_targets(const double* sources, int64_t n, const dou
 // time a (densities, out, nrhs, direction) combination is seen with the
 // current workspaces and kernel choices, then replayed on the caller's
 // stream.  The graph holds kernel launches only.
-static hipError_t apply_graph(ifgf::DevicePlan& p, const void* a, int nrhs, void* out, double kappa, bool adj,
+static hipError_t apply_graph(ifgf::DevicePlan& p, const void* a, int nrhs, void* out, bool adj,
                               hipStream_t st)
 {
     hipError_t e = ifgf::run_prepare(p, nrhs);
@@ -398,7 +398,7 @@ static hipError_t apply_graph(ifgf::DevicePlan& p, const void* a, int nrhs, void
             return e;
         if ((e = hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
         p.capturing = true;
-        hipError_t ea = ifgf::run_apply(p, a, nrhs, out, kappa, p.cap_stream);
+        hipError_t ea = ifgf::run_apply(p, a, nrhs, out, adj, p.cap_stream);
         p.capturing = false;
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(p.cap_stream, &graph);
@@ -423,7 +423,7 @@ static hipError_t apply_graph(ifgf::DevicePlan& p, const void* a, int nrhs, void
     }
     hit->used = ++p.graph_clock;
     if ((e = hipGraphLaunch(hit->exec, st)) != hipSuccess) return e;
-    ifgf::note_apply(p, a, nrhs, kappa);
+    ifgf::note_apply(p, a, nrhs, adj);
     return hipSuccess;
 }
 
@@ -433,10 +433,9 @@ static ifgf_status apply_common(ifgf_plan_t plan, const void* a, int32_t nrhs, v
     if (s != IFGF_OK) return s;
     ifgf::DevicePlan& p = plan->p;
     DeviceGuard g(p.device);
-    double kappa = adj ? -p.hp.kappa : p.hp.kappa;
-    hipError_t e = p.use_graph && !p.profiling
-                       ? apply_graph(p, a, nrhs, out, kappa, adj, (hipStream_t)stream)
-                       : ifgf::run_apply(p, a, nrhs, out, kappa, (hipStream_t)stream);
+    p.last_stream = (hipStream_t)stream;
+    hipError_t e = p.use_graph && !p.profiling ? apply_graph(p, a, nrhs, out, adj, (hipStream_t)stream)
+                                               : ifgf::run_apply(p, a, nrhs, out, adj, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, adj ? "ifgf_apply_adjoint" : "ifgf_apply");
     return IFGF_OK;
 }
@@ -510,18 +509,30 @@ ifgf_status ifgf_apply_adjoint(ifgf_plan_t plan, const void* v, int32_t nrhs, vo
     return apply_common(plan, v, nrhs, out, stream, true);
 }
 
-ifgf_status ifgf_grad_targets(ifgf_plan_t plan, const void* densities, const void* grad_out, int32_t nrhs,
-                              double* grad_xyz, void* stream)
+static ifgf_status grad_common(ifgf_plan_t plan, const void* densities, const void* grad_out, int32_t nrhs,
+                               double* grad_xyz, void* stream, bool reuse)
 {
     ifgf_status s = check_apply_args(plan, densities, grad_xyz, nrhs);
     if (s != IFGF_OK) return s;
     if (!grad_out) return fail(IFGF_E_INVALID_ARG, "grad_out is NULL");
-    if (nrhs > ifgf::kMaxRhsPass) return fail(IFGF_E_UNSUPPORTED, "ifgf_grad_targets takes at most 16 right-hand sides");
     ifgf::DevicePlan& p = plan->p;
     DeviceGuard g(p.device);
-    hipError_t e = ifgf::run_grad(p, densities, grad_out, nrhs, grad_xyz, true, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "ifgf_grad_targets");
+    p.last_stream = (hipStream_t)stream;
+    hipError_t e = ifgf::run_grad(p, densities, grad_out, nrhs, grad_xyz, reuse, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, reuse ? "ifgf_grad_targets_stored" : "ifgf_grad_targets");
     return IFGF_OK;
+}
+
+ifgf_status ifgf_grad_targets(ifgf_plan_t plan, const void* densities, const void* grad_out, int32_t nrhs,
+                              double* grad_xyz, void* stream)
+{
+    return grad_common(plan, densities, grad_out, nrhs, grad_xyz, stream, false);
+}
+
+ifgf_status ifgf_grad_targets_stored(ifgf_plan_t plan, const void* densities, const void* grad_out, int32_t nrhs,
+                                     double* grad_xyz, void* stream)
+{
+    return grad_common(plan, densities, grad_out, nrhs, grad_xyz, stream, true);
 }
 
 ifgf_status ifgf_plan_stats(ifgf_plan_t plan, ifgf_stats* out)
@@ -538,7 +549,9 @@ ifgf_status ifgf_plan_check(ifgf_plan_t plan, int64_t* misses)
     *misses = 0;
     if (plan->p.host_only) return IFGF_OK;
     DeviceGuard g(plan->p.device);
-    hipError_t e = hipDeviceSynchronize();
+    // the plan's last stream and its side stream (not the whole device)
+    hipError_t e = hipStreamSynchronize(plan->p.last_stream);
+    if (e == hipSuccess && plan->p.side) e = hipStreamSynchronize(plan->p.side);
     if (e != hipSuccess) return hip_fail(e, "ifgf_plan_check");
     unsigned long long m = 0;
     e = hipMemcpy(&m, plan->p.miss, sizeof(m), hipMemcpyDeviceToHost);

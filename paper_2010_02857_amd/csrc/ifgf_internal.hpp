@@ -265,9 +265,12 @@ struct LevelDev {
 
 struct KernelConsts {
     ChebNodes cs, ca;        // radial and angular node sets
-    double kappa;            // signed wavenumber (negative for the adjoint)
+    double kappa;            // wavenumber of the phases: k, or -k for the adjoint
     int n;                   // points
     unsigned long long* miss;  // device counter of interpolation misses
+    int adj;                 // 1: the adjoint (conjugated centred factors and
+                             // ratios); never inferred from the sign of kappa,
+                             // which is -0.0 for the adjoint at k = 0
 };
 
 // A plan: the host hierarchy, its device copy and the workspaces.
@@ -336,6 +339,8 @@ struct DevicePlan {
     };
     std::vector<GraphEntry> graphs;
     uint64_t graph_clock = 0;
+    // stream of the last apply or gradient call (synchronised by ifgf_plan_check)
+    hipStream_t last_stream = nullptr;
     // what the stored cone values hold (for gradient reuse)
     const void* stored_dens = nullptr;
     int stored_nrhs = 0;
@@ -375,15 +380,15 @@ class StageTimer {
     size_t e0_ = (size_t)-1;
 };
 
-// Kernel pipeline entry points (kernels.hip).  `kappa` is signed: -k for
-// the adjoint.  Each enqueues on `stream` and returns hipSuccess or the
-// first launch error.
-hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t stream);
+// Kernel pipeline entry points (kernels.hip).  `adj` selects the adjoint
+// (windows swapped, kernel conjugated).  Each enqueues on `stream` and
+// returns hipSuccess or the first launch error.
+hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t stream);
 // Allocates the workspaces an apply with nrhs right-hand sides needs (so
 // that the apply itself allocates nothing and can be captured).
 hipError_t run_prepare(DevicePlan& p, int nrhs);
 // Records after an apply (eager or replayed) what the stored cone values hold.
-void note_apply(DevicePlan& p, const void* dens, int nrhs, double kappa);
+void note_apply(DevicePlan& p, const void* dens, int nrhs, bool adj);
 // Times every child-to-parent variant of every level for nrhs right-hand
 // sides (densities zero, synchronous) and keeps the fastest.
 hipError_t run_autotune(DevicePlan& p, int nrhs, hipStream_t st);

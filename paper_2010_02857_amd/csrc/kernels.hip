@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval(KernelConsts kc, LevelDe
 // local coordinates and centred factor of (target, cousin box) were computed
 // with the plan, so no FP64 geometry is left.  Entries of one target box are
 // stored cousin-major, so the targets of a box read consecutive entries.
-// The centred factor is conjugated for the adjoint (kappa < 0).
+// The centred factor is conjugated for the adjoint (kc.adj).
 template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_cousin_eval_pairs(KernelConsts kc, LevelDev L,
                                                               const cpx<T>* __restrict__ F, cpx<T>* __restrict__ out)
@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval_pairs(KernelConsts kc, L
     const long long np = L.npairs_cou;
     const T* pt = (const T*)L.pr_t;
     const T* pg = (const T*)L.pr_g;
-    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    const T conj_sign = kc.adj ? (T)-1 : (T)1;
     cpx<T> acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values(KernelConsts kc,
             }
         }
     }
-    const T sg = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    const T sg = kc.adj ? (T)-1 : (T)1;
 #pragma unroll
     for (int r = 0; r < QR; ++r) {
         const int e = L.pr_order[i0 + r];
@@ -617,7 +617,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, Lev
 // local coordinates and re-centring ratio of interpolation point nu of the
 // parent cone of slot `pslot` seen from the child in octant o are read from
 // the frame of (parent cone, o); only the child's slot is looked up.  For
-// the adjoint (kappa < 0) the tabulated ratio is conjugated.
+// the adjoint (kc.adj) the tabulated ratio is conjugated.
 template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_child_to_parent_frames(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                    const cpx<T>* __restrict__ Fc,
@@ -631,7 +631,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_frames(KernelConsts 
     const int j = Lp.slot_box[pslot];
     const T* frt = (const T*)Lc.fr_t;
     const T* frr = (const T*)Lc.fr_ratio;
-    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    const T conj_sign = kc.adj ? (T)-1 : (T)1;
     cpx<T> acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(NT) k_child_to_parent_lds(KernelConsts kc, Lev
     const int sp = active ? slot_at<ORD>(Lc, slot0 + s_me) : 0;
     const T* frt = (const T*)Lc.fr_t;
     const T* frr = (const T*)Lc.fr_ratio;
-    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    const T conj_sign = kc.adj ? (T)-1 : (T)1;
 
     // (slot, octant) frames and an inclusive scan of their group counts
     if (tid < 64) {
@@ -978,7 +978,7 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
     const float* F = (const float*)Fc;
     const float* frt = (const float*)Lc.fr_t;
     const float* frr = (const float*)Lc.fr_ratio;
-    const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
+    const float conj_sign = kc.adj ? -1.f : 1.f;
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
     const int j = Lp.slot_box[sp];
 
@@ -1263,7 +1263,7 @@ k_child_to_parent_quads(KernelConsts kc, LevelDev Lc, LevelDev Lp,
     const int slot0 = xcd_block(blockIdx.x, gridDim.x) * S;
     const T* frt = (const T*)Lc.fr_t;
     const T* frr = (const T*)Lc.fr_ratio;
-    const T conj_sign = kc.kappa < 0.0 ? (T)-1 : (T)1;
+    const T conj_sign = kc.adj ? (T)-1 : (T)1;
     for (int i = tid; i < S * P; i += kBlock) acc[i] = cpx<T>{(T)0, (T)0};
 
     for (int o = 0; o < 8; ++o) {
@@ -1463,7 +1463,7 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
     if (tile >= Lc.ntiles) return;
     const float* frt = (const float*)Lc.fr_t;
     const float* frr = (const float*)Lc.fr_ratio;
-    const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
+    const float conj_sign = kc.adj ? -1.f : 1.f;
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
     const int cc = lane & 15, ph = lane >> 4;  // combine: complex column, point phase
 
@@ -1729,7 +1729,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval_mfma(KernelConsts kc, Le
     const long long np = L.npairs_cou;
     const float* pt = (const float*)L.pr_t;
     const float* pg = (const float*)L.pr_g;
-    const float conj_sign = kc.kappa < 0.0 ? -1.f : 1.f;
+    const float conj_sign = kc.adj ? -1.f : 1.f;
     const float* Ff = (const float*)F;
     float* outf = (float*)out;
 
@@ -1822,7 +1822,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConst
     lagrange<float, PS>((double)pt[ic], kc.cs, Ls);
     lagrange<float, PA>((double)pt[no + ic], kc.ca, Lt);
     lagrange<float, PA>((double)pt[2 * no + ic], kc.ca, Lpv);
-    const float gr = pg[ic], gi = (kc.kappa < 0.0 ? -1.f : 1.f) * pg[no + ic];
+    const float gr = pg[ic], gi = (kc.adj ? -1.f : 1.f) * pg[no + ic];
     const long long e = L.pr_order[ic];       // -1: a placeholder, not stored
     const float* Ff = (const float*)F;
     float* pf = (float*)pval;
@@ -1909,7 +1909,7 @@ __global__ void __launch_bounds__(kBlock) k_near_grad(KernelConsts kc, LevelDev 
 //   d/dx [G(x, x_k) P] = P grad G + G (dP/dts 2/ds grad s + dP/dtt 2/dang grad theta
 //                                      + dP/dtp 2/dang grad phi),
 // grad s = -s v / r^2, grad theta = (vx vz, vy vz, -rho^2) / (rho r^2),
-// grad phi = (-vy, vx, 0) / rho^2.
+// grad phi = (-vy, vx, 0) / rho^2 (rho > 0; on the polar axis see below).
 template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
                                                         const cpx<T>* __restrict__ F, const cpx<T>* __restrict__ gout,
@@ -1947,8 +1947,24 @@ __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDe
         const double rho2 = v0 * v0 + v1 * v1, rho = sqrt(rho2);
         const double cs_ = 2.0 / L.ds, ca_ = 2.0 / L.dang;
         const double gs[3] = {-cl.s * v0 / r2 * cs_, -cl.s * v1 / r2 * cs_, -cl.s * v2 / r2 * cs_};
-        const double gt[3] = {v0 * v2 / (rho * r2) * ca_, v1 * v2 / (rho * r2) * ca_, -rho / r2 * ca_};
-        const double gp[3] = {-v1 / rho2 * ca_, v0 / rho2 * ca_, 0.0};
+        double gt[3], gp[3];
+        if (rho > 0.0) {
+            gt[0] = v0 * v2 / (rho * r2) * ca_;
+            gt[1] = v1 * v2 / (rho * r2) * ca_;
+            gt[2] = -rho / r2 * ca_;
+            gp[0] = -v1 / rho2 * ca_;
+            gp[1] = v0 / rho2 * ca_;
+            gp[2] = 0.0;
+        } else {
+            // on the frame's polar axis phi is undefined and the interpolant is
+            // not differentiable across the axis: take the derivative along it
+            // plus the one-sided derivative into the half-plane phi = 0 that
+            // holds the axis (atan2(0, 0) = 0): grad theta = (cos theta, 0, 0) / r,
+            // no phi term
+            gt[0] = v2 / r2 * ca_;
+            gt[1] = gt[2] = 0.0;
+            gp[0] = gp[1] = gp[2] = 0.0;
+        }
         T c, s;
         expi<T>(kc.kappa * r, c, s);
         T inv = (T)(kInv4Pi / r);
@@ -1980,16 +1996,23 @@ __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDe
     grad[3 * i + 2] += acc2;
 }
 
-// [n][3] (Morton order) -> grad [wn][3], the window's points (input order).
+// [n][3] (Morton order) -> grad [wn][3], the window's points (input order);
+// with acc the values are added (passes of right-hand sides after the first).
 __global__ void __launch_bounds__(kBlock) k_permute_grad(const double* __restrict__ in, double* __restrict__ out,
-                                                         const int32_t* __restrict__ iperm, Window w)
+                                                         const int32_t* __restrict__ iperm, Window w, int acc)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= w.wn) return;
     int i = iperm[w.w0 + j];
-    out[3 * j] = in[3 * i];
-    out[3 * j + 1] = in[3 * i + 1];
-    out[3 * j + 2] = in[3 * i + 2];
+    if (acc) {
+        out[3 * j] += in[3 * i];
+        out[3 * j + 1] += in[3 * i + 1];
+        out[3 * j + 2] += in[3 * i + 2];
+    } else {
+        out[3 * j] = in[3 * i];
+        out[3 * j + 1] = in[3 * i + 1];
+        out[3 * j + 2] = in[3 * i + 2];
+    }
 }
 
 // ------------------------------------------------------------- host side
@@ -2346,11 +2369,13 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
 }
 
 template <typename T, int PS, int PA, int RB>
-hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* out, double kappa, hipStream_t st)
+hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* out, bool adj, hipStream_t st)
 {
     const int n = (int)p.hp.n;
     using C = cpx<T>;
-    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), kappa, n, p.miss};
+    // the adjoint conjugates every factor e^{i k .}: the phases use -k, and
+    // the tabulated centred factors and ratios are conjugated (kc.adj)
+    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), adj ? -p.hp.kappa : p.hp.kappa, n, p.miss, adj ? 1 : 0};
     hipError_t e;
     // (a capture records the side stream's work too: it joins the capture
     // through the first event wait and leaves it through the last; the side
@@ -2359,8 +2384,8 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     hipStream_t sd = two ? p.side : st;
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
-        // forward: sources -> targets; adjoint (kappa < 0): targets -> sources
-        const Window w = kappa < 0.0 ? target_window(p) : source_window(p);
+        // forward: sources -> targets; adjoint: targets -> sources
+        const Window w = adj ? target_window(p) : source_window(p);
         k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n, w, nrhs, r0);
     }
     if (two) {
@@ -2379,7 +2404,7 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     }
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_OUT, st);
-        const Window w = kappa < 0.0 ? source_window(p) : target_window(p);
+        const Window w = adj ? source_window(p) : target_window(p);
         k_permute_out<T, RB><<<grid_for((size_t)w.wn), kBlock, 0, st>>>((const C*)p.out_m, (C*)out, p.iperm, w, nrhs,
                                                                         r0);
     }
@@ -2387,22 +2412,22 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
 }
 
 template <typename T, int PS, int PA, int RB>
-hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
+hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs, int r0, double* grad, bool reuse,
                      hipStream_t st)
 {
     const int n = (int)p.hp.n;
     using C = cpx<T>;
-    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), p.hp.kappa, n, p.miss};
+    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), p.hp.kappa, n, p.miss, 0};
     if (!reuse)
         {
             StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
             k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)dens, (C*)p.dens_m, p.perm, n,
-                                                                source_window(p), nrhs, 0);
+                                                                source_window(p), nrhs, r0);
         }
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
         k_permute_in<T, RB><<<grid_for(n), kBlock, 0, st>>>((const C*)gout, (C*)p.gout_m, p.perm, n,
-                                                            target_window(p), nrhs, 0);
+                                                            target_window(p), nrhs, r0);
     }
     // the near-field and cousin gradients on the side stream, as in apply_pass
     hipError_t e;
@@ -2426,22 +2451,23 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_GRAD, st);
         const Window w = target_window(p);
-        k_permute_grad<<<grid_for((size_t)w.wn), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, w);
+        // passes after the first add their right-hand sides' share
+        k_permute_grad<<<grid_for((size_t)w.wn), kBlock, 0, st>>>(p.grad_m, grad, p.iperm, w, r0 > 0 ? 1 : 0);
     }
     return hipGetLastError();
 }
 
 template <typename T, int PS, int PA>
-hipError_t apply_t(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t st)
+hipError_t apply_t(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t st)
 {
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPass) {
         int rb = rb_for(std::min(kMaxRhsPass, nrhs - r0));
         bool store = p.ws_store_pref && nrhs <= kMaxRhsPass;
         hipError_t e = ensure_workspace<T>(p, rb, store, nullptr);
         if (e != hipSuccess) return e;
-        if (rb == 1) e = apply_pass<T, PS, PA, 1>(p, dens, nrhs, r0, out, kappa, st);
-        else if (rb == 4) e = apply_pass<T, PS, PA, 4>(p, dens, nrhs, r0, out, kappa, st);
-        else e = apply_pass<T, PS, PA, 16>(p, dens, nrhs, r0, out, kappa, st);
+        if (rb == 1) e = apply_pass<T, PS, PA, 1>(p, dens, nrhs, r0, out, adj, st);
+        else if (rb == 4) e = apply_pass<T, PS, PA, 4>(p, dens, nrhs, r0, out, adj, st);
+        else e = apply_pass<T, PS, PA, 16>(p, dens, nrhs, r0, out, adj, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -2451,14 +2477,22 @@ template <typename T, int PS, int PA>
 hipError_t grad_t(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
                   hipStream_t st)
 {
-    const int rb = rb_for(nrhs);
-    bool fresh = false;
-    hipError_t e = ensure_workspace<T>(p, rb, p.ws_store_pref, &fresh);
-    if (e != hipSuccess) return e;
-    if (fresh) reuse = false;
-    if (rb == 1) return grad_pass<T, PS, PA, 1>(p, dens, gout, nrhs, grad, reuse, st);
-    if (rb == 4) return grad_pass<T, PS, PA, 4>(p, dens, gout, nrhs, grad, reuse, st);
-    return grad_pass<T, PS, PA, 16>(p, dens, gout, nrhs, grad, reuse, st);
+    // passes of at most 16 right-hand sides; the stored cone values can only
+    // serve a single pass
+    if (nrhs > kMaxRhsPass) reuse = false;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPass) {
+        const int rb = rb_for(std::min(kMaxRhsPass, nrhs - r0));
+        bool fresh = false;
+        const bool store = p.ws_store_pref && nrhs <= kMaxRhsPass;
+        hipError_t e = ensure_workspace<T>(p, rb, store, &fresh);
+        if (e != hipSuccess) return e;
+        if (fresh) reuse = false;
+        if (rb == 1) e = grad_pass<T, PS, PA, 1>(p, dens, gout, nrhs, r0, grad, reuse, st);
+        else if (rb == 4) e = grad_pass<T, PS, PA, 4>(p, dens, gout, nrhs, r0, grad, reuse, st);
+        else e = grad_pass<T, PS, PA, 16>(p, dens, gout, nrhs, r0, grad, reuse, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T, int PS, int PA, int RB>
@@ -2474,7 +2508,7 @@ hipError_t autotune_t(DevicePlan& p, hipStream_t st)
     if (D < 4) return hipSuccess;
     const bool prof = p.profiling;
     p.profiling = false;
-    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), hp.kappa, (int)hp.n, p.miss};
+    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), hp.kappa, (int)hp.n, p.miss, 0};
     if ((e = hipMemsetAsync(p.dens_m, 0, (size_t)hp.n * RB * sizeof(C), st)) != hipSuccess) return e;
     if (hp.L[D].nslots > 0)
         k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
@@ -2558,9 +2592,9 @@ hipError_t run_prepare(DevicePlan& p, int nrhs)
                                      : ensure_workspace<double>(p, rb, store, nullptr);
 }
 
-void note_apply(DevicePlan& p, const void* dens, int nrhs, double kappa)
+void note_apply(DevicePlan& p, const void* dens, int nrhs, bool adj)
 {
-    p.stored_valid = p.ws_store && kappa == p.hp.kappa && nrhs <= kMaxRhsPass && p.ws_rb == rb_for(nrhs);
+    p.stored_valid = p.ws_store && !adj && nrhs <= kMaxRhsPass && p.ws_rb == rb_for(nrhs);
     p.stored_dens = dens;
     p.stored_nrhs = nrhs;
 }
@@ -2617,20 +2651,20 @@ int kernel_choice(const DevicePlan& p, int nrhs, int d)
     return -1;
 }
 
-hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, double kappa, hipStream_t st)
+hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t st)
 {
     const int ps = p.hp.ps, pa = p.hp.pang;
     hipError_t e;
     bool mixed = p.precision == IFGF_MIXED;
     if (ps == 3 && pa == 5)
-        e = mixed ? apply_t<float, 3, 5>(p, dens, nrhs, out, kappa, st) : apply_t<double, 3, 5>(p, dens, nrhs, out, kappa, st);
+        e = mixed ? apply_t<float, 3, 5>(p, dens, nrhs, out, adj, st) : apply_t<double, 3, 5>(p, dens, nrhs, out, adj, st);
     else if (ps == 4 && pa == 6)
-        e = mixed ? apply_t<float, 4, 6>(p, dens, nrhs, out, kappa, st) : apply_t<double, 4, 6>(p, dens, nrhs, out, kappa, st);
+        e = mixed ? apply_t<float, 4, 6>(p, dens, nrhs, out, adj, st) : apply_t<double, 4, 6>(p, dens, nrhs, out, adj, st);
     else if (ps == 2 && pa == 3)
-        e = mixed ? apply_t<float, 2, 3>(p, dens, nrhs, out, kappa, st) : apply_t<double, 2, 3>(p, dens, nrhs, out, kappa, st);
+        e = mixed ? apply_t<float, 2, 3>(p, dens, nrhs, out, adj, st) : apply_t<double, 2, 3>(p, dens, nrhs, out, adj, st);
     else
         return hipErrorInvalidValue;
-    if (e == hipSuccess) note_apply(p, dens, nrhs, kappa);
+    if (e == hipSuccess) note_apply(p, dens, nrhs, adj);
     return e;
 }
 
@@ -2639,9 +2673,8 @@ hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs,
 {
     const int ps = p.hp.ps, pa = p.hp.pang;
     bool mixed = p.precision == IFGF_MIXED;
-    if (nrhs > kMaxRhsPass) return hipErrorInvalidValue;
-    reuse = reuse && p.ws_store && p.stored_valid && p.stored_dens == dens && p.stored_nrhs == nrhs &&
-            p.ws_rb == rb_for(nrhs);
+    reuse = reuse && nrhs <= kMaxRhsPass && p.ws_store && p.stored_valid && p.stored_dens == dens &&
+            p.stored_nrhs == nrhs && p.ws_rb == rb_for(nrhs);
     hipError_t e;
     if (ps == 3 && pa == 5)
         e = mixed ? grad_t<float, 3, 5>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 3, 5>(p, dens, gout, nrhs, grad, reuse, st);
@@ -2651,7 +2684,7 @@ hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs,
         e = mixed ? grad_t<float, 2, 3>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 2, 3>(p, dens, gout, nrhs, grad, reuse, st);
     else
         return hipErrorInvalidValue;
-    if (e == hipSuccess && p.ws_store) {
+    if (e == hipSuccess && p.ws_store && nrhs <= kMaxRhsPass) {
         // the stored cone values now hold these densities (reused or rebuilt)
         p.stored_valid = true;
         p.stored_dens = dens;

@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.ifgf_apply.argtypes = [P, P, I32, P, P]
         L.ifgf_apply_adjoint.argtypes = [P, P, I32, P, P]
         L.ifgf_grad_targets.argtypes = [P, P, P, I32, P, P]
+        L.ifgf_grad_targets_stored.argtypes = [P, P, P, I32, P, P]
         L.ifgf_plan_stats.argtypes = [P, ctypes.POINTER(Stats)]
         L.ifgf_plan_check.argtypes = [P, ctypes.POINTER(I64)]
         L.ifgf_plan_destroy.argtypes = [P]
@@ -108,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.ifgf_last_error.argtypes = []
         L.ifgf_last_error.restype = ctypes.c_char_p
         for f in (L.ifgf_plan_create, L.ifgf_plan_create_targets, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
+                  L.ifgf_grad_targets_stored,
                   L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy, L.ifgf_plan_profile,
                   L.ifgf_plan_stage_times, L.ifgf_plan_autotune, L.ifgf_plan_kernel_choice,
                   L.ifgf_plan_set_kernel_choice, L.ifgf_plan_kernel_candidates):
@@ -317,16 +319,20 @@ class Plan:
     def adjoint(self, v):
         return self.apply(v, adjoint=True)
 
-    def grad_targets(self, a, g):
-        """sum_r Re(conj(g_r) dI_r/dx) for every target, (m, 3) float64."""
+    def grad_targets(self, a, g, stored: bool = False):
+        """sum_r Re(conj(g_r) dI_r/dx) for every target, (m, 3) float64.
+        stored=True reuses the cone values of the last apply when it took the
+        same tensor `a`; the caller guarantees that a has not been modified
+        since (ifgf_grad_targets_stored)."""
         import torch
         a2, _ = self._prep(a, self.n)
         g2, _ = self._prep(g, self.m)
         if g2.shape[0] != a2.shape[0]:
             raise ValueError("grad_out must have as many right-hand sides as the densities")
         out = torch.empty((self.m, 3), dtype=torch.float64, device=a2.device)
-        _check(lib().ifgf_grad_targets(self._h, ctypes.c_void_p(a2.data_ptr()), ctypes.c_void_p(g2.data_ptr()),
-                                       a2.shape[0], ctypes.c_void_p(out.data_ptr()), self._stream(a2)))
+        f = lib().ifgf_grad_targets_stored if stored else lib().ifgf_grad_targets
+        _check(f(self._h, ctypes.c_void_p(a2.data_ptr()), ctypes.c_void_p(g2.data_ptr()),
+                 a2.shape[0], ctypes.c_void_p(out.data_ptr()), self._stream(a2)))
         return out
 
 
@@ -353,7 +359,10 @@ def _function():
             ga = plan.adjoint(g) if ctx.needs_input_grad[1] else None
             gx = None
             if ctx.needs_input_grad[2]:
-                gx = plan.grad_targets(a, g)
+                # a is a saved tensor: autograd has checked that it was not
+                # modified in place since the forward, so the cone values that
+                # apply stored for it may be reused
+                gx = plan.grad_targets(a, g, stored=True)
             return None, ga, gx
 
     return IFGFFunction
