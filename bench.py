@@ -1,23 +1,30 @@
 """Benchmark: IFGF matvecs per second on one MI355X.
 
-Workload: unit sphere, N = 393,216 points (6 x 256 x 256 cube-sphere),
-kappa = 32 pi (diameter 32 wavelengths), complex Gaussian densities,
-(P_s, P_ang) = (3, 5) Chebyshev nodes, 1 x 2 x 4 leaf cones, H_D about a
-quarter wavelength.  One timed step is one IFGF matvec in the mixed path
-(FP32 arithmetic, FP64 geometry and phase reduction) with inputs resident in
-device memory.  Plan construction is excluded from the timed region and
-reported separately (as the paper reports T_pre apart from T_acc).
+Headline workload: unit sphere, N = 6,291,456 points (6 x 1024 x 1024
+cube-sphere), kappa = 128 pi (diameter 128 wavelengths), 4 complex Gaussian
+density vectors per apply, (P_s, P_ang) = (3, 5) Chebyshev nodes, 1 x 2 x 4
+leaf cones, H_D about a quarter wavelength, FP64 arithmetic throughout (the
+precision the oracle and the paper's accuracy figures refer to).  One timed
+step is one IFGF apply of the 4 right-hand sides with inputs resident in
+device memory; value = 4 / (seconds per step) matvecs per second.  Plan
+construction is excluded from the timed region and reported separately (as
+the paper reports T_pre apart from T_acc).
+
+Extras in the same JSON line: the mixed path (FP32 arithmetic, FP64
+geometry) on the same workload, FP64 at 1 right-hand side, and the figures
+of the N = 393,216, kappa = 32 pi sphere (mixed 1 and 16 right-hand sides,
+FP64, adjoint, graph replay, target gradient).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+       [--no-extras] [--workload 5|2] [--precision fp64|mixed]
 Prints one JSON line.
 
 Profiling: `python bench.py --profile-commands DIR` prints the four
 rocprofv3 commands (kernel trace with stats; FETCH_SIZE; WRITE_SIZE; SQ
-instruction counters) whose
-outputs `python bench.py --summarize DIR` turns into the summaries under
-profiles/.  The counter runs also time a plain copy kernel of known size
-(--copy-calibration), whose counter readings give the bytes-per-KiB scale
-applied to the IFGF kernels' readings.
+instruction counters) whose outputs `python bench.py --summarize DIR` turns
+into the summaries under profiles/.  The counter runs also time a plain copy
+kernel of known size (--copy-calibration), whose counter readings give the
+bytes-per-KiB scale applied to the IFGF kernels' readings.
 """
 from __future__ import annotations
 
@@ -38,10 +45,6 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-# The paper's time for this workload (Table timings2: sphere, N = 393216,
-# kappa a = 32 pi, eps = 1.13e-3): 133 s per matvec on one core of an
-# i7-8750H.  Another machine's number: context, not a target.
-PAPER_MATVECS_PER_S = 1.0 / 133.0
 
 
 def kernel_source_hash() -> str:
@@ -52,20 +55,26 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-WORKLOAD_TAG = "sphere393216"
-TRACE_ARGS = "--steps 5 --warmup 1 --no-extras --no-cpu-baseline"
-PMC_ARGS = "--steps 2 --warmup 1 --no-extras --no-cpu-baseline --copy-calibration"
+# the profiled configuration: the headline (workload 5, FP64, its 4 RHS)
+PROFILE_WORKLOAD = 5
+PROFILE_PRECISION = "fp64"
+WORKLOAD_TAG = "sphere6291456_fp64_4rhs"
+TRACE_ARGS = "--steps 2 --warmup 1 --no-extras --no-cpu-baseline"
+PMC_ARGS = "--steps 1 --warmup 1 --no-extras --no-cpu-baseline --copy-calibration"
 SQ_ARGS = "--steps 1 --warmup 1 --no-extras --no-cpu-baseline"
-SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VALU_MFMA_F32 SQ_VALU_MFMA_BUSY_CYCLES "
-               "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_INST_LDS")
+SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VALU_MFMA_F32 SQ_INSTS_VALU_MFMA_F64 "
+               "SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_LDS")
 SIMDS = 1024                   # 256 CUs x 4 SIMDs
 CLOCK_HZ = 2.4e9
 COPY_NUMEL = 64 << 20          # float32 elements read and written by the calibration copy
+# child-to-parent variants that run on the matrix cores
+MFMA_VARIANTS = ("mfma", "mfma_geometry", "boxes")
 
 
 def profile_commands(d: str) -> list[str]:
     return [
-        f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- python3 bench.py {TRACE_ARGS}",
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- python3 bench.py {TRACE_ARGS} "
+        f"--stats-out {d}/plan_stats.json",
         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- python3 bench.py {PMC_ARGS}",
         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- python3 bench.py {PMC_ARGS}",
         f"rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d {d}/sq -o run -- python3 bench.py {SQ_ARGS}",
@@ -126,7 +135,7 @@ def summarize(d: str) -> int:
         a[0] += 1
         a[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
     total = sum(v[1] for v in agg.values())
-    lines = [f"# Kernel trace, {WORKLOAD_TAG} (mixed, 1 RHS): {TRACE_ARGS}", "",
+    lines = [f"# Kernel trace, {WORKLOAD_TAG}: {TRACE_ARGS}", "",
              "Command (repository root):", "", "    " + cmds[0], "",
              f"Launches of the {steps} timed matvecs (autotuning and warm-up launches excluded).", "",
              "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
@@ -141,9 +150,9 @@ def summarize(d: str) -> int:
     with open(os.path.join(out_dir, f"{stage}_{WORKLOAD_TAG}_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(lines))
     # HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
-    rec = {"kernel_source_hash": kernel_source_hash(), "nrhs": 1, "stage": stage, "workload": WORKLOAD_TAG,
+    rec = {"kernel_source_hash": kernel_source_hash(), "stage": stage, "workload": WORKLOAD_TAG,
            "commands": cmds[1:]}
-    md = [f"# HBM traffic of `{stage}`, {WORKLOAD_TAG} (mixed, 1 RHS)", "", "Commands (repository root):", ""]
+    md = [f"# HBM traffic of `{stage}`, {WORKLOAD_TAG}", "", "Commands (repository root):", ""]
     md += ["    " + c for c in cmds[1:]] + [""]
     psteps = _steps(PMC_ARGS)
     for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
@@ -204,9 +213,7 @@ def summarize_sq(d: str, cmd: str, trace_rows: list) -> None:
     occupies a SIMD for 4 cycles, a 16x16x4 FP32 MFMA for 32)."""
     import collections
     import csv
-    from paper_2010_02857_amd import ifgf, inputs
-    w = inputs.WORKLOADS[2]
-    st = ifgf.Plan(w.points(), w.kappa, host_only=True).stats()
+    st = json.load(open(os.path.join(d, "plan_stats.json")))
     evals = st["n_parent_evals"]
     D = st["D"]
     rows = _timed(list(csv.DictReader(open(_find(os.path.join(d, "sq"), "counter_collection.csv")))),
@@ -220,22 +227,23 @@ def summarize_sq(d: str, cmd: str, trace_rows: list) -> None:
     # durations of the same launches in the trace run (its first timed matvec)
     dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
            for r in sorted(trace_rows, key=lambda r: int(r["Dispatch_Id"])) if "k_child_to_parent" in r["Kernel_Name"]]
-    lines = [f"# Instruction mix of `child_to_parent`, {WORKLOAD_TAG} (mixed, 1 RHS)", "",
+    lines = [f"# Instruction mix of `child_to_parent`, {WORKLOAD_TAG}", "",
              "Command (repository root):", "", "    " + cmd, "",
              "One timed matvec; launches in order of the child level.  Per evaluation: lane instructions "
-             "(wave instructions x 64) per (parent interpolation point, child) evaluation.  Issue fractions: "
+             "(wave instructions x 64) per (parent interpolation point, child) evaluation (MFMA F64: wave "
+             "instructions per evaluation).  Issue fractions: "
              f"VALU = 4 x wave VALU instructions, MFMA = busy cycles, over {SIMDS} SIMDs x "
              f"{CLOCK_HZ / 1e9:.1f} GHz x the launch's duration in the kernel trace.", "",
-             "| child level | kernel | ms | VALU / eval | LDS / eval | VALU issue | MFMA busy |",
-             "|---|---|---|---|---|---|---|"]
+             "| child level | kernel | ms | VALU / eval | LDS / eval | MFMA F64 / eval | VALU issue | MFMA busy |",
+             "|---|---|---|---|---|---|---|---|"]
     for i, (k, e) in enumerate(per.items()):
         lvl = D - i
         t = dur[i] if i < len(dur) else float("nan")
         cap = SIMDS * CLOCK_HZ * t
         ev = max(evals[lvl], 1)
         lines.append(f"| {lvl} | `{e['name']}` | {t * 1e3:.3f} | {e.get('SQ_INSTS_VALU', 0) * 64 / ev:.0f} | "
-                     f"{e.get('SQ_INSTS_LDS', 0) * 64 / ev:.0f} | {4 * e.get('SQ_INSTS_VALU', 0) / cap:.2f} | "
-                     f"{e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / cap:.2f} |")
+                     f"{e.get('SQ_INSTS_LDS', 0) * 64 / ev:.0f} | {e.get('SQ_INSTS_VALU_MFMA_F64', 0) / ev:.2f} | "
+                     f"{4 * e.get('SQ_INSTS_VALU', 0) / cap:.2f} | {e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / cap:.2f} |")
     lines.append("")
     # the other stages, per kernel over the matvec: VALU issue (transcendentals
     # included) and MFMA busy against the same capacity
@@ -295,15 +303,49 @@ def stage_work(stats: dict, stage: str, nrhs: int, P: int, elem_bytes: int) -> t
     return 0.0, 2 * n * nrhs * elem_bytes
 
 
+def roofline_of(stats: dict, stages: dict, levels: dict, choice: dict, nrhs: int, steps: int, P: int,
+                elem_bytes: int, fp64: bool, traffic) -> dict:
+    """Roofline of the child-to-parent stage (the dominant one): algorithmic
+    flops of one launch (the plan's (parent point, child) evaluations x
+    (4 P + 8) flops x right-hand sides) over its average launch duration,
+    measured with HIP events on its stream over the timed region; per level
+    too, with the variant that ran there."""
+    ms, launches = stages["child_to_parent"]
+    flops, byts = stage_work(stats, "child_to_parent", nrhs, P, elem_bytes)
+    per_launch_s = ms / 1e3 / launches
+    lpa = launches / steps
+    achieved = flops / lpa / per_launch_s / 1e12
+    mfma = all(choice.get(d) in MFMA_VARIANTS for d in levels)
+    peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
+    per_level = {}
+    for d, (lms, lcnt) in sorted(levels.items()):
+        ev = stats["n_parent_evals"][d] * nrhs * (4 * P + 8)
+        t = lms / 1e3 / lcnt
+        per_level[str(d)] = {"variant": choice.get(d), "avg_ms": round(t * 1e3, 3),
+                             "TFLOPs": round(ev / t / 1e12, 3), "frac": round(ev / t / 1e12 / peak, 4)}
+    return {"bound": "mfma" if mfma else "alu", "kernel": "child_to_parent", "achieved": round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": traffic,
+            "avg_launch_ms": round(per_launch_s * 1e3, 4), "launches_per_step": lpa,
+            "algorithmic_flops_per_launch": flops / lpa, "algorithmic_bytes_per_launch": byts / lpa,
+            "achieved_algorithmic_GBps": round(byts / lpa / per_launch_s / 1e9, 1), "hbm_peak_GBps": PEAK_HBM_GBS,
+            "peak_note": ("FP64: 78.6 TFLOP/s for both the vector units and the matrix cores" if fp64 else
+                          "FP32: 157.3 TFLOP/s (matrix cores; packed vector FP32, not used here)"),
+            "per_level": per_level}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=PROFILE_WORKLOAD, choices=(2, 5))
+    ap.add_argument("--precision", default=PROFILE_PRECISION, choices=("fp64", "mixed"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / batched / adjoint / gradient timings")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and workloads")
+    ap.add_argument("--autotune", action="store_true", help="autotune the headline plan (default: the default rule)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy of known size (for scaling HBM byte counters)")
+    ap.add_argument("--stats-out", metavar="FILE", help="write the headline plan's statistics as JSON")
     ap.add_argument("--profile-commands", metavar="DIR", help="print the profiling commands and exit")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from profiling outputs and exit")
     args = ap.parse_args()
@@ -322,6 +364,9 @@ def main() -> int:
     import oracle
     from paper_2010_02857_amd import ifgf, inputs
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
     if args.copy_calibration:
         src = torch.ones(COPY_NUMEL, dtype=torch.float32, device="cuda")
@@ -330,36 +375,52 @@ def main() -> int:
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    w = inputs.WORKLOADS[2]
+    w = inputs.WORKLOADS[args.workload]
     p = w.points()
     n = p.shape[0]
+    nrhs = w.nrhs
+    prec = args.precision
+    fp64 = prec == "fp64"
+    cdt = torch.complex128 if fp64 else torch.complex64
     a = w.densities()
     P = 75
 
-    def log(msg):
-        print(msg, file=sys.stderr, flush=True)
+    def time_fn(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(reps):
+            fn()
+        s1.record()
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / reps
 
     # ---- plan (excluded from the timed region)
     t0 = time.time()
-    plan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=16, store_levels=0)
+    plan = ifgf.Plan(p, w.kappa, precision=prec, max_nrhs=nrhs, store_levels=0)
     t_plan = time.time() - t0
     st = plan.stats()
-    log(f"plan: N={n} D={st['D']} cones/level={st['n_cones'][3:]} {t_plan:.1f}s")
-    # kernel selection per level (part of the set-up, like the plan)
-    t0 = time.time()
-    plan.autotune(1)
-    if not args.no_extras:
-        plan.autotune(16)
-    t_tune = time.time() - t0
-    choice = {str(d): v for d, v in plan.kernel_choice(1).items()}
-    log(f"autotune {t_tune:.2f}s: {choice}")
-    x = torch.from_numpy(a).to(torch.complex64).cuda()
+    log(f"plan: {w.name} N={n} D={st['D']} {prec} cones/level={st['n_cones'][3:]} {t_plan:.1f}s "
+        f"device {st['device_bytes'] / 1e9:.2f} GB")
+    if args.stats_out:
+        with open(args.stats_out, "w") as fh:
+            json.dump(st, fh)
+    t_tune = 0.0
+    if args.autotune:
+        t0 = time.time()
+        plan.autotune(nrhs)
+        t_tune = time.time() - t0
+    choice = plan.kernel_choice(nrhs)
+    log(f"child-to-parent kernels ({'autotuned' if args.autotune else 'default rule'}): {choice}")
+    x = torch.from_numpy(a).to(cdt).cuda()
 
     for _ in range(args.warmup):
         plan.apply(x)
     torch.cuda.synchronize()
 
-    # ---- timed region: K matvecs, per-stage HIP events on the same stream
+    # ---- timed region: K applies, per-stage HIP events on the launch streams
     plan.profile(True)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -371,148 +432,183 @@ def main() -> int:
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
     stages = plan.stage_times()
+    c2p_levels = plan.level_times("child_to_parent")
+    cousin_levels = plan.level_times("cousin_eval")
     plan.profile(False)
     ms_step = ms_total / args.steps
-    value = 1000.0 / ms_step
-    log(f"mixed 1 RHS: {ms_step:.3f} ms/matvec; stages {stages}")
+    value = nrhs * 1000.0 / ms_step
+    log(f"{prec} {nrhs} RHS: {ms_step:.3f} ms/apply; stages {stages}")
     assert plan.misses() == 0
+    ws_bytes = plan.stats()["device_bytes"]
 
-    # ---- accuracy of this result against the direct sum (1000 targets)
-    idx = inputs.error_subset(2, n, 1000)
+    # ---- accuracy against the direct sum on 1000 random targets (every RHS);
+    # the same direct sum, timed, is the CPU baseline (extrapolated)
+    M = 1000
+    idx = inputs.error_subset(args.workload, n, M)
+    t0 = time.time()
     d = oracle.direct(p, a, w.kappa, targets=p[idx], skip=idx)
-    eps = float(np.linalg.norm(out.cpu().numpy()[0, idx] - d[0]) / np.linalg.norm(d[0]))
-    log(f"eps_M vs direct = {eps:.3e}")
+    t_direct = time.time() - t0
+    outh = out.cpu().numpy()
+    eps = float(np.linalg.norm(outh[:, idx] - d) / np.linalg.norm(d))
+    log(f"eps_M vs direct (M={M}, {nrhs} RHS) = {eps:.3e}; direct sum {t_direct:.1f} s")
 
-    # ---- roofline of the dominant forward kernel
-    fwd = ["permute_in", "nearfield", "leaf_nodes", "cousin_eval", "child_to_parent", "permute_out"]
-    dom = max(fwd, key=lambda s: stages[s][0])
-    dom_ms, dom_launches = stages[dom]
-    flops, byts = stage_work(st, dom, 1, P, 8)
-    per_launch_s = dom_ms / 1e3 / dom_launches
-    launches_per_apply = dom_launches / args.steps
-    flops_per_launch = flops / launches_per_apply
-    bytes_per_launch = byts / launches_per_apply
-    achieved = flops_per_launch / per_launch_s / 1e12
+    # ---- roofline of the dominant kernel stage (child-to-parent)
     traffic = None
-    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{WORKLOAD_TAG}.json")
-    if os.path.exists(tf):
+    tf = os.path.join(ROOT, "profiles", f"traffic_child_to_parent_{WORKLOAD_TAG}.json")
+    if (args.workload, prec) == (PROFILE_WORKLOAD, PROFILE_PRECISION) and os.path.exists(tf):
         rec = json.load(open(tf))
-        if rec.get("kernel_source_hash") == kernel_source_hash() and rec.get("nrhs") == 1:
+        if rec.get("kernel_source_hash") == kernel_source_hash():
             traffic = rec.get("hbm_bytes_per_launch")
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
-                "avg_launch_ms": round(per_launch_s * 1e3, 4), "launches_per_step": launches_per_apply,
-                "algorithmic_flops_per_launch": flops_per_launch,
-                "algorithmic_bytes_per_launch": bytes_per_launch,
-                "achieved_algorithmic_GBps": round(bytes_per_launch / per_launch_s / 1e9, 1),
-                "hbm_peak_GBps": PEAK_HBM_GBS}
+    roofline = roofline_of(st, stages, c2p_levels, choice, nrhs, args.steps, P, 16 if fp64 else 8, fp64, traffic)
 
     result = {
         "metric": "IFGF matvecs/s at rel err <=1e-3 (FP64 vs mixed, 1 vs batched RHS); N^2/s",
-        "value": round(value, 3),
+        "value": round(value, 4),
         "unit": "matvecs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(ms_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(value / PAPER_MATVECS_PER_S, 1),
-        "dtype": "f32",
+        "vs_baseline": None,
+        "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "sphere-393216-k32pi", "n": n, "kappa": w.kappa, "nrhs": 1,
-                   "precision": "mixed (f32 arithmetic, f64 geometry)", "degrees": [3, 5], "leaf_cones": [1, 2, 4],
-                   "levels": st["D"]},
+        "config": {"workload": w.name, "n": n, "kappa": w.kappa, "nrhs": nrhs,
+                   "precision": "fp64" if fp64 else "mixed (f32 arithmetic, f64 geometry)", "degrees": [3, 5],
+                   "leaf_cones": [1, 2, 4], "levels": st["D"]},
         "eps_vs_direct": eps,
-        "n2_per_s": n * n * value,
+        "eps_targets": M,
+        "n2_per_s": float(n) * n * value,
         "t_plan_s": round(t_plan, 2),
         "t_autotune_s": round(t_tune, 2),
-        "child_to_parent_kernels": choice,
-        "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
+        "plan_device_bytes": int(st["device_bytes"]),
+        "device_bytes_with_workspaces": int(ws_bytes),
+        "torch_max_allocated_bytes": int(torch.cuda.max_memory_allocated()),
+        "child_to_parent_kernels": {str(k): v for k, v in choice.items()},
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items() if v[1]},
+        "cousin_eval_ms_per_level": {str(k): round(v[0] / args.steps, 3) for k, v in cousin_levels.items()},
         "roofline": roofline,
+        "paper_context": "Table timings1, N = 6291456 sphere row: one matvec on one CPU core of another machine "
+                         "(context only, not a target)",
     }
 
-    # ---- the other paths of the metric (timed outside the main region)
-    if not args.no_extras:
-        def time_fn(fn, reps):
-            fn()
-            torch.cuda.synchronize()
-            s0 = torch.cuda.Event(enable_timing=True)
-            s1 = torch.cuda.Event(enable_timing=True)
-            s0.record()
-            for _ in range(reps):
-                fn()
-            s1.record()
-            torch.cuda.synchronize()
-            return s0.elapsed_time(s1) / reps
-
-        ms_adj = time_fn(lambda: plan.adjoint(x), 5)
-        # the same matvec replayed from a captured HIP graph
-        gplan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=1, store_levels=0, use_graph=True)
-        gplan.autotune(1)
-        gout = torch.empty_like(x)
-        ms_graph = time_fn(lambda: gplan.apply(x, out=gout), 10)
-        graph_eq = bool(torch.equal(gout, plan.apply(x))) if gplan.kernel_choice(1) == plan.kernel_choice(1) else None
-        del gplan
-        g = torch.from_numpy(inputs.densities(402, 1, n)).to(torch.complex64).cuda()
-        ms_grad = time_fn(lambda: plan.grad_targets(x, g), 3)
-        x16 = torch.from_numpy(inputs.densities(2, 16, n)).to(torch.complex64).cuda()
-        plan.apply(x16)
-        plan.profile(True)
-        ms_b16 = time_fn(lambda: plan.apply(x16), 3)
-        st16 = plan.stage_times()
-        plan.profile(False)
-        result["stage_ms_per_step_16rhs"] = {k: round(v[0] / 4, 4) for k, v in st16.items() if v[1]}
-        # the child-to-parent roofline at 16 right-hand sides (matrix cores),
-        # from the same stage timers: 4 applies were recorded
-        c16 = st16.get("child_to_parent")
-        if c16 and c16[1]:
-            fl16, _ = stage_work(st, "child_to_parent", 16, P, 8)
-            avg16 = c16[0] / c16[1] / 1e3
-            ach16 = fl16 / (c16[1] / 4) / avg16 / 1e12
-            result["roofline_16rhs"] = {"bound": "mfma", "kernel": "child_to_parent", "achieved": round(ach16, 3),
-                                        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                                        "frac": round(ach16 / PEAK_FP32_TFLOPS, 5), "avg_launch_ms": round(avg16 * 1e3, 4)}
-        plan_choice16 = plan.kernel_choice(16)
-        del plan
+    if not args.no_extras and args.workload == 5:
+        # FP64 at 1 RHS on the same plan (the plain single-RHS FP64 IFGF)
+        if fp64:
+            x1 = x[:1].contiguous()
+            ms1 = time_fn(lambda: plan.apply(x1), 2)
+            result["fp64_1rhs_matvecs_per_s"] = round(1000.0 / ms1, 4)
+            log(f"fp64 1 RHS: {ms1:.1f} ms")
+        del plan, x
         torch.cuda.empty_cache()
-        plan64 = ifgf.Plan(p, w.kappa, precision="fp64", max_nrhs=1, store_levels=0)
-        x64 = torch.from_numpy(a).cuda()
-        ms64 = time_fn(lambda: plan64.apply(x64), 5)
-        out64 = plan64.apply(x64).cpu().numpy()
-        eps64 = float(np.linalg.norm(out64[0, idx] - d[0]) / np.linalg.norm(d[0]))
-        mixed_vs_fp64 = float(np.linalg.norm(out.cpu().numpy() - out64) / np.linalg.norm(out64))
-        del plan64
+        # the mixed path on the same workload and right-hand sides
+        t0 = time.time()
+        pm = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=nrhs, store_levels=0)
+        t_pm = time.time() - t0
+        xm = torch.from_numpy(a).to(torch.complex64).cuda()
+        pm.profile(True)
+        msm = time_fn(lambda: pm.apply(xm), 5)
+        stm = pm.stage_times()
+        pm.profile(False)
+        outm = pm.apply(xm).cpu().numpy()
+        epsm = float(np.linalg.norm(outm[:, idx] - d) / np.linalg.norm(d))
         result.update({
-            "fp64_1rhs_matvecs_per_s": round(1000.0 / ms64, 3),
-            "fp64_eps_vs_direct": eps64,
-            "mixed_vs_fp64_rel": mixed_vs_fp64,
-            "speedup_mixed_vs_fp64_1rhs": round(ms64 / ms_step, 3),
-            "mixed_16rhs_matvecs_per_s": round(16 * 1000.0 / ms_b16, 3),
-            "speedup_mixed16_vs_fp64_1rhs": round(16 * ms64 / ms_b16, 3),
-            "adjoint_matvecs_per_s": round(1000.0 / ms_adj, 3),
-            "graph_replay_1rhs_matvecs_per_s": round(1000.0 / ms_graph, 3),
-            "graph_replay_equals_eager": graph_eq,
-            "child_to_parent_kernels_16rhs": {str(d): v for d, v in plan_choice16.items()},
-            "grad_targets_per_s": round(1000.0 / ms_grad, 3),
+            "mixed_matvecs_per_s": round(nrhs * 1000.0 / msm, 4),
+            "mixed_ms_per_step": round(msm, 3),
+            "mixed_eps_vs_direct": epsm,
+            "mixed_vs_fp64_rel": float(np.linalg.norm(outm - outh) / np.linalg.norm(outh)) if fp64 else None,
+            "mixed_t_plan_s": round(t_pm, 2),
+            "mixed_child_to_parent_kernels": {str(k): v for k, v in pm.kernel_choice(nrhs).items()},
+            "mixed_stage_ms_per_step": {k: round(v[0] / 6, 3) for k, v in stm.items() if v[1]},
         })
-        log(f"fp64 {ms64:.3f} ms, batched16 {ms_b16:.3f} ms, adjoint {ms_adj:.3f} ms, grad {ms_grad:.3f} ms")
+        if fp64:
+            result["speedup_mixed_vs_fp64"] = round(ms_step / msm, 3)
+            if "fp64_1rhs_matvecs_per_s" in result:
+                result["speedup_mixed_batched_vs_fp64_1rhs"] = round(
+                    result["mixed_matvecs_per_s"] / result["fp64_1rhs_matvecs_per_s"], 3)
+        log(f"mixed {nrhs} RHS: {msm:.1f} ms, eps {epsm:.3e}")
+        del pm, xm
+        torch.cuda.empty_cache()
+        result["sphere393216"] = sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log)
 
-    # ---- the oracle on the host cores (one full matvec of the same workload)
+    # ---- the oracle on the host cores: the O1 direct sum above, on M of the
+    # N targets, extrapolated to one full matvec of all right-hand sides
     if not args.no_cpu_baseline:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t0 = time.time()
-        oracle.ifgf(p, a, w.kappa)
-        t_or = time.time() - t0
-        result["cpu_baseline"] = {"value": round(1.0 / t_or, 5), "unit": "matvecs/s", "cores": cores,
+        full_s = t_direct * n / M
+        result["cpu_baseline"] = {"value": round(nrhs / full_s, 7), "unit": "matvecs/s", "cores": cores,
                                   "kind": "oracle",
-                                  "sample": "one full FP64 oracle IFGF matvec of the same workload (N=393216, "
-                                            "includes the oracle's own hierarchy construction); "
-                                            f"{t_or:.1f} s"}
-        log(f"oracle: {t_or:.1f} s on {cores} threads")
+                                  "sample": f"FP64 direct sum (the oracle's O(N^2) definition) on {M} random "
+                                            f"targets x {n} sources x {nrhs} RHS: {t_direct:.1f} s; extrapolated "
+                                            f"x{n // M} to one full matvec ({full_s:.0f} s)",
+                                  "extrapolated": True}
 
     print(json.dumps(result), flush=True)
     return 0
+
+
+def sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log) -> dict:
+    """The N = 393216, kappa = 32 pi sphere: mixed 1 and 16 RHS (with the
+    child-to-parent roofline of each), FP64 1 RHS, adjoint, graph replay,
+    target gradient."""
+    w = inputs.WORKLOADS[2]
+    p = w.points()
+    n = p.shape[0]
+    a = w.densities()
+    res = {"workload": w.name}
+    t0 = time.time()
+    plan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=16, store_levels=0)
+    res["t_plan_s"] = round(time.time() - t0, 2)
+    st = plan.stats()
+    plan.autotune(1)
+    plan.autotune(16)
+    x = torch.from_numpy(a).to(torch.complex64).cuda()
+    plan.profile(True)
+    ms1 = time_fn(lambda: plan.apply(x), 10)
+    s1 = plan.stage_times()
+    l1 = plan.level_times("child_to_parent")
+    plan.profile(False)
+    ch1 = plan.kernel_choice(1)
+    res["mixed_1rhs_matvecs_per_s"] = round(1000.0 / ms1, 3)
+    res["roofline_1rhs"] = roofline_of(st, s1, l1, ch1, 1, 11, 75, 8, False, None)
+    res["stage_ms_1rhs"] = {k: round(v[0] / 11, 3) for k, v in s1.items() if v[1]}
+    out = plan.apply(x).cpu().numpy()
+    idx = inputs.error_subset(2, n, 1000)
+    d = oracle.direct(p, a, w.kappa, targets=p[idx], skip=idx)
+    res["mixed_eps_vs_direct"] = float(np.linalg.norm(out[:, idx] - d) / np.linalg.norm(d))
+    res["adjoint_matvecs_per_s"] = round(1000.0 / time_fn(lambda: plan.adjoint(x), 5), 3)
+    g = torch.from_numpy(inputs.densities(402, 1, n)).to(torch.complex64).cuda()
+    res["grad_targets_per_s"] = round(1000.0 / time_fn(lambda: plan.grad_targets(x, g), 3), 3)
+    x16 = torch.from_numpy(inputs.densities(2, 16, n)).to(torch.complex64).cuda()
+    plan.profile(True)
+    ms16 = time_fn(lambda: plan.apply(x16), 3)
+    s16 = plan.stage_times()
+    l16 = plan.level_times("child_to_parent")
+    plan.profile(False)
+    res["mixed_16rhs_matvecs_per_s"] = round(16 * 1000.0 / ms16, 3)
+    res["roofline_16rhs"] = roofline_of(st, s16, l16, plan.kernel_choice(16), 16, 4, 75, 8, False, None)
+    res["stage_ms_16rhs"] = {k: round(v[0] / 4, 3) for k, v in s16.items() if v[1]}
+    del plan
+    torch.cuda.empty_cache()
+    gplan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=1, store_levels=0, use_graph=True)
+    gplan.autotune(1)
+    gout = torch.empty_like(x)
+    res["graph_replay_1rhs_matvecs_per_s"] = round(1000.0 / time_fn(lambda: gplan.apply(x, out=gout), 10), 3)
+    res["graph_replay_equals_eager"] = bool(np.array_equal(gout.cpu().numpy(), out)) \
+        if gplan.kernel_choice(1) == ch1 else None
+    del gplan
+    torch.cuda.empty_cache()
+    p64 = ifgf.Plan(p, w.kappa, precision="fp64", max_nrhs=1, store_levels=0)
+    x64 = torch.from_numpy(a).cuda()
+    ms64 = time_fn(lambda: p64.apply(x64), 5)
+    res["fp64_1rhs_matvecs_per_s"] = round(1000.0 / ms64, 3)
+    res["speedup_mixed_vs_fp64_1rhs"] = round(ms64 / ms1, 3)
+    res["speedup_mixed16_vs_fp64_1rhs"] = round(16 * ms64 / ms16, 3)
+    del p64
+    torch.cuda.empty_cache()
+    log(f"sphere393216: {res}")
+    return res
 
 
 if __name__ == "__main__":

@@ -186,6 +186,27 @@ ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, int32_t nrhs, vo
  * same layouts and rules as ifgf_apply.                                    */
 ifgf_status ifgf_apply_adjoint(ifgf_plan_t plan, const void* v, int32_t nrhs, void* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as ifgf_apply, bit for bit, computed with no allocation at all.
+ * The apply's workspaces (densities and output in the plan's point order,
+ * two cone-value buffers, cousin-pair values) are carved from a static
+ * device array of 256 MiB that the library holds on each GPU it runs on
+ * until the process ends; its address is taken when a plan is created on
+ * that GPU.  Everything runs on `stream` (no second stream, no events,
+ * stage timing off for the call).  The plan's own workspaces and any cone
+ * values it stored are left untouched.
+ *   Limit: when the workspaces of this plan and nrhs exceed the array,
+ *   IFGF_E_INVALID_ARG with the byte counts in ifgf_last_error(), and
+ *   nothing is launched.  (N = 6144 at 16 right-hand sides fits; a plan of
+ *   393216 points does not.)
+ *   Every call on one GPU, from any plan, shares that GPU's array and it
+ *   keeps the last call's contents (every part is written before it is
+ *   read): calls that overlap on one GPU race, so order them on one stream
+ *   or synchronise between them.
+ * Arguments and layouts as for ifgf_apply.                                 */
+ifgf_status ifgf_apply_noalloc(ifgf_plan_t plan, const void* densities, int32_t nrhs, void* out, void* stream);
+
 /* Gradient of a real loss L(I) with respect to the target coordinates, the
  * sources held fixed:
  *   grad_xyz[l][c] = sum_r Re( conj(g_r(x_l)) * dI_r(x_l)/dx_{l,c} ),
@@ -292,11 +313,18 @@ typedef enum {
  * enable = 0 stops.  Off by default; recording adds two events per launch. */
 ifgf_status ifgf_plan_profile(ifgf_plan_t plan, int32_t enable);
 
-/* Synchronises, then returns per stage the summed kernel milliseconds and the
- * number of launches recorded since profiling was enabled (arrays of
- * IFGF_NUM_STAGES entries, host).  Totals keep accumulating until the next
- * ifgf_plan_profile(plan, 1). */
+/* Synchronises the plan's streams, then returns per stage the summed kernel
+ * milliseconds and the number of launches recorded since profiling was
+ * enabled (arrays of IFGF_NUM_STAGES entries, host).  Totals keep
+ * accumulating until the next ifgf_plan_profile(plan, 1). */
 ifgf_status ifgf_plan_stage_times(ifgf_plan_t plan, double* ms, int64_t* launches);
+
+/* The same totals split by level for one stage (arrays of IFGF_MAX_LEVELS +
+ * 1 entries, host): entry d holds the cousin evaluation of level d, the
+ * child-to-parent step from level d to d - 1, the leaf values at d = D;
+ * stages without a level are reported at entry 0.  Synchronises the plan's
+ * streams first. */
+ifgf_status ifgf_plan_level_times(ifgf_plan_t plan, int32_t stage, double* ms, int64_t* launches);
 
 /* Releases the plan and all memory it owns.  NULL is accepted. */
 ifgf_status ifgf_plan_destroy(ifgf_plan_t plan);

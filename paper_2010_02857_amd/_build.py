@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libifgf.so")
-SOURCES = ["plan.hip", "kernels.hip", "api.hip"]
+SOURCES = ["plan.hip", "plan_gpu.hip", "kernels.hip", "api.hip"]
 ARCH = os.environ.get("IFGF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -135,7 +135,11 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
             if ((e = upload(p, H.chl_start, &L.chl_start)) != hipSuccess) return e;
         }
         L.use_pairs = H.use_pairs ? 1 : 0;
-        if (H.use_pairs) {
+        if (H.use_pairs && H.pairs_device) {
+            // computed in device memory from this level's tables (uploaded above)
+            if ((e = build_pairs_device(p, d, H.pairs_ordered)) != hipSuccess) return e;
+            p.max_pairs = std::max<int64_t>(p.max_pairs, (int64_t)H.pair_base[H.nbox]);
+        } else if (H.use_pairs) {
             L.npairs_cou = (long long)H.pr_slot.size();
             std::vector<long long> pb(H.pair_base.begin(), H.pair_base.end());
             if ((e = upload(p, pb, &L.pair_base)) != hipSuccess) return e;
@@ -300,8 +304,13 @@ static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt,
             size_t fr = 0, tot = 0;
             if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min(0.25 * (double)fr, 64.0 * (1ull << 30));
         }
+        // relevant cones and pair tables on the GPU (IFGF_HOST_PLAN=1: on the host)
+        std::unique_ptr<ifgf::ConeMarker> marker;
+        const char* hv = std::getenv("IFGF_HOST_PLAN");
+        const bool on_gpu = !p.host_only && !(hv && std::atoi(hv) != 0);
+        if (on_gpu) marker = ifgf::make_gpu_cone_marker();
         msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes,
-                                    ord_bytes, budget, p.hp, code);
+                                    ord_bytes, budget, p.hp, code, marker.get(), on_gpu);
     } catch (const std::bad_alloc&) {
         delete pl;
         return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed while building the plan");
@@ -321,6 +330,13 @@ static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt,
             return hip_fail(e, "hipGetDevice");
         }
         p.device = dev;
+        // the device's scratch address for ifgf_apply_noalloc, taken at set-up
+        // (once per device, with the plan's device current)
+        e = ifgf::scratch_init(dev);
+        if (e != hipSuccess) {
+            delete pl;
+            return hip_fail(e, "taking the address of the device scratch array");
+        }
         e = upload_plan(p);
         if (e != hipSuccess) {
             release(p);
@@ -509,6 +525,23 @@ ifgf_status ifgf_apply_adjoint(ifgf_plan_t plan, const void* v, int32_t nrhs, vo
     return apply_common(plan, v, nrhs, out, stream, true);
 }
 
+ifgf_status ifgf_apply_noalloc(ifgf_plan_t plan, const void* densities, int32_t nrhs, void* out, void* stream)
+{
+    ifgf_status s = check_apply_args(plan, densities, out, nrhs);
+    if (s != IFGF_OK) return s;
+    ifgf::DevicePlan& p = plan->p;
+    const size_t need = ifgf::noalloc_bytes(p, nrhs), have = ifgf::scratch_bytes();
+    if (need > have)
+        return fail(IFGF_E_INVALID_ARG, "ifgf_apply_noalloc: the workspaces of this plan and nrhs need " +
+                                            std::to_string(need) + " bytes, more than the " + std::to_string(have) +
+                                            "-byte device scratch array; use ifgf_apply");
+    DeviceGuard g(p.device);
+    p.last_stream = (hipStream_t)stream;
+    hipError_t e = ifgf::run_apply_noalloc(p, densities, nrhs, out, false, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ifgf_apply_noalloc");
+    return IFGF_OK;
+}
+
 static ifgf_status grad_common(ifgf_plan_t plan, const void* densities, const void* grad_out, int32_t nrhs,
                                double* grad_xyz, void* stream, bool reuse)
 {
@@ -567,16 +600,41 @@ ifgf_status ifgf_plan_profile(ifgf_plan_t plan, int32_t enable)
     if (p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
     DeviceGuard g(p.device);
     if (enable) {
-        hipError_t e = hipDeviceSynchronize();
+        hipError_t e = hipStreamSynchronize(p.last_stream);
+        if (e == hipSuccess && p.side) e = hipStreamSynchronize(p.side);
         if (e != hipSuccess) return hip_fail(e, "ifgf_plan_profile");
         p.pending.clear();
         p.next_event = 0;
         for (int i = 0; i < IFGF_NUM_STAGES; ++i) {
             p.stage_ms[i] = 0.0;
             p.stage_launches[i] = 0;
+            for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) {
+                p.level_ms[i][d] = 0.0;
+                p.level_launches[i][d] = 0;
+            }
         }
     }
     p.profiling = enable != 0;
+    return IFGF_OK;
+}
+
+// Folds the recorded event pairs into the per-stage and per-level totals.
+static ifgf_status collect_times(ifgf::DevicePlan& p)
+{
+    hipError_t e = hipStreamSynchronize(p.last_stream);
+    if (e == hipSuccess && p.side) e = hipStreamSynchronize(p.side);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+    for (const auto& q : p.pending) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, p.events[q.e0], p.events[q.e1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        p.stage_ms[q.stage] += t;
+        p.stage_launches[q.stage] += 1;
+        p.level_ms[q.stage][q.level] += t;
+        p.level_launches[q.stage][q.level] += 1;
+    }
+    p.pending.clear();
+    p.next_event = 0;
     return IFGF_OK;
 }
 
@@ -586,20 +644,27 @@ ifgf_status ifgf_plan_stage_times(ifgf_plan_t plan, double* ms, int64_t* launche
     ifgf::DevicePlan& p = plan->p;
     if (p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
     DeviceGuard g(p.device);
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "ifgf_plan_stage_times");
-    for (const auto& q : p.pending) {
-        float t = 0.f;
-        e = hipEventElapsedTime(&t, p.events[q.e0], p.events[q.e1]);
-        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-        p.stage_ms[q.stage] += t;
-        p.stage_launches[q.stage] += 1;
-    }
-    p.pending.clear();
-    p.next_event = 0;
+    ifgf_status s = collect_times(p);
+    if (s != IFGF_OK) return s;
     for (int i = 0; i < IFGF_NUM_STAGES; ++i) {
         ms[i] = p.stage_ms[i];
         launches[i] = p.stage_launches[i];
+    }
+    return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_level_times(ifgf_plan_t plan, int32_t stage, double* ms, int64_t* launches)
+{
+    if (!plan || !ms || !launches) return fail(IFGF_E_INVALID_ARG, "NULL argument");
+    if (stage < 0 || stage >= IFGF_NUM_STAGES) return fail(IFGF_E_INVALID_ARG, "unknown stage");
+    ifgf::DevicePlan& p = plan->p;
+    if (p.host_only) return fail(IFGF_E_UNSUPPORTED, "plan was created with host_only");
+    DeviceGuard g(p.device);
+    ifgf_status s = collect_times(p);
+    if (s != IFGF_OK) return s;
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) {
+        ms[d] = p.level_ms[stage][d];
+        launches[d] = p.level_launches[stage][d];
     }
     return IFGF_OK;
 }

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -175,6 +176,8 @@ struct HostLevel {
     // slot of the cone of cousin c that contains t, t's local coordinates in
     // it and the centred factor G(x_t, x_c); built when they fit the budget.
     bool use_pairs = false;
+    bool pairs_device = false;                // built in device memory (plan_gpu.hip), not here
+    bool pairs_ordered = false;               // with the cone-ordered copy
     std::vector<int64_t> pair_base;           // [nbox + 1]
     std::vector<int32_t> pr_slot;             // [npairs]
     std::vector<double> pr_t;                 // [3][npairs] (structure of arrays)
@@ -196,14 +199,30 @@ struct HostPlan {
     ifgf_stats stats{};
 };
 
+// Marks and numbers the relevant cone segments of one level (rules (i) and
+// (ii) of Sec. 3.3.2) in place of the host loop: fills hp.L[d]'s nslots,
+// slot_start, slot_box, slot_cone, cell_base and cell_mask exactly as the
+// host builder would, and adds the cones marked only by dilation to
+// n_dilated.  Returns "" or a message (code set).
+struct ConeMarker {
+    virtual ~ConeMarker() = default;
+    virtual std::string mark_level(HostPlan& hp, int d, bool dilate, int64_t& n_dilated, ifgf_status& code) = 0;
+};
+// The device implementation (plan_gpu.hip); uses the current GPU.
+std::unique_ptr<ConeMarker> make_gpu_cone_marker();
+
 // Builds the hierarchy; returns an empty string on success, else a message.
 // `code` receives the ifgf_status on failure.
 // tab_elem_bytes: device bytes of one tabulated cousin-target pair (0: none);
 // ord_elem_bytes: device bytes of its cone-ordered copy (0: none);
 // pair_budget: device bytes the pair tables may take.
+// marker: numbers the relevant cones (null: on the host).
+// pairs_device: the pair tables are left to build_pairs_device (only their
+// offsets pair_base are built here).
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
                             int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
-                            double pair_budget, HostPlan& hp, ifgf_status& code);
+                            double pair_budget, HostPlan& hp, ifgf_status& code, ConeMarker* marker = nullptr,
+                            bool pairs_device = false);
 
 // ---------------------------------------------------------- device mirror
 
@@ -263,6 +282,19 @@ struct LevelDev {
     const void* pro_g;
 };
 
+// Slot of cone (cell, i_s) of `box`, or -1 if it was not marked relevant.
+__device__ inline int lookup(const LevelDev& L, int box, int cell, int is)
+{
+    size_t c = (size_t)box * L.ncell + cell;
+    const unsigned long long* M = L.cell_mask + c * L.W;
+    int w = is >> 6, bit = is & 63;
+    unsigned long long m = M[w];
+    if (!((m >> bit) & 1ull)) return -1;
+    int cnt = __popcll(m & ((1ull << bit) - 1ull));
+    for (int i = 0; i < w; ++i) cnt += __popcll(M[i]);
+    return L.cell_base[c] + cnt;
+}
+
 struct KernelConsts {
     ChebNodes cs, ca;        // radial and angular node sets
     double kappa;            // wavenumber of the phases: k, or -k for the adjoint
@@ -311,10 +343,14 @@ struct DevicePlan {
     bool profiling = false;
     std::vector<hipEvent_t> events;
     size_t next_event = 0;
-    struct Pending { int stage; size_t e0, e1; };
+    struct Pending { int stage, level; size_t e0, e1; };
     std::vector<Pending> pending;
     double stage_ms[IFGF_NUM_STAGES] = {};
     int64_t stage_launches[IFGF_NUM_STAGES] = {};
+    // the same per level (stages of one level: cousin evaluation d, the
+    // child-to-parent step from d; others at level 0)
+    double level_ms[IFGF_NUM_STAGES][IFGF_MAX_LEVELS + 1] = {};
+    int64_t level_launches[IFGF_NUM_STAGES][IFGF_MAX_LEVELS + 1] = {};
     // child-to-parent variant per (right-hand-side block 1 / 4 / 16, level),
     // -1: the default rule; set by ifgf_plan_autotune
     int c2p_choice[3][IFGF_MAX_LEVELS + 1];
@@ -331,6 +367,7 @@ struct DevicePlan {
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> sync_ev;   // [0] inputs permuted, [1] side done, then cone levels ready / read
     bool capturing = false;            // an apply graph is being captured
+    bool no_alloc = false;             // ifgf_apply_noalloc: one stream, scratch workspaces
     // captured apply graphs (use_graph)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -350,7 +387,7 @@ struct DevicePlan {
 // Records a HIP event pair around one kernel launch when profiling is on.
 class StageTimer {
   public:
-    StageTimer(DevicePlan& p, int stage, hipStream_t st) : p_(p), stage_(stage), st_(st)
+    StageTimer(DevicePlan& p, int stage, hipStream_t st, int level = 0) : p_(p), stage_(stage), level_(level), st_(st)
     {
         if (p_.profiling) e0_ = record();
     }
@@ -358,7 +395,7 @@ class StageTimer {
     {
         if (p_.profiling && e0_ != (size_t)-1) {
             size_t e1 = record();
-            if (e1 != (size_t)-1) p_.pending.push_back({stage_, e0_, e1});
+            if (e1 != (size_t)-1) p_.pending.push_back({stage_, level_, e0_, e1});
         }
     }
 
@@ -375,7 +412,7 @@ class StageTimer {
         return i;
     }
     DevicePlan& p_;
-    int stage_;
+    int stage_, level_;
     hipStream_t st_;
     size_t e0_ = (size_t)-1;
 };
@@ -384,6 +421,9 @@ class StageTimer {
 // (windows swapped, kernel conjugated).  Each enqueues on `stream` and
 // returns hipSuccess or the first launch error.
 hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t stream);
+// Level d's cousin-target pair table (and with `ordered` its cone-ordered
+// copy) computed in device memory from the uploaded level (plan_gpu.hip).
+hipError_t build_pairs_device(DevicePlan& p, int d, bool ordered);
 // Allocates the workspaces an apply with nrhs right-hand sides needs (so
 // that the apply itself allocates nothing and can be captured).
 hipError_t run_prepare(DevicePlan& p, int nrhs);
@@ -402,5 +442,14 @@ int kernel_candidates(const DevicePlan& p, int nrhs, int d, int* v);
 bool set_kernel_choice(DevicePlan& p, int nrhs, int d, int variant);
 hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,
                     hipStream_t stream);
+// The apply with its workspaces in the library's static per-GPU scratch
+// array (no allocation, everything on `stream`); hipErrorOutOfMemory when
+// they do not fit in scratch_bytes().
+hipError_t run_apply_noalloc(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t stream);
+// Takes the current device's scratch address (once per device).
+hipError_t scratch_init(int device);
+size_t scratch_bytes();
+// Scratch bytes an apply of nrhs right-hand sides needs in that mode.
+size_t noalloc_bytes(const DevicePlan& p, int nrhs);
 
 }  // namespace ifgf

@@ -13,6 +13,7 @@
 #include "ifgf_internal.hpp"
 
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
 
 namespace ifgf {
@@ -122,18 +123,6 @@ __device__ inline void lagrange_d(double t, const ChebNodes& cn, T* L, T* dL)
     }
 }
 
-// Slot of cone (cell, i_s) of `box`, or -1 if it was not marked relevant.
-__device__ inline int lookup(const LevelDev& L, int box, int cell, int is)
-{
-    size_t c = (size_t)box * L.ncell + cell;
-    const unsigned long long* M = L.cell_mask + c * L.W;
-    int w = is >> 6, bit = is & 63;
-    unsigned long long m = M[w];
-    if (!((m >> bit) & 1ull)) return -1;
-    int cnt = __popcll(m & ((1ull << bit) - 1ull));
-    for (int i = 0; i < w; ++i) cnt += __popcll(M[i]);
-    return L.cell_base[c] + cnt;
-}
 
 // sum_{a,b,c} F[a][b][c][r] Ls[a] Lt[b] Lp[c] for the RB right-hand sides,
 // contracted one direction at a time (phi, then theta, then s), which needs
@@ -825,13 +814,22 @@ constexpr int lds_threads()
     return kBlock;
 }
 
-// Batched child-to-parent interpolation on the matrix cores (16 complex
-// right-hand sides, FP32).  One wavefront handles one parent slot.  For every
-// child octant and every child cone ("group") the frame's interpolation
-// points falling into that cone form the rows of 16 x 16 x 4 FP32 MFMA tiles:
+// Wavefronts per block of the per-slot matrix-core kernels: 4, fewer when the
+// slots' accumulators (P x 2 RB values each) would pass 40 KB of LDS.
+template <typename T, int P, int RB>
+constexpr int mfma_waves()
+{
+    return (4 * P * 2 * RB * (int)sizeof(T) <= 40960) ? 4 : ((2 * P * 2 * RB * (int)sizeof(T) <= 40960) ? 2 : 1);
+}
+
+// Batched child-to-parent interpolation on the matrix cores (FP32, or FP64
+// with the FP64 matrix instruction).  One wavefront handles one parent slot.
+// For every child octant and every child cone ("group") the frame's
+// interpolation points falling into that cone form the rows of 16 x 16 x 4
+// MFMA tiles:
 //   D[row][col] = sum_k A[row][k] B[k][col],
 // A = the tensor Chebyshev weights of the row's point, B = the child cone's
-// values, 32 real columns (re, im of 16 right-hand sides) in two tiles.  The
+// values, 2 RB real columns (re, im of RB right-hand sides) in tiles of 16.  The
 // K index is ordered so that lane quarter q (lanes 16q..16q+15) always takes
 // the phi-node c = q: its weights are Ls[a] Lt[b] Lp[q] with (a, b) fixed
 // per step; the remaining phi-nodes c >= 4 follow in a short tail.  The
@@ -839,18 +837,34 @@ constexpr int lds_threads()
 // wavefront's own LDS copy of the slot's values, so no two wavefronts write
 // the same data and the result does not depend on scheduling.
 typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 matrix-core product in the operand type: FP32
+// (v_mfma_f32_16x16x4_f32) or FP64 (v_mfma_f64_16x16x4_f64).  Both take the
+// same lane layout: A[lane % 16][lane / 16], B[lane / 16][lane % 16], and
+// D[4 (lane / 16) + i][lane % 16] in element i of the result.
+template <typename T> struct MfmaVec;
+template <> struct MfmaVec<float> { typedef mf4 type; };
+template <> struct MfmaVec<double> { typedef md4 type; };
+template <typename T>
+using mvec = typename MfmaVec<T>::type;
+__device__ inline mf4 mfma16(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline md4 mfma16(double a, double b, md4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // v[i] for a lane-dependent i, as a chain of selects on register values.
 // The empty asm makes each element opaque, so the compiler cannot fold the
 // chain back into an indexed load, which would move the array to scratch
 // memory and make every use wait for all outstanding global loads.
-template <int N>
-__device__ inline float pick(const float* v, int i)
+template <int N, typename T>
+__device__ inline T pick(const T* v, int i)
 {
-    float x = v[0];
+    T x = v[0];
 #pragma unroll
     for (int j = 1; j < N; ++j) {
-        float y = v[j];
+        T y = v[j];
         asm("" : "+v"(y));
         x = i == j ? y : x;
     }
@@ -861,42 +875,42 @@ __device__ inline float pick(const float* v, int i)
 // columns the NC real values of the RB right-hand sides in NT tiles of 16.
 // `b` holds the child cone's values as B operands (K ordering as described
 // above); Ls/Lt/Lpv are the Chebyshev weights of this lane's row.
-template <int PS, int PA, int NT>
-__device__ inline void mfma_tile(const float (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4], const float* Ls,
-                                 const float* Lt, const float* Lpv, int q, mf4* c)
+template <int PS, int PA, int NT, typename T>
+__device__ inline void mfma_tile(const T (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4], const T* Ls,
+                                 const T* Lt, const T* Lpv, int q, mvec<T>* c)
 {
     constexpr int NAB = PS * PA;
     constexpr int NREM = NAB * (PA - 4);
     constexpr int KTAIL = (NREM + 3) / 4;
-    const float lq = pick<4>(Lpv, q);
+    const T lq = pick<4>(Lpv, q);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) c[t] = mf4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NT; ++t) c[t] = mvec<T>{(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
     for (int ab = 0; ab < NAB; ++ab) {
         const int a = ab / PA, bb = ab - a * PA;
-        const float w = Ls[a] * Lt[bb] * lq;
+        const T w = Ls[a] * Lt[bb] * lq;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b[t][ab], c[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) c[t] = mfma16(w, b[t][ab], c[t]);
     }
 #pragma unroll
     for (int jt = 0; jt < KTAIL; ++jt) {
         const int m = 4 * jt + q;
-        float w = 0.f;
+        T w = (T)0;
         if (m < NREM) {
             const int abm = m / (PA - 4), cc = 4 + (m - abm * (PA - 4));
             const int a = abm / PA, bb = abm - a * PA;
             w = pick<PS>(Ls, a) * pick<PA>(Lt, bb) * pick<PA>(Lpv, cc);
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, b[t][NAB + jt], c[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) c[t] = mfma16(w, b[t][NAB + jt], c[t]);
     }
 }
 
 // B operands of a child cone: lane (q, col) takes K entries (a, b, c = q)
 // and the tail entries c >= 4, column 16 t + col of every tile t.
-template <int PS, int PA, int NC, int NT>
-__device__ inline void mfma_load_b(const float* __restrict__ Fcs, int q, int col,
-                                   float (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4])
+template <int PS, int PA, int NC, int NT, typename T>
+__device__ inline void mfma_load_b(const T* __restrict__ Fcs, int q, int col,
+                                   T (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4])
 {
     constexpr int NAB = PS * PA;
     constexpr int NREM = NAB * (PA - 4);
@@ -906,11 +920,11 @@ __device__ inline void mfma_load_b(const float* __restrict__ Fcs, int q, int col
         const int cg = 16 * t + col;
         const bool ok = cg < NC;
 #pragma unroll
-        for (int ab = 0; ab < NAB; ++ab) b[t][ab] = ok ? Fcs[(size_t)(ab * PA + q) * NC + cg] : 0.f;
+        for (int ab = 0; ab < NAB; ++ab) b[t][ab] = ok ? Fcs[(size_t)(ab * PA + q) * NC + cg] : (T)0;
 #pragma unroll
         for (int jt = 0; jt < KTAIL; ++jt) {
             const int m = 4 * jt + q;
-            float v = 0.f;
+            T v = (T)0;
             if (ok && m < NREM) {
                 const int abm = m / (PA - 4), cc = 4 + (m - abm * (PA - 4));
                 v = Fcs[(size_t)(abm * PA + cc) * NC + cg];
@@ -923,62 +937,60 @@ __device__ inline void mfma_load_b(const float* __restrict__ Fcs, int q, int col
 // Epilogue of a tile: rows 4q + i, column col of each tile; multiply by the
 // row's ratio (complex: columns 2r, 2r+1 are re, im of right-hand side r) and
 // accumulate into the wavefront's LDS values of the parent slot.
-template <int NC, int NT>
-__device__ inline void mfma_epilogue(const mf4* c, int q, int col, int t0, int cnt, const int* rownode,
-                                     const float* ratio_re, const float* ratio_im, float* acc)
+template <int NC, int NT, typename T>
+__device__ inline void mfma_epilogue(const mvec<T>* c, int q, int col, int t0, int cnt, const int* rownode,
+                                     const T* ratio_re, const T* ratio_im, T* acc)
 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int ri = t0 + 4 * q + i;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const float v = c[t][i];
-            const float pv = __shfl_xor(v, 1, 64);
+            const T v = c[t][i];
+            const T pv = __shfl_xor(v, 1, 64);
             const int cg = 16 * t + col;
             if (ri < cnt && cg < NC) {
                 const int nu = rownode[ri];
-                const float gr = ratio_re[ri], gi = ratio_im[ri];
-                const float o = (col & 1) == 0 ? v * gr - pv * gi : pv * gi + v * gr;
+                const T gr = ratio_re[ri], gi = ratio_im[ri];
+                const T o = (col & 1) == 0 ? v * gr - pv * gi : pv * gi + v * gr;
                 acc[nu * NC + cg] += o;
             }
         }
     }
 }
 
-template <int PS, int PA, int RB>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RB >= 16 ? 3 : 4)))
-k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
-                                                                 const cpx<float>* __restrict__ Fc,
-                                                                 cpx<float>* __restrict__ Fp)
+template <typename T, int PS, int PA, int RB, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (RB >= 16 ? 1 : 2) : (RB >= 16 ? 3 : 4))))
+k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* __restrict__ Fc,
+                       cpx<T>* __restrict__ Fp)
 {
     constexpr int P = PS * PA * PA;
     constexpr int NC = 2 * RB;                 // real columns
     constexpr int NT = (NC + 15) / 16;         // 16-column tiles
     constexpr int G = kMaxFrameGroups;
-    constexpr int W = kBlock / 64;             // wavefronts (parent slots) per block
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
-    __shared__ float accs[W][P * NC];
+    __shared__ T accs[W][P * NC];
     constexpr int ME = 64;                     // entries looked up at once
     __shared__ int sgo[W][9];                  // first entry of each octant
     __shared__ int entcs[W][ME];               // child slot of the entry, -1 missing
     __shared__ int entf[W][ME];                // its frame
     __shared__ int entr[W][ME];                // its rows: first | count << 8 (group order)
     __shared__ int rown[W][P];                 // point of each row of the current group
-    __shared__ float rre[W][P], rim[W][P];     // its ratio
-    __shared__ float rts[W][P], rtt[W][P], rtp[W][P];  // its local coordinates
+    __shared__ T rre[W][P], rim[W][P];         // its ratio
+    __shared__ T rts[W][P], rtt[W][P], rtp[W][P];  // its local coordinates
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int sp = xcd_block(blockIdx.x, gridDim.x) * W + wv;
     if (sp >= Lp.nslots) return;               // whole wavefront leaves; no block barriers below
-    float* acc = accs[wv];
-    for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
+    T* acc = accs[wv];
+    for (int i = lane; i < P * NC; i += 64) acc[i] = (T)0;
 
-    const float* F = (const float*)Fc;
-    const float* frt = (const float*)Lc.fr_t;
-    const float* frr = (const float*)Lc.fr_ratio;
-    const float conj_sign = kc.adj ? -1.f : 1.f;
+    const T* F = (const T*)Fc;
+    const T* frt = (const T*)Lc.fr_t;
+    const T* frr = (const T*)Lc.fr_ratio;
+    const T conj_sign = kc.adj ? (T)-1 : (T)1;
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
     const int j = Lp.slot_box[sp];
 
@@ -1002,9 +1014,9 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
     // loads of entry e: B operands (raw) and its rows' point data; those of
     // the next entry are issued while the current entry's tiles run
     constexpr int RPL = (P + 63) / 64;
-    float bn[NT][NK];
+    T bn[NT][NK];
     int pn[RPL];
-    float pt[RPL][3], pg[RPL][2];
+    T pt[RPL][3], pg[RPL][2];
     auto fetch = [&](int e) {
         const int f = entf[wv][e];
         const int cs = entcs[wv][e];
@@ -1047,7 +1059,7 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
     for (int e = 0; e < ne; ++e) {
         const int cs = entcs[wv][e];
         const int cnt = entr[wv][e] >> 8;
-        float b[NT][NK];
+        T b[NT][NK];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -1073,24 +1085,24 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
         }
         wave_lds_fence();
         for (int t0 = 0; t0 < cnt; t0 += 16) {
-            float Ls[PS], Lt[PA], Lpv[PA];
+            T Ls[PS], Lt[PA], Lpv[PA];
             const int rr = t0 + row;
             const int rc = rr < cnt ? rr : 0;
-            lagrange<float, PS>((double)rts[wv][rc], kc.cs, Ls);
-            lagrange<float, PA>((double)rtt[wv][rc], kc.ca, Lt);
-            lagrange<float, PA>((double)rtp[wv][rc], kc.ca, Lpv);
+            lagrange<T, PS>((double)rts[wv][rc], kc.cs, Ls);
+            lagrange<T, PA>((double)rtt[wv][rc], kc.ca, Lt);
+            lagrange<T, PA>((double)rtp[wv][rc], kc.ca, Lpv);
             if (rr >= cnt) {
 #pragma unroll
-                for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
+                for (int i = 0; i < PS; ++i) Ls[i] = (T)0;
             }
-            mf4 c[NT];
+            mvec<T> c[NT];
             mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
             mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
         }
         wave_lds_fence();
     }
     }
-    float* out = (float*)(Fp + (size_t)sp * P * RB);
+    T* out = (T*)(Fp + (size_t)sp * P * RB);
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
 }
 
@@ -1098,32 +1110,31 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp,
 // child-frame geometry of its interpolation points in FP64 (as
 // k_child_to_parent does), and the wavefront groups the points by child cone
 // with ballots before running the MFMA tiles.
-template <int PS, int PA, int RB>
-__global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
-                                                                     const cpx<float>* __restrict__ Fc,
-                                                                     cpx<float>* __restrict__ Fp)
+template <typename T, int PS, int PA, int RB, int W>
+__global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+                                                                      const cpx<T>* __restrict__ Fc,
+                                                                      cpx<T>* __restrict__ Fp)
 {
     constexpr int P = PS * PA * PA;
     constexpr int NC = 2 * RB;
     constexpr int NT = (NC + 15) / 16;
-    constexpr int W = kBlock / 64;
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
     static_assert(P <= 128, "two passes of 64 points");
-    __shared__ float accs[W][P * NC];
-    __shared__ float nt[W][P][3];              // local coordinates of every point
-    __shared__ float nrr[W][P], nri[W][P];     // ratio of every point
+    __shared__ T accs[W][P * NC];
+    __shared__ T nt[W][P][3];                  // local coordinates of every point
+    __shared__ T nrr[W][P], nri[W][P];         // ratio of every point
     __shared__ int rown[W][P];
-    __shared__ float rre[W][P], rim[W][P];
+    __shared__ T rre[W][P], rim[W][P];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int sp = xcd_block(blockIdx.x, gridDim.x) * W + wv;
     if (sp >= Lp.nslots) return;
-    float* acc = accs[wv];
-    for (int i = lane; i < P * NC; i += 64) acc[i] = 0.f;
+    T* acc = accs[wv];
+    for (int i = lane; i < P * NC; i += 64) acc[i] = (T)0;
 
-    const float* F = (const float*)Fc;
+    const T* F = (const T*)Fc;
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
     const int j = Lp.slot_box[sp];
     const int pcone = Lp.slot_cone[sp];
@@ -1151,15 +1162,15 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConst
                 ConeLoc cl;
                 cone_locate(v[0], v[1], v[2], Lc.h, Lc.ds, Lc.dang, Lc.ns, Lc.nc, cl);
                 key[h] = (unsigned)(cl.cell * Lc.ns + cl.is);
-                nt[wv][nu][0] = (float)cl.ts;
-                nt[wv][nu][1] = (float)cl.tt;
-                nt[wv][nu][2] = (float)cl.tp;
+                nt[wv][nu][0] = (T)cl.ts;
+                nt[wv][nu][1] = (T)cl.tt;
+                nt[wv][nu][2] = (T)cl.tp;
                 const double num = (ov[0] * ov[0] + ov[1] * ov[1] + ov[2] * ov[2]) -
                                    2.0 * (y0 * ov[0] + y1 * ov[1] + y2 * ov[2]);
                 const double diff = num / (cl.r + ry);
-                float cph, sph;
-                expi<float>(kc.kappa * diff, cph, sph);
-                const float mag = (float)(ry / cl.r);
+                T cph, sph;
+                expi<T>(kc.kappa * diff, cph, sph);
+                const T mag = (T)(ry / cl.r);
                 nrr[wv][nu] = mag * cph;
                 nri[wv][nu] = mag * sph;
             }
@@ -1196,30 +1207,30 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent_mfma_geo(KernelConst
                 if (lane == 0) atomicAdd(kc.miss, (unsigned long long)cnt);
                 continue;
             }
-            float b[NT][NK];
+            T b[NT][NK];
             mfma_load_b<PS, PA, NC, NT>(F + (size_t)cs * P * NC, q, col, b);
             for (int t0 = 0; t0 < cnt; t0 += 16) {
-                float Ls[PS], Lt[PA], Lpv[PA];
+                T Ls[PS], Lt[PA], Lpv[PA];
                 const int rr = t0 + row;
                 if (rr < cnt) {
                     const int nu = rown[wv][rr];
-                    lagrange<float, PS>((double)nt[wv][nu][0], kc.cs, Ls);
-                    lagrange<float, PA>((double)nt[wv][nu][1], kc.ca, Lt);
-                    lagrange<float, PA>((double)nt[wv][nu][2], kc.ca, Lpv);
+                    lagrange<T, PS>((double)nt[wv][nu][0], kc.cs, Ls);
+                    lagrange<T, PA>((double)nt[wv][nu][1], kc.ca, Lt);
+                    lagrange<T, PA>((double)nt[wv][nu][2], kc.ca, Lpv);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < PS; ++i) Ls[i] = 0.f;
+                    for (int i = 0; i < PS; ++i) Ls[i] = (T)0;
 #pragma unroll
-                    for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = 0.f;
+                    for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = (T)0;
                 }
-                mf4 c[NT];
+                mvec<T> c[NT];
                 mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
                 mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
                 __threadfence_block();
             }
         }
     }
-    float* out = (float*)(Fp + (size_t)sp * P * RB);
+    T* out = (T*)(Fp + (size_t)sp * P * RB);
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
 }
 
@@ -2122,7 +2133,7 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
         if (groups) v[n++] = kC2PLds;
         if (groups && L.slot_order) v[n++] = kC2PLdsTiled;
     }
-    if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
+    if constexpr (RB >= 4 && PA >= 4 && P <= 128) {
         v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
     }
     if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
@@ -2187,12 +2198,15 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
         break;
     case kC2PMfma:
     case kC2PMfmaGeometry:
-        if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4 && P <= 128) {
-            const unsigned nb = (unsigned)((nps + kBlock / 64 - 1) / (kBlock / 64));
+        if constexpr (RB >= 4 && PA >= 4 && P <= 128) {
+            // wavefronts per block: the slots' accumulators in LDS stay under
+            // about 40 KB per block
+            constexpr int W = mfma_waves<T, P, RB>();
+            const unsigned nb = (unsigned)((nps + W - 1) / W);
             if (variant == kC2PMfma)
-                k_child_to_parent_mfma<PS, PA, RB><<<nb, kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                k_child_to_parent_mfma<T, PS, PA, RB, W><<<nb, 64 * W, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
             else
-                k_child_to_parent_mfma_geo<PS, PA, RB><<<nb, kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                k_child_to_parent_mfma_geo<T, PS, PA, RB, W><<<nb, 64 * W, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
             return;
         }
         break;
@@ -2284,12 +2298,12 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
     const int n = (int)hp.n;
     using C = cpx<T>;
     if (grad) {
-        StageTimer tm_(p, IFGF_STAGE_COUSIN_GRAD, st);
+        StageTimer tm_(p, IFGF_STAGE_COUSIN_GRAD, st, d);
         k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
                                                                      (const C*)p.gout_m, p.grad_m);
         return;
     }
-    StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st);
+    StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st, d);
     bool done = false;
     if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4) {
         if (p.L[d].use_pairs && cousin_mfma_enabled()) {
@@ -2340,7 +2354,7 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
     if (D < 3) return hipSuccess;
     if (!reuse && hp.L[D].nslots > 0)
         {
-            StageTimer tm_(p, IFGF_STAGE_LEAF_NODES, st);
+            StageTimer tm_(p, IFGF_STAGE_LEAF_NODES, st, D);
             k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
                 kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
         }
@@ -2360,7 +2374,7 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                             if ((e = hipStreamWaitEvent(st, ev_read(p, dd), 0)) != hipSuccess) return e;
                             break;
                         }
-                StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st);
+                StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st, d);
                 c2p_launch<T, PS, PA, RB>(p, kc, d, c2p_variant<T, PS, PA, RB>(p, d), st);
             }
         if (two && d > 3 && (e = hipEventRecord(ev_ready(p, d - 1), st)) != hipSuccess) return e;
@@ -2380,7 +2394,8 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     // (a capture records the side stream's work too: it joins the capture
     // through the first event wait and leaves it through the last; the side
     // stream and its events exist by then, made by run_prepare)
-    const bool two = side_stream_enabled() && (p.capturing ? p.side != nullptr : ensure_side(p) == hipSuccess);
+    const bool two = !p.no_alloc && side_stream_enabled() &&
+                     (p.capturing ? p.side != nullptr : ensure_side(p) == hipSuccess);
     hipStream_t sd = two ? p.side : st;
     {
         StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
@@ -2431,7 +2446,8 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
     }
     // the near-field and cousin gradients on the side stream, as in apply_pass
     hipError_t e;
-    const bool two = side_stream_enabled() && (p.capturing ? p.side != nullptr : ensure_side(p) == hipSuccess);
+    const bool two = !p.no_alloc && side_stream_enabled() &&
+                     (p.capturing ? p.side != nullptr : ensure_side(p) == hipSuccess);
     hipStream_t sd = two ? p.side : st;
     if (two) {
         if ((e = hipEventRecord(p.sync_ev[0], st)) != hipSuccess) return e;
@@ -2471,6 +2487,90 @@ hipError_t apply_t(DevicePlan& p, const void* dens, int nrhs, void* out, bool ad
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// ------------------------------------------------ the no-allocation apply
+
+// Scratch of ifgf_apply_noalloc: the workspaces of an apply (densities and
+// output in Morton order, two cone-value buffers, cousin-pair values) carved
+// from one static device array.  Each GPU the library runs on holds its own
+// copy until the process ends; every no-allocation call on a GPU shares it.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Address of this GPU's scratch array, taken once per device with that
+// device current (host code never passes the array's name to a kernel: it is
+// a host-side stand-in, not a device address).
+static hipError_t scratch_address(int device, void** ptr)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void* q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = q;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// Bytes of the no-allocation workspaces (256-byte aligned parts): densities
+// and output [n][rb], two cone-value buffers [slots][P][rb], pair values.
+static size_t noalloc_parts(const DevicePlan& p, int nrhs, size_t* b_dens, size_t* b_cone, size_t* b_pval)
+{
+    const HostPlan& hp = p.hp;
+    const size_t rb = (size_t)rb_for(std::min(kMaxRhsPass, nrhs));
+    const size_t ce = p.precision == IFGF_MIXED ? 8 : 16;
+    size_t maxs = 0;
+    for (int d = 3; d <= hp.D; ++d) maxs = std::max(maxs, (size_t)hp.L[d].nslots);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    *b_dens = up((size_t)hp.n * rb * ce);
+    *b_cone = up(maxs * hp.P * rb * ce);
+    *b_pval = up((size_t)p.max_pairs * rb * ce);
+    return 2 * *b_dens + 2 * *b_cone + *b_pval;
+}
+
+template <typename T, int PS, int PA>
+hipError_t apply_noalloc_t(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t st,
+                           void* base)
+{
+    const HostPlan& hp = p.hp;
+    size_t b_dens, b_cone, b_pval;
+    if (noalloc_parts(p, nrhs, &b_dens, &b_cone, &b_pval) > kScratchBytes) return hipErrorOutOfMemory;
+    // the plan's own workspaces are set aside (untouched) for the call
+    void* s_dens = p.dens_m;
+    void* s_out = p.out_m;
+    void* s_pval = p.pval;
+    void* s_F[IFGF_MAX_LEVELS + 1];
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) s_F[d] = p.F[d];
+    const bool s_prof = p.profiling;
+    unsigned char* q = (unsigned char*)base;
+    p.dens_m = q;
+    p.out_m = q + b_dens;
+    void* cone[2] = {q + 2 * b_dens, q + 2 * b_dens + b_cone};
+    p.pval = p.max_pairs > 0 ? (void*)(q + 2 * b_dens + 2 * b_cone) : nullptr;
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) p.F[d] = d >= 3 && d <= hp.D ? cone[d & 1] : nullptr;
+    p.no_alloc = true;
+    p.profiling = false;   // stage timers would create events
+    hipError_t e = hipSuccess;
+    for (int r0 = 0; r0 < nrhs && e == hipSuccess; r0 += kMaxRhsPass) {
+        const int rbp = rb_for(std::min(kMaxRhsPass, nrhs - r0));
+        if (rbp == 1) e = apply_pass<T, PS, PA, 1>(p, dens, nrhs, r0, out, adj, st);
+        else if (rbp == 4) e = apply_pass<T, PS, PA, 4>(p, dens, nrhs, r0, out, adj, st);
+        else e = apply_pass<T, PS, PA, 16>(p, dens, nrhs, r0, out, adj, st);
+    }
+    p.no_alloc = false;
+    p.profiling = s_prof;
+    p.dens_m = s_dens;
+    p.out_m = s_out;
+    p.pval = s_pval;
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) p.F[d] = s_F[d];
+    return e;
 }
 
 template <typename T, int PS, int PA>
@@ -2666,6 +2766,38 @@ hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, bool 
         return hipErrorInvalidValue;
     if (e == hipSuccess) note_apply(p, dens, nrhs, adj);
     return e;
+}
+
+hipError_t scratch_init(int device) {
+    void* q = nullptr;
+    return scratch_address(device, &q);
+}
+
+size_t scratch_bytes() { return kScratchBytes; }
+
+size_t noalloc_bytes(const DevicePlan& p, int nrhs)
+{
+    size_t a, b, c;
+    return noalloc_parts(p, nrhs, &a, &b, &c);
+}
+
+hipError_t run_apply_noalloc(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t st)
+{
+    void* base = nullptr;
+    hipError_t e = scratch_address(p.device, &base);
+    if (e != hipSuccess) return e;
+    const int ps = p.hp.ps, pa = p.hp.pang;
+    const bool mixed = p.precision == IFGF_MIXED;
+    if (ps == 3 && pa == 5)
+        return mixed ? apply_noalloc_t<float, 3, 5>(p, dens, nrhs, out, adj, st, base)
+                     : apply_noalloc_t<double, 3, 5>(p, dens, nrhs, out, adj, st, base);
+    if (ps == 4 && pa == 6)
+        return mixed ? apply_noalloc_t<float, 4, 6>(p, dens, nrhs, out, adj, st, base)
+                     : apply_noalloc_t<double, 4, 6>(p, dens, nrhs, out, adj, st, base);
+    if (ps == 2 && pa == 3)
+        return mixed ? apply_noalloc_t<float, 2, 3>(p, dens, nrhs, out, adj, st, base)
+                     : apply_noalloc_t<double, 2, 3>(p, dens, nrhs, out, adj, st, base);
+    return hipErrorInvalidValue;
 }
 
 hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs, double* grad, bool reuse,

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -14,6 +15,26 @@
 
 namespace ifgf {
 namespace {
+
+// IFGF_PLAN_TIMES=1: seconds of each phase of the construction on stderr
+// (per building thread).
+struct PhaseClock {
+    bool on = false;
+    std::chrono::steady_clock::time_point t;
+    void start()
+    {
+        const char* e = std::getenv("IFGF_PLAN_TIMES");
+        on = e && std::atoi(e) != 0;
+        t = std::chrono::steady_clock::now();
+    }
+    void lap(const char* what)
+    {
+        auto n = std::chrono::steady_clock::now();
+        if (on) std::fprintf(stderr, "plan: %-36s %8.3f s\n", what, std::chrono::duration<double>(n - t).count());
+        t = n;
+    }
+};
+thread_local PhaseClock g_clock;
 
 int host_threads()
 {
@@ -46,6 +67,27 @@ void parallel_for(int64_t n, F&& f, int64_t grain = 1)
     for (int t = 1; t < nt; ++t) th.emplace_back(work);
     work();
     for (auto& t : th) t.join();
+}
+
+// Sorts v ascending: chunks sorted on the thread pool, then merged pairwise
+// in rounds (each round's merges in parallel).
+void parallel_sort(std::vector<uint64_t>& v)
+{
+    const int64_t n = (int64_t)v.size();
+    int nc = 1;
+    while (nc < host_threads()) nc *= 2;
+    if (n < (int64_t)1 << 16 || nc == 1) {
+        std::sort(v.begin(), v.end());
+        return;
+    }
+    std::vector<int64_t> cut(nc + 1);
+    for (int c = 0; c <= nc; ++c) cut[c] = n * c / nc;
+    parallel_for(nc, [&](int64_t c) { std::sort(v.begin() + cut[c], v.begin() + cut[c + 1]); });
+    for (int w = 1; w < nc; w *= 2)
+        parallel_for(nc / (2 * w), [&](int64_t i) {
+            const int64_t a = cut[2 * w * i], m = cut[2 * w * i + w], b = cut[2 * w * (i + 1)];
+            std::inplace_merge(v.begin() + a, v.begin() + m, v.begin() + b);
+        });
 }
 
 uint64_t interleave3(uint64_t x, uint64_t y, uint64_t z, int bits)
@@ -100,16 +142,23 @@ int32_t host_lookup(const HostLevel& L, int64_t b, int cell, int is)
     return L.cell_base[c] + cnt;
 }
 
-// Cousin-target pair table of level d (see HostLevel::use_pairs).
-void build_pairs(HostPlan& hp, int d)
+// First pair of every target box: entry pair_base[T] + c n_T + t is
+// (cousin c, target t) of box T.
+void pair_offsets(HostLevel& L)
 {
-    HostLevel& L = hp.L[d];
     L.pair_base.assign(L.nbox + 1, 0);
     for (int64_t T = 0; T < L.nbox; ++T) {
         int64_t nT = L.box_start[T + 1] - L.box_start[T];
         int64_t cT = L.cou_start[T + 1] - L.cou_start[T];
         L.pair_base[T + 1] = L.pair_base[T] + nT * cT;
     }
+}
+
+// Cousin-target pair table of level d (see HostLevel::use_pairs).
+void build_pairs(HostPlan& hp, int d)
+{
+    HostLevel& L = hp.L[d];
+    pair_offsets(L);
     const int64_t np = L.pair_base[L.nbox];
     L.pr_slot.assign(np, -1);
     L.pr_t.assign((size_t)3 * np, 0.0);
@@ -221,9 +270,10 @@ void build_frames(HostPlan& hp, int d)
             if (L.child_of[(size_t)j * 8 + o] >= 0) keys.push_back((uint64_t)Lp.slot_cone[sl] * 8 + o);
     }
     L.npairs = (int64_t)keys.size();
-    std::sort(keys.begin(), keys.end());
+    parallel_sort(keys);
     keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
     L.nframes = (int64_t)keys.size();
+    g_clock.lap("    frame keys");
     // tabulate when frames are shared at least 4x, or when the table is small
     // enough (it replaces FP64 geometry in the kernels, also at levels where
     // every frame is used once)
@@ -244,6 +294,7 @@ void build_frames(HostPlan& hp, int d)
                 L.pframe[(size_t)sl * 8 + o] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), key) - keys.begin());
             }
     }, 1024);
+    g_clock.lap("    frame of each slot");
     L.fr_key.resize((size_t)L.nframes * P);
     L.fr_t.resize((size_t)L.nframes * P * 3);
     L.fr_ratio.resize((size_t)L.nframes * P * 2);
@@ -281,6 +332,7 @@ void build_frames(HostPlan& hp, int d)
                 }
         }
     }, 64);
+    g_clock.lap("    frame geometry");
     // groups: distinct child cones per frame, in order of first appearance
     L.fr_ngrp.assign(L.nframes, 0);
     L.fr_gkey.assign((size_t)L.nframes * kMaxFrameGroups, 0);
@@ -330,6 +382,7 @@ void build_frames(HostPlan& hp, int d)
     // of its 8 children).  Large blocks give long runs, hence full tiles of
     // like masks; small blocks keep the child cones a block reads together
     // in cache.
+    g_clock.lap("    frame groups");
     const int64_t blk = tile_box_block();
     const int64_t nblk = (Lp.nbox + blk - 1) / blk;
     const int mode = tile_sort();
@@ -510,10 +563,12 @@ void build_tile_entries(HostPlan& hp, int d)
 
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
                             int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
-                            double pair_budget, HostPlan& hp,
-                            ifgf_status& code)
+                            double pair_budget, HostPlan& hp, ifgf_status& code, ConeMarker* marker,
+                            bool pairs_device)
 {
     auto t0 = std::chrono::steady_clock::now();
+    g_clock.start();
+    auto phase = [&](const char* what) { g_clock.lap(what); };
     code = IFGF_E_INVALID_ARG;
     if (!points) return "points is NULL";
     if (n < 2) return "need at least two points";
@@ -577,6 +632,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
     const double HD = std::ldexp(H1, -(D - 1));
     const int64_t nbD = (int64_t)1 << (D - 1);
 
+    phase("root box and levels");
     // Leaf multi-index and Morton code of every point; sort by code (ties by
     // coordinates, so equal points become neighbours in the order).
     std::vector<int64_t> kD(3 * n);
@@ -611,6 +667,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         mcode[i] = mort[order[i]];
     }
 
+    phase("Morton sort");
     // Relevant boxes of every level: unique Morton prefixes.
     hp.L.assign(D + 1, HostLevel());
     for (int d = 1; d <= D; ++d) {
@@ -641,6 +698,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         }
     }
 
+    phase("relevant boxes");
     // Parents and children.
     for (int d = 1; d <= D; ++d) {
         HostLevel& L = hp.L[d];
@@ -667,6 +725,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         }
     }
 
+    phase("parents and children");
     // Neighbours (|a - k|_inf <= 1, self included) on every level.
     for (int d = 1; d <= D; ++d) {
         HostLevel& L = hp.L[d];
@@ -694,6 +753,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
             std::copy(&tmp[27 * b], &tmp[27 * b] + cnt[b], &L.nbr[L.nbr_start[b]]);
     }
 
+    phase("neighbours");
     // Cousins: relevant children of the parent's neighbours that are not
     // neighbours themselves (eq. defcousinboxes).
     for (int d = 1; d <= D; ++d) {
@@ -722,6 +782,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         for (int64_t b = 0; b < L.nbox; ++b) std::copy(lists[b].begin(), lists[b].end(), &L.cou[L.cou_start[b]]);
     }
 
+    phase("cousins");
     // Cone intervals: leaf counts given; going up, a_d = 2 iff 2 kappa H_d > 1.
     hp.L[D].ns = leaf_ns;
     hp.L[D].nc = leaf_nc;
@@ -764,6 +825,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                     }
     }
 
+    phase("cone intervals and nodes");
     // Relevant cone segments, sweeping d = 3..D (eq. defallrelevantconesegments):
     // (i) the cone of every cousin point, (ii) for d >= 4 the cone of every
     // interpolation point of the parent's relevant cones.
@@ -798,7 +860,16 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                     }
         };
         const HostLevel* Lp = &hp.L[d - 1];
-        if (d >= 4) build_frames(hp, d);
+        if (d >= 4) {
+            build_frames(hp, d);
+            phase("  frames (level)");
+        }
+        if (marker) {
+            std::string err = marker->mark_level(hp, d, dilate, n_dilated, code);
+            if (!err.empty()) return err;
+            phase("  relevant cones on the GPU (level)");
+            continue;
+        }
         parallel_for(L.nbox, [&](int64_t b) {
             const double* ctr = &L.box_ctr[3 * b];
             for (int32_t ci = L.cou_start[b]; ci < L.cou_start[b + 1]; ++ci) {
@@ -896,6 +967,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                 }
             }
         }, 1);
+        phase(d >= 4 ? "  relevant cones (level)" : "  relevant cones (level 3)");
     }
     for (int d = 1; d < 3 && d <= D; ++d) {
         HostLevel& L = hp.L[d];
@@ -903,7 +975,9 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
     }
     for (int d = 4; d <= D; ++d)
         if (hp.L[d].use_frames && hp.L[d].frame_groups_ok && hp.L[d].ntiles > 0) build_tile_entries(hp, d);
+    phase("box tile entries");
 
+    phase("relevant cones, frames, tiles");
     // Cousin-target pair tables, coarse levels first, while the budget lasts.
     {
         const double per = tab_elem_bytes;
@@ -918,11 +992,19 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
             const bool both = ord_elem_bytes > 0.0 && used + npairs * (per + ord_elem_bytes) <= pair_budget;
             if (!both && used + npairs * per > pair_budget) break;
             used += npairs * (both ? per + ord_elem_bytes : per);
+            if (pairs_device) {
+                pair_offsets(L);
+                L.use_pairs = true;
+                L.pairs_device = true;
+                L.pairs_ordered = both;
+                continue;
+            }
             build_pairs(hp, d);
             if (both) build_pair_order(L);
         }
     }
 
+    phase("cousin-target pair tables");
     // Statistics.
     ifgf_stats& st = hp.stats;
     std::memset(&st, 0, sizeof(st));
@@ -973,6 +1055,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         st.n_near_pairs = nearp - n;
     }
     st.n_dilated = n_dilated;
+    phase("statistics");
     st.t_plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     code = IFGF_OK;
     return std::string();

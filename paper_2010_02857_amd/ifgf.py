@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
                                                ctypes.POINTER(P)]
         L.ifgf_apply.argtypes = [P, P, I32, P, P]
         L.ifgf_apply_adjoint.argtypes = [P, P, I32, P, P]
+        L.ifgf_apply_noalloc.argtypes = [P, P, I32, P, P]
         L.ifgf_grad_targets.argtypes = [P, P, P, I32, P, P]
         L.ifgf_grad_targets_stored.argtypes = [P, P, P, I32, P, P]
         L.ifgf_plan_stats.argtypes = [P, ctypes.POINTER(Stats)]
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
         L.ifgf_plan_destroy.argtypes = [P]
         L.ifgf_plan_profile.argtypes = [P, I32]
         L.ifgf_plan_stage_times.argtypes = [P, P, P]
+        L.ifgf_plan_level_times.argtypes = [P, I32, P, P]
         L.ifgf_plan_autotune.argtypes = [P, I32, P]
         L.ifgf_plan_kernel_choice.argtypes = [P, I32, P]
         L.ifgf_plan_set_kernel_choice.argtypes = [P, I32, P]
@@ -109,7 +111,7 @@ def lib() -> ctypes.CDLL:
         L.ifgf_last_error.argtypes = []
         L.ifgf_last_error.restype = ctypes.c_char_p
         for f in (L.ifgf_plan_create, L.ifgf_plan_create_targets, L.ifgf_apply, L.ifgf_apply_adjoint, L.ifgf_grad_targets,
-                  L.ifgf_grad_targets_stored,
+                  L.ifgf_grad_targets_stored, L.ifgf_apply_noalloc, L.ifgf_plan_level_times,
                   L.ifgf_plan_stats, L.ifgf_plan_check, L.ifgf_plan_destroy, L.ifgf_plan_profile,
                   L.ifgf_plan_stage_times, L.ifgf_plan_autotune, L.ifgf_plan_kernel_choice,
                   L.ifgf_plan_set_kernel_choice, L.ifgf_plan_kernel_candidates):
@@ -236,6 +238,15 @@ class Plan:
                                            cnt.ctypes.data_as(ctypes.c_void_p)))
         return {s: (float(ms[i]), int(cnt[i])) for i, s in enumerate(self.STAGES)}
 
+    def level_times(self, stage: str) -> dict:
+        """{level d: (milliseconds, launches)} of one stage since
+        profile(True) (levels with launches only)."""
+        ms = np.zeros(MAX_LEVELS + 1, np.float64)
+        cnt = np.zeros(MAX_LEVELS + 1, np.int64)
+        _check(lib().ifgf_plan_level_times(self._h, self.STAGES.index(stage), ms.ctypes.data_as(ctypes.c_void_p),
+                                           cnt.ctypes.data_as(ctypes.c_void_p)))
+        return {d: (float(ms[d]), int(cnt[d])) for d in range(MAX_LEVELS + 1) if cnt[d]}
+
     C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes", "quads", "lds_tiled")
 
     def autotune(self, nrhs: int = 1):
@@ -318,6 +329,18 @@ class Plan:
 
     def adjoint(self, v):
         return self.apply(v, adjoint=True)
+
+    def apply_noalloc(self, a, out):
+        """IFGF(a) into the preallocated contiguous `out` with no device
+        allocation by the library (ifgf_apply_noalloc: workspaces in its
+        static per-GPU scratch array)."""
+        a2, _ = self._prep(a, self.n)
+        if out.dtype != a2.dtype or out.device != a2.device or out.numel() != a2.shape[0] * self.m \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of the output's shape and dtype")
+        _check(lib().ifgf_apply_noalloc(self._h, ctypes.c_void_p(a2.data_ptr()), a2.shape[0],
+                                        ctypes.c_void_p(out.data_ptr()), self._stream(a2)))
+        return out
 
     def grad_targets(self, a, g, stored: bool = False):
         """sum_r Re(conj(g_r) dI_r/dx) for every target, (m, 3) float64.

@@ -631,3 +631,55 @@ def test_cfg2_matches_oracle(torch, w2, prec):
     e, ei = rel(out, ref), rel_inf(out, ref)
     print(f"cfg2 {prec} vs oracle: l2 {e:.3e} inf {ei:.3e}", flush=True)
     assert max(e, ei) < (FP64_TOL if prec == "fp64" else MIXED_TOL)
+
+
+# ------------------------------------------------ plan construction on the GPU
+
+@pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46", "lattice"])
+def test_gpu_plan_counts_match_oracle(torch, case):
+    """The relevant cones marked and numbered on the GPU (rules (i) and (ii)
+    of Sec. 3.3.2) give per-level counts equal to the oracle's, as the host
+    builder does."""
+    kw = {}
+    if case == "cfg1":
+        w = inputs.WORKLOADS[1]
+        p, k = w.points(), w.kappa
+    elif case == "cloud":
+        p, k, kw = inputs.random_box_points(3000, 5), 25.0, {"levels": 5}
+    elif case == "laplace":
+        p, k = inputs.cube_sphere(20), 0.0
+    elif case == "lattice":
+        p, k, kw = inputs.lattice(17), 8.0, {"levels": 4}
+    elif case == "leaf23":
+        p, k, kw = inputs.cube_sphere(20, 0.25), 15.0, {"leaf": (2, 3)}
+    else:
+        p, k, kw = inputs.cube_sphere(20), 10.0, {"degrees": (4, 6)}
+    st = make_plan(p, k, "fp64", dilate=False, **kw).stats()
+    so = oracle.ifgf(p, inputs.densities(1, 1, p.shape[0]), k, **kw)["stats"]
+    assert st["D"] == so["D"]
+    for key in ("n_boxes", "n_cones", "n_cousin_evals", "n_parent_evals"):
+        assert st[key] == so[key], key
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("mixed", 1), ("mixed", 4)])
+def test_gpu_plan_equals_host_plan(torch, monkeypatch, prec, nrhs):
+    """The plan built on the GPU (relevant cones, slot tables, cousin-pair
+    tables in target and cone order) and the one built on the host
+    (IFGF_HOST_PLAN=1) have the same counts and give bitwise equal results,
+    forward and adjoint, on a sphere and on a ragged cloud."""
+    for pts, k in ((inputs.cube_sphere(24), 6.0 * math.pi), (inputs.random_box_points(5000, 8), 12.0)):
+        a = dev(torch, inputs.densities(42, nrhs, pts.shape[0]), prec)
+        res = {}
+        for flag in ("0", "1"):
+            monkeypatch.setenv("IFGF_HOST_PLAN", flag)
+            plan = make_plan(pts, k, prec, max_nrhs=16)
+            st = plan.stats()
+            res[flag] = (st, plan.apply(a).cpu().numpy(), plan.adjoint(a).cpu().numpy())
+            assert plan.misses() == 0
+            del plan
+        (s0, o0, j0), (s1, o1, j1) = res["0"], res["1"]
+        for key in ("n_cones", "n_dilated", "pairs_tabulated", "n_frames"):
+            assert s0[key] == s1[key], key
+        assert sum(s0["pairs_tabulated"]) > 0
+        assert np.array_equal(o0, o1) and np.array_equal(j0, j1)
+    monkeypatch.delenv("IFGF_HOST_PLAN")
