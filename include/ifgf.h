@@ -253,17 +253,22 @@ typedef enum {
     IFGF_C2P_GEOMETRY = 0,      /* per point, child-frame geometry in FP64      */
     IFGF_C2P_FRAMES = 1,        /* per point, tabulated frames                  */
     IFGF_C2P_LDS = 2,           /* frames, child cones staged in LDS            */
-    IFGF_C2P_MFMA = 3,          /* batched RHS on matrix cores, per slot        */
+    IFGF_C2P_MFMA = 3,          /* batched RHS on matrix cores, per slot (FP32
+                                   or FP64, 4 or 16 RHS)                      */
     IFGF_C2P_MFMA_GEOMETRY = 4, /* the same without frame tables                */
     IFGF_C2P_BOXES = 5,         /* matrix cores, boxes of one parent cone as
                                    matrix columns (FP32, 1 or 4 RHS per pass) */
     IFGF_C2P_QUADS = 6,         /* vector units, 1 RHS: each child cone value
                                    read from LDS once for up to 4 points (2 in
                                    FP64) of the same child cone               */
-    IFGF_C2P_LDS_TILED = 7      /* IFGF_C2P_LDS visiting the parent slots in
+    IFGF_C2P_LDS_TILED = 7,     /* IFGF_C2P_LDS visiting the parent slots in
                                    box-tile order (blocks of boxes, one parent
                                    cone after the other), which shares frames
                                    in cache                                   */
+    IFGF_C2P_BOX_ACC = 8        /* matrix cores (FP32 or FP64), boxes of one
+                                   parent cone as matrix columns, parent values
+                                   accumulated in LDS, weights formed in
+                                   registers                                  */
 } ifgf_c2p_variant;
 
 /* Times every applicable child-to-parent variant at every level for nrhs

@@ -44,6 +44,8 @@ class _Stats(ctypes.Structure):
         ("n_parent_evals", ctypes.c_int64 * (MAX_LEVELS + 1)),
         ("n_far_pairs", ctypes.c_int64 * (MAX_LEVELS + 1)),
         ("n_near_pairs", ctypes.c_int64),
+        ("t_pre", ctypes.c_double),
+        ("t_acc", ctypes.c_double),
     ]
 
 
@@ -156,6 +158,7 @@ def ifgf(pts, dens, kappa, levels=0, degrees=(3, 5), leaf=(1, 2), targets=None, 
     D = st.D
     stats = {
         "D": D, "H1": st.H1, "x1": list(st.x1), "n_near_pairs": st.n_near_pairs,
+        "t_pre": st.t_pre, "t_acc": st.t_acc,
     }
     for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes",
                 "n_cousin_evals", "n_parent_evals", "n_far_pairs"):

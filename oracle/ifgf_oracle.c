@@ -41,6 +41,7 @@
 
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -495,6 +496,7 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
     }
     const cplx* a = (const cplx*)dens;
     const int P = ps * pang * pang;
+    const double t_start = omp_get_wtime();   /* T_pre: the hierarchy below */
 
     /* Root box B_1^1 containing Gamma_N (eq. deffirstbox; reading R6). */
     double lo[3], hi[3];
@@ -759,6 +761,7 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
     }
 
     /* ------------------------------------------------ operator evaluation */
+    const double t_eval = omp_get_wtime();   /* T_acc: from here on */
     /* Output and gradient accumulate as [target][rhs] (interleaved complex);
      * they are transposed to [rhs][target] at the end. */
     double* acc = (double*)calloc((size_t)2 * m * nrhs + 2, sizeof(double));
@@ -985,9 +988,12 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
         }
     if (sig)
         for (int64_t t = 0; t < m; ++t) sig[t] = sg[t];
+    const double t_end = omp_get_wtime();
 
     if (stats) {
         memset(stats, 0, sizeof(*stats));
+        stats->t_pre = t_eval - t_start;
+        stats->t_acc = t_end - t_eval;
         stats->D = D;
         stats->H1 = H1;
         for (int c = 0; c < 3; ++c) stats->x1[c] = x1[c];

@@ -43,6 +43,10 @@ typedef struct {
     int64_t n_far_pairs[ORACLE_MAX_LEVELS + 1];     /* (target, source) pairs
                                                        covered at level d    */
     int64_t n_near_pairs;                     /* pairs summed directly       */
+    double t_pre;                             /* seconds: hierarchy and
+                                                 relevant cones (T_pre)      */
+    double t_acc;                             /* seconds: operator
+                                                 evaluation (T_acc)          */
 } oracle_stats;
 
 /* Direct O(N^2) sum of Sec. 2, eq. (field1) with the Helmholtz kernel of

@@ -89,7 +89,8 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
     p.allocs.push_back(m);
     p.miss = (unsigned long long*)m;
     if ((e = hipMemset(m, 0, sizeof(unsigned long long))) != hipSuccess) return e;
-    const size_t zb = (size_t)hp.P * kMaxRhsPass * 2 * sizeof(float);
+    // zeros for one cone of kMaxRhsPass right-hand sides in the widest type
+    const size_t zb = (size_t)hp.P * kMaxRhsPass * 2 * sizeof(double);
     if ((e = hipMalloc(&m, zb)) != hipSuccess) return e;
     p.allocs.push_back(m);
     p.zero_cone = m;

@@ -24,7 +24,7 @@ constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone p
 constexpr int kPairQuad = 4;        // cone-ordered cousin pairs share a cone in runs of this length
 // child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)
 enum { kC2PGeometry = 0, kC2PFrames = 1, kC2PLds = 2, kC2PMfma = 3, kC2PMfmaGeometry = 4, kC2PBoxes = 5,
-       kC2PQuads = 6, kC2PLdsTiled = 7, kC2PVariants = 8 };
+       kC2PQuads = 6, kC2PLdsTiled = 7, kC2PBoxAcc = 8, kC2PVariants = 9 };
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).

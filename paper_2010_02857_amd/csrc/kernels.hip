@@ -841,14 +841,21 @@ typedef double md4 __attribute__((ext_vector_type(4)));
 
 // 16 x 16 x 4 matrix-core product in the operand type: FP32
 // (v_mfma_f32_16x16x4_f32) or FP64 (v_mfma_f64_16x16x4_f64).  Both take the
-// same lane layout: A[lane % 16][lane / 16], B[lane / 16][lane % 16], and
-// D[4 (lane / 16) + i][lane % 16] in element i of the result.
+// operands as A[lane % 16][lane / 16] and B[lane / 16][lane % 16]; element i
+// of the result holds D[row][lane % 16] with row = 4 (lane / 16) + i in FP32
+// but row = lane / 16 + 4 i in FP64 (checked on the device: mfma_row).
 template <typename T> struct MfmaVec;
 template <> struct MfmaVec<float> { typedef mf4 type; };
 template <> struct MfmaVec<double> { typedef md4 type; };
 template <typename T>
 using mvec = typename MfmaVec<T>::type;
 __device__ inline mf4 mfma16(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+// Row of element i of a 16 x 16 x 4 result in lane quarter q.
+template <typename T>
+__device__ inline int mfma_row(int q, int i)
+{
+    return sizeof(T) == 8 ? q + 4 * i : 4 * q + i;
+}
 __device__ inline md4 mfma16(double a, double b, md4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -934,7 +941,7 @@ __device__ inline void mfma_load_b(const T* __restrict__ Fcs, int q, int col,
     }
 }
 
-// Epilogue of a tile: rows 4q + i, column col of each tile; multiply by the
+// Epilogue of a tile: rows mfma_row(q, i), column col of each tile; multiply by the
 // row's ratio (complex: columns 2r, 2r+1 are re, im of right-hand side r) and
 // accumulate into the wavefront's LDS values of the parent slot.
 template <int NC, int NT, typename T>
@@ -943,7 +950,7 @@ __device__ inline void mfma_epilogue(const mvec<T>* c, int q, int col, int t0, i
 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int ri = t0 + 4 * q + i;
+        const int ri = t0 + mfma_row<T>(q, i);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const T v = c[t][i];
@@ -1708,6 +1715,204 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
     }
 }
 
+// Box-batched child-to-parent with the parent values accumulated in LDS
+// (FP32 or FP64 matrix instructions).  Same tiles, entries and matrix
+// shapes as k_child_to_parent_boxes -- one wavefront per tile of boxes that
+// share a parent cone, 16 (box, right-hand side) columns per pass, rows =
+// the points of one child cone ("group") of the octant's frame, K = the
+// child cone's nodes -- but the wavefront keeps only the octant's local
+// coordinates and ratios in LDS and forms each row's Chebyshev weights in
+// registers, and the epilogue multiplies every raw result by its point's
+// ratio and adds it to the pass's values in LDS (each (point, column)
+// belongs to one lane of one tile in an octant, so there are no races).
+// Without the raw-result and weight staging, FP64 fits in registers and
+// LDS at two waves per SIMD, FP32 at three.
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3)))
+k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* __restrict__ Fc,
+                         cpx<T>* __restrict__ Fp, const cpx<T>* __restrict__ zero_cone)
+{
+    constexpr int P = PS * PA * PA;
+    constexpr int NT = 2;                      // tiles per pass: real and imaginary parts
+    static_assert(16 % RB == 0, "a pass holds whole boxes");
+    constexpr int BX = 16 / RB;                // boxes per pass (16 complex columns)
+    constexpr int AS = 33;                     // row stride of the accumulators (re 0..15, im 16..31)
+    constexpr int ME = kBoxMaxEnt;
+    constexpr int NAB = PS * PA;
+    constexpr int NREM = NAB * (PA - 4);
+    constexpr int NK = NAB + (NREM + 3) / 4;
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    static_assert(P <= 255 && ME >= kMaxFrameGroups, "entry and point indices");
+    __shared__ T acc[P * AS];                  // the pass's parent values by point
+    __shared__ T rt[3][P];                     // local coordinates of the octant's points
+    __shared__ T rg[2][P];                     // their ratios
+    __shared__ uint8_t sord[8 * P];            // points of the 8 frames in group order
+    __shared__ int sfr[8];                     // frame of each octant, -1
+    __shared__ int sgo[9];                     // first entry of each octant
+    __shared__ int bslot[kBoxTile];
+    __shared__ uint8_t smask[kBoxTile];        // children of each tile box (bit o)
+    __shared__ int einfo[ME];                  // g0 | cnt << 8 | o << 16
+    __shared__ int ecs[ME * BX];               // child slot of (entry, box of the pass), -1
+
+    const int lane = threadIdx.x;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    if (tile >= Lc.ntiles) return;
+    const T* frt = (const T*)Lc.fr_t;
+    const T* frr = (const T*)Lc.fr_ratio;
+    const T conj_sign = kc.adj ? (T)-1 : (T)1;
+    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+
+    int my_slot = -1;
+    if (lane < kBoxTile) {
+        my_slot = Lc.bt_slot[(size_t)tile * kBoxTile + lane];
+        bslot[lane] = my_slot;
+        smask[lane] = Lc.te_mask[(size_t)tile * kBoxTile + lane];
+    }
+    if (lane < 8) sfr[lane] = Lc.bt_frame[(size_t)tile * 8 + lane];
+    if (lane < 9) sgo[lane] = Lc.te_go[(size_t)tile * 9 + lane];
+    const int64_t ebase = Lc.te_start[tile];
+    const int nbt = __popcll(__ballot(my_slot >= 0));
+    wave_lds_fence();
+    for (int i = lane; i < 8 * P; i += 64) {
+        const int o = i / P, r = i - o * P;
+        const int f = sfr[o];
+        const uint8_t v = Lc.fr_order[(size_t)(f >= 0 ? f : 0) * P + r];
+        sord[i] = f >= 0 ? v : (uint8_t)0;
+    }
+    wave_lds_fence();
+
+    // B operands of an entry: column col is (box col / RB, right-hand side
+    // col % RB); tile 0 takes the real parts, tile 1 the imaginary parts.  A
+    // missing child reads the zero cone.
+    T bn[NT][NK];
+    auto fetch_b = [&](int ei) {
+        const int cs = ecs[ei * BX + col / RB];
+        const cpx<T>* src = cs >= 0 ? Fc + (size_t)cs * P * RB + (col % RB) : zero_cone + (col % RB);
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) {
+            const cpx<T> v = src[(size_t)(ab * PA + q) * RB];
+            bn[0][ab] = v.x;
+            bn[1][ab] = v.y;
+        }
+#pragma unroll
+        for (int jt = 0; jt < NK - NAB; ++jt) {
+            int m = 4 * jt + q;
+            m = m < NREM ? m : NREM - 1;
+            const int abm = m / (PA - 4), c4 = 4 + (m - abm * (PA - 4));
+            const cpx<T> v = src[(size_t)(abm * PA + c4) * RB];
+            bn[0][NAB + jt] = v.x;
+            bn[1][NAB + jt] = v.y;
+        }
+    };
+
+    for (int b0 = 0; b0 < nbt; b0 += BX) {
+        for (int i = lane; i < P * AS; i += 64) acc[i] = (T)0;
+        // octants in which a box of the pass has a child
+        int pm = 0;
+        if constexpr (BX == 16) {
+            pm = 255;
+        } else {
+            const int bl = lane >> 3, o = lane & 7;
+            const bool has = lane < BX * 8 && b0 + bl < kBoxTile && ((smask[b0 + bl] >> o) & 1);
+            const unsigned long long bal = __ballot(has);
+#pragma unroll
+            for (int k = 0; k < BX; ++k) pm |= (int)((bal >> (8 * k)) & 255ull);
+        }
+        auto live = [&](int o) { return sfr[o] >= 0 && ((pm >> o) & 1); };
+        int o0 = 0;
+        while (o0 < 8) {
+            // a chunk of whole octants with at most ME entries
+            int o1 = o0 + 1;
+            while (o1 < 8 && sgo[o1 + 1] - sgo[o0] <= ME) ++o1;
+            const int e0 = sgo[o0], ne = sgo[o1] - e0;
+            const int64_t eb = ebase + e0;
+            wave_lds_fence();
+            for (int i = lane; i < ne; i += 64) einfo[i] = Lc.te_info[eb + i];
+            for (int i = lane; i < ne * BX; i += 64) {
+                const int ei = i / BX, bl = i - ei * BX;
+                const int bi = b0 + bl;
+                int cs = bi < kBoxTile ? Lc.te_cs[(size_t)(eb + ei) * kBoxTile + bi] : -1;
+                if (cs == -2) {
+                    atomicAdd(kc.miss, (unsigned long long)((Lc.te_info[eb + ei] >> 8) & 255));
+                    cs = -1;
+                }
+                ecs[i] = cs;
+            }
+            wave_lds_fence();
+            for (int o = o0; o < o1; ++o) {
+                if (!live(o)) continue;
+                // the octant's frame: coordinates and ratio of every point
+                const int f = sfr[o];
+                for (int nu = lane; nu < P; nu += 64) {
+                    const size_t e = (size_t)f * P + nu;
+                    rt[0][nu] = frt[3 * e];
+                    rt[1][nu] = frt[3 * e + 1];
+                    rt[2][nu] = frt[3 * e + 2];
+                    rg[0][nu] = frr[2 * e];
+                    rg[1][nu] = conj_sign * frr[2 * e + 1];
+                }
+                const int e_lo = sgo[o] - e0, e_hi = sgo[o + 1] - e0;
+                if (e_lo < e_hi) fetch_b(e_lo);
+                wave_lds_fence();
+                const uint8_t* ord = &sord[o * P];
+                for (int ei = e_lo; ei < e_hi; ++ei) {
+                    const int info = einfo[ei];
+                    const int g0 = info & 255, cnt = (info >> 8) & 255;
+                    // the entry's operands, taken over from the prefetch, then
+                    // the next entry's loads (this entry's again after the last)
+                    T b[NT][NK];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int kk = 0; kk < NK; ++kk) {
+                            b[t][kk] = bn[t][kk];
+                            asm volatile("" : "+v"(b[t][kk]));
+                        }
+                    fetch_b(ei + 1 < e_hi ? ei + 1 : ei);
+                    for (int t0 = 0; t0 < cnt; t0 += 16) {
+                        const int rr = t0 + row;
+                        const int nu_r = ord[g0 + (rr < cnt ? rr : 0)];
+                        T Ls[PS], Lt[PA], Lpv[PA];
+                        lagrange<T, PS>((double)rt[0][nu_r], kc.cs, Ls);
+                        lagrange<T, PA>((double)rt[1][nu_r], kc.ca, Lt);
+                        lagrange<T, PA>((double)rt[2][nu_r], kc.ca, Lpv);
+                        if (rr >= cnt) {
+#pragma unroll
+                            for (int i = 0; i < PS; ++i) Ls[i] = (T)0;
+                        }
+                        mvec<T> c[NT];
+                        mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
+                        // the lane's rows: ratio times value into the pass's accumulators
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int ri = t0 + mfma_row<T>(q, i);
+                            if (ri < cnt) {
+                                const int nu = ord[g0 + ri];
+                                const T vr = c[0][i], vi = c[1][i];
+                                const T gr = rg[0][nu], gi = rg[1][nu];
+                                acc[nu * AS + col] += vr * gr - vi * gi;
+                                acc[nu * AS + 16 + col] += vr * gi + vi * gr;
+                            }
+                        }
+                    }
+                }
+                wave_lds_fence();
+            }
+            o0 = o1;
+        }
+        wave_lds_fence();
+        // write the pass's slots: column cc is (box cc / RB, right-hand side cc % RB)
+        for (int i = lane; i < P * 16; i += 64) {
+            const int nu = i >> 4, cc = i & 15;
+            const int bl = cc / RB, r = cc - bl * RB;
+            const int bi = b0 + bl;
+            const int s = bi < kBoxTile ? bslot[bi] : -1;
+            if (s >= 0) Fp[((size_t)s * P + nu) * RB + r] = cpx<T>{acc[nu * AS + cc], acc[nu * AS + 16 + cc]};
+        }
+        wave_lds_fence();
+    }
+}
+
 // Interpolation at cousin targets for batched right-hand sides on the matrix
 // cores (FP32), through the tabulated pairs.  One wavefront takes a target
 // box and up to 16 of its targets as the rows of 16 x 16 x 4 MFMA tiles;
@@ -2028,7 +2233,15 @@ __global__ void __launch_bounds__(kBlock) k_permute_grad(const double* __restric
 
 // ------------------------------------------------------------- host side
 
-inline unsigned grid_for(size_t items) { return (unsigned)((items + kBlock - 1) / kBlock); }
+// Blocks of kBlock threads for `items` threads.  A dispatch counts its
+// work-items in 32 bits, so a launch of 2^32 or more would be cut short:
+// such a request gives 0 blocks, and the launch fails (IFGF_E_HIP) instead of
+// silently covering part of the items.
+inline unsigned grid_for(size_t items)
+{
+    const size_t b = (items + kBlock - 1) / kBlock;
+    return b * kBlock >= ((size_t)1 << 32) ? 0u : (unsigned)b;
+}
 
 // Source and target windows of a plan: every point is both unless the plan
 // was created with distinct targets.
@@ -2139,6 +2352,9 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
     if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
         if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxes;
     }
+    if constexpr (PA >= 4 && P <= 128) {
+        if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAcc;
+    }
     if constexpr (RB == 1 && P <= 255) {
         if (groups) v[n++] = kC2PQuads;
     }
@@ -2158,9 +2374,9 @@ int c2p_default(const DevicePlan& p, int d)
             if (v[i] == x) return true;
         return false;
     };
-    if (has(kC2PBoxes) &&
-        (double)p.hp.L[d - 1].nslots >= box_fill_min(RB) * kBoxTile * (double)p.L[d].ntiles)
-        return kC2PBoxes;
+    const bool full = (double)p.hp.L[d - 1].nslots >= box_fill_min(RB) * kBoxTile * (double)p.L[d].ntiles;
+    if (has(kC2PBoxes) && full) return kC2PBoxes;
+    if (std::is_same<T, double>::value && has(kC2PBoxAcc) && full) return kC2PBoxAcc;
     if (has(kC2PMfma)) return kC2PMfma;
     if (has(kC2PMfmaGeometry)) return kC2PMfmaGeometry;
     if (has(kC2PLds)) return kC2PLds;
@@ -2192,6 +2408,13 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
     case kC2PBoxes:
         if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
             k_child_to_parent_boxes<PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+            return;
+        }
+        break;
+    case kC2PBoxAcc:
+        if constexpr (PA >= 4 && P <= 128) {
+            k_child_to_parent_boxacc<T, PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
                 kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
             return;
         }

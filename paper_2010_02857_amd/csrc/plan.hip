@@ -69,6 +69,29 @@ void parallel_for(int64_t n, F&& f, int64_t grain = 1)
     for (auto& t : th) t.join();
 }
 
+// Stable sort by `less`: chunks sorted on the thread pool, then merged
+// pairwise in rounds (each round's merges in parallel; merging keeps the
+// order of equal elements).
+template <class T, class Less>
+void parallel_stable_sort(std::vector<T>& v, Less less)
+{
+    const int64_t n = (int64_t)v.size();
+    int nc = 1;
+    while (nc < host_threads()) nc *= 2;
+    if (n < (int64_t)1 << 15 || nc == 1) {
+        std::stable_sort(v.begin(), v.end(), less);
+        return;
+    }
+    std::vector<int64_t> cut(nc + 1);
+    for (int c = 0; c <= nc; ++c) cut[c] = n * c / nc;
+    parallel_for(nc, [&](int64_t c) { std::stable_sort(v.begin() + cut[c], v.begin() + cut[c + 1], less); });
+    for (int w = 1; w < nc; w *= 2)
+        parallel_for(nc / (2 * w), [&](int64_t i) {
+            const int64_t a = cut[2 * w * i], m = cut[2 * w * i + w], b = cut[2 * w * (i + 1)];
+            std::inplace_merge(v.begin() + a, v.begin() + m, v.begin() + b, less);
+        });
+}
+
 // Sorts v ascending: chunks sorted on the thread pool, then merged pairwise
 // in rounds (each round's merges in parallel).
 void parallel_sort(std::vector<uint64_t>& v)
@@ -388,60 +411,62 @@ void build_frames(HostPlan& hp, int d)
     const int mode = tile_sort();
     std::vector<std::vector<int32_t>> btiles(nblk);   // kBoxTile entries per tile, -1 padded
     std::vector<int64_t> bt(nblk + 1, 0);
-    parallel_for(nblk, [&](int64_t b) {
+    auto mask = [&](int32_t sl) {
+        int m = 0;
+        for (int o = 0; o < 8; ++o) m |= (L.child_of[(size_t)Lp.slot_box[sl] * 8 + o] >= 0) << o;
+        return m;
+    };
+    // a run's tiles as kBoxTile entries each (-1 padded); cost = the octant
+    // passes they run
+    auto emit = [](std::vector<int32_t>& dst, const int32_t* sl, int n) {
+        for (int k = 0; k < kBoxTile; ++k) dst.push_back(k < n ? sl[k] : -1);
+    };
+    struct Open {
+        int m, n;
+        int32_t s[kBoxTile];
+    };
+    // blocks one after the other, each block's sort and runs on all threads
+    for (int64_t b = 0; b < nblk; ++b) {
         const int64_t j0 = b * blk, j1 = std::min<int64_t>(Lp.nbox, j0 + blk);
-        std::vector<int32_t> v;
-        for (int64_t sl = Lp.slot_start[j0]; sl < Lp.slot_start[j1]; ++sl) v.push_back((int32_t)sl);
-        auto mask = [&](int32_t sl) {
-            int m = 0;
-            for (int o = 0; o < 8; ++o) m |= (L.child_of[(size_t)Lp.slot_box[sl] * 8 + o] >= 0) << o;
-            return m;
-        };
-        std::vector<int> mk(v.size());
-        std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
+        std::vector<int32_t> v((size_t)(Lp.slot_start[j1] - Lp.slot_start[j0]));
+        std::iota(v.begin(), v.end(), Lp.slot_start[j0]);
+        parallel_stable_sort(v, [&](int32_t x, int32_t y) {
             if (Lp.slot_cone[x] != Lp.slot_cone[y]) return Lp.slot_cone[x] < Lp.slot_cone[y];
             return mode != 0 && mask(x) < mask(y);
         });
-        for (size_t k = 0; k < v.size(); ++k) mk[k] = mask(v[k]);
-        std::vector<int32_t>& out = btiles[b];
-        // a run's tiles as kBoxTile entries each (-1 padded); cost = the
-        // octant passes they run
-        auto emit = [&](std::vector<int32_t>& dst, const int32_t* sl, int n) {
-            for (int k = 0; k < kBoxTile; ++k) dst.push_back(k < n ? sl[k] : -1);
-        };
-        auto cost = [&](const std::vector<int32_t>& w) {
-            int64_t c = 0;
-            for (size_t t = 0; t < w.size(); t += kBoxTile) {
-                int m = 0;
-                for (int k = 0; k < kBoxTile; ++k)
-                    if (w[t + k] >= 0) m |= mask(w[t + k]);
-                c += __builtin_popcount(m);
-            }
-            return c;
-        };
-        struct Open {
-            int m, n;
-            int32_t s[kBoxTile];
-        };
-        std::vector<Open> open;
-        std::vector<size_t> rem;
-        std::vector<int32_t> cut, grp;
-        for (size_t i = 0; i < v.size();) {
-            size_t e = i;
-            while (e < v.size() && Lp.slot_cone[v[e]] == Lp.slot_cone[v[i]]) ++e;
+        std::vector<int> mk(v.size());
+        parallel_for((int64_t)v.size(), [&](int64_t k) { mk[k] = mask(v[k]); }, 4096);
+        // runs of one parent cone
+        std::vector<size_t> run{0};
+        for (size_t k = 1; k < v.size(); ++k)
+            if (Lp.slot_cone[v[k]] != Lp.slot_cone[v[k - 1]]) run.push_back(k);
+        run.push_back(v.size());
+        const int64_t nrun = (int64_t)run.size() - 1;
+        std::vector<std::vector<int32_t>> rout(nrun);
+        parallel_for(nrun, [&](int64_t r) {
+            const size_t i = run[r], e = run[r + 1];
+            auto cost = [&](const std::vector<int32_t>& w) {
+                int64_t c = 0;
+                for (size_t t = 0; t < w.size(); t += kBoxTile) {
+                    int m = 0;
+                    for (int k = 0; k < kBoxTile; ++k)
+                        if (w[t + k] >= 0) m |= mask(w[t + k]);
+                    c += __builtin_popcount(m);
+                }
+                return c;
+            };
             // the run cut in order (by child mask unless mode 0)
-            cut.clear();
+            std::vector<int32_t> cut;
             for (size_t k0 = i; k0 < e; k0 += kBoxTile) emit(cut, &v[k0], (int)std::min<size_t>(kBoxTile, e - k0));
             if (mode != 2 || e - i <= (size_t)kBoxTile) {
-                out.insert(out.end(), cut.begin(), cut.end());
-                i = e;
-                continue;
+                rout[r].swap(cut);
+                return;
             }
             // or: full tiles of one child mask, then the rest, largest masks
             // first, each to the open tile whose octants it widens least;
             // the run keeps whichever of the two runs fewer passes
-            grp.clear();
-            rem.clear();
+            std::vector<int32_t> grp;
+            std::vector<size_t> rem;
             for (size_t a = i; a < e;) {
                 size_t z = a;
                 while (z < e && mk[z] == mk[a]) ++z;
@@ -453,7 +478,7 @@ void build_frames(HostPlan& hp, int d)
             std::stable_sort(rem.begin(), rem.end(), [&](size_t x, size_t y) {
                 return __builtin_popcount(mk[x]) > __builtin_popcount(mk[y]);
             });
-            open.clear();
+            std::vector<Open> open;
             for (size_t x : rem) {
                 int best = -1, bg = 9;
                 for (int t = 0; t < (int)open.size(); ++t) {
@@ -472,12 +497,16 @@ void build_frames(HostPlan& hp, int d)
                 open[best].s[open[best].n++] = v[x];
             }
             for (const Open& t : open) emit(grp, t.s, t.n);
-            const std::vector<int32_t>& pick = cost(grp) < cost(cut) ? grp : cut;
-            out.insert(out.end(), pick.begin(), pick.end());
-            i = e;
-        }
+            if (cost(grp) < cost(cut)) rout[r].swap(grp);
+            else rout[r].swap(cut);
+        }, 64);
+        std::vector<int32_t>& out = btiles[b];
+        size_t tot = 0;
+        for (const auto& w : rout) tot += w.size();
+        out.reserve(tot);
+        for (const auto& w : rout) out.insert(out.end(), w.begin(), w.end());
         bt[b + 1] = (int64_t)(out.size() / kBoxTile);
-    }, 1);
+    }
     for (int64_t b = 0; b < nblk; ++b) bt[b + 1] += bt[b];
     L.ntiles = bt[nblk];
     L.bt_slot.assign((size_t)L.ntiles * kBoxTile, -1);

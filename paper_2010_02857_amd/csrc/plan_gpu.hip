@@ -30,7 +30,16 @@ namespace {
 
 constexpr int kPB = 256;   // threads per block of the builder kernels
 
-inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kPB - 1) / kPB); }
+// Blocks of a launch over n items: the builder kernels loop with a stride of
+// the whole grid, and the grid stays far below 2^32 work-items (a dispatch
+// counts its work-items in 32 bits; rule (ii) alone can pass 4e9 items).
+inline unsigned blocks_for(int64_t n)
+{
+    const int64_t b = (n + kPB - 1) / kPB;
+    return (unsigned)(b < ((int64_t)1 << 20) ? (b > 0 ? b : 1) : ((int64_t)1 << 20));
+}
+
+#define GRID_LOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kPB)
 
 struct Marks {
     unsigned long long* prim;  // [nbox][wpb] cones marked by rules (i) and (ii)
@@ -92,15 +101,15 @@ __global__ void __launch_bounds__(kPB) k_mark_cousin_points(Marks M, int nbox, i
                                                             const double* __restrict__ box_ctr,
                                                             const double* __restrict__ pts, int dilate)
 {
-    const int64_t ci = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (ci >= ncou) return;
-    const int b = owner(cou_start, nbox, ci);
-    const int c = cou[ci];
-    const double c0 = box_ctr[3 * b], c1 = box_ctr[3 * b + 1], c2 = box_ctr[3 * b + 2];
-    for (int j = box_start[c]; j < box_start[c + 1]; ++j) {
-        ConeLoc cl;
-        cone_locate(pts[3 * j] - c0, pts[3 * j + 1] - c1, pts[3 * j + 2] - c2, M.h, M.ds, M.dang, M.ns, M.nc, cl);
-        mark_cone(M, b, cl, dilate);
+    GRID_LOOP(ci, ncou) {
+        const int b = owner(cou_start, nbox, ci);
+        const int c = cou[ci];
+        const double c0 = box_ctr[3 * b], c1 = box_ctr[3 * b + 1], c2 = box_ctr[3 * b + 2];
+        for (int j = box_start[c]; j < box_start[c + 1]; ++j) {
+            ConeLoc cl;
+            cone_locate(pts[3 * j] - c0, pts[3 * j + 1] - c1, pts[3 * j + 2] - c2, M.h, M.ds, M.dang, M.ns, M.nc, cl);
+            mark_cone(M, b, cl, dilate);
+        }
     }
 }
 
@@ -124,30 +133,30 @@ struct ParentNodes {
 
 __global__ void __launch_bounds__(kPB) k_mark_parent_nodes(Marks M, ParentNodes N, int64_t total, int dilate)
 {
-    const int64_t gid = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (gid >= total) return;
-    const int64_t pr = gid / N.P;
-    const int nu = (int)(gid - pr * N.P);
-    const int b = owner(N.off, N.nbox, pr);
-    const int oct = N.box_oct[b];
-    const int sl = N.pslot_start[N.parent[b]] + (int)(pr - N.off[b]);
-    if (N.use_frames) {
-        const int f = N.pframe[(int64_t)sl * 8 + oct];
-        set_bit(M.prim + (int64_t)b * M.wpb, N.fr_key[(int64_t)f * N.P + nu]);
-        return;
+    GRID_LOOP(gid, total) {
+        const int64_t pr = gid / N.P;
+        const int nu = (int)(gid - pr * N.P);
+        const int b = owner(N.off, N.nbox, pr);
+        const int oct = N.box_oct[b];
+        const int sl = N.pslot_start[N.parent[b]] + (int)(pr - N.off[b]);
+        if (N.use_frames) {
+            const int f = N.pframe[(int64_t)sl * 8 + oct];
+            set_bit(M.prim + (int64_t)b * M.wpb, N.fr_key[(int64_t)f * N.P + nu]);
+            continue;
+        }
+        const int pc = N.pslot_cone[sl];
+        const int pcell = pc / N.pns, pis = pc - pcell * N.pns;
+        const int a = nu / (N.pang * N.pang), bc = nu - a * N.pang * N.pang;
+        const double rr = N.pnode_r[pis * N.ps + a];
+        const double* dir = &N.pnode_dir[((int64_t)pcell * N.pang * N.pang + bc) * 3];
+        double o[3];
+        for (int x = 0; x < 3; ++x) o[x] = ((oct >> x) & 1) ? 0.5 * N.H : -0.5 * N.H;
+        double v[3];
+        node_minus(rr, dir, o, v);
+        ConeLoc cl;
+        cone_locate(v[0], v[1], v[2], M.h, M.ds, M.dang, M.ns, M.nc, cl);
+        mark_cone(M, b, cl, dilate);
     }
-    const int pc = N.pslot_cone[sl];
-    const int pcell = pc / N.pns, pis = pc - pcell * N.pns;
-    const int a = nu / (N.pang * N.pang), bc = nu - a * N.pang * N.pang;
-    const double rr = N.pnode_r[pis * N.ps + a];
-    const double* dir = &N.pnode_dir[((int64_t)pcell * N.pang * N.pang + bc) * 3];
-    double o[3];
-    for (int x = 0; x < 3; ++x) o[x] = ((oct >> x) & 1) ? 0.5 * N.H : -0.5 * N.H;
-    double v[3];
-    node_minus(rr, dir, o, v);
-    ConeLoc cl;
-    cone_locate(v[0], v[1], v[2], M.h, M.ds, M.dang, M.ns, M.nc, cl);
-    mark_cone(M, b, cl, dilate);
 }
 
 // Folds the dilation marks into the primary ones (counting the cones they
@@ -157,18 +166,18 @@ __global__ void __launch_bounds__(kPB) k_merge_count(unsigned long long* __restr
                                                      int dilate, int64_t* __restrict__ cnt,
                                                      unsigned long long* __restrict__ ndil)
 {
-    const int64_t w = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (w >= nwords) return;
-    unsigned long long m = prim[w];
-    if (dilate) {
-        const unsigned long long extra = dil[w] & ~m;
-        if (extra) {
-            atomicAdd(ndil, (unsigned long long)__popcll(extra));
-            m |= extra;
-            prim[w] = m;
+    GRID_LOOP(w, nwords) {
+        unsigned long long m = prim[w];
+        if (dilate) {
+            const unsigned long long extra = dil[w] & ~m;
+            if (extra) {
+                atomicAdd(ndil, (unsigned long long)__popcll(extra));
+                m |= extra;
+                prim[w] = m;
+            }
         }
+        cnt[w] = __popcll(m);
     }
-    cnt[w] = __popcll(m);
 }
 
 // Slot tables of the marked cones: slot = number of marked cones before it
@@ -180,38 +189,38 @@ __global__ void __launch_bounds__(kPB) k_fill_cells(const unsigned long long* __
                                                     unsigned long long* __restrict__ cell_mask,
                                                     int32_t* __restrict__ slot_box, int32_t* __restrict__ slot_cone)
 {
-    const int64_t gid = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (gid >= (int64_t)nbox * ncell) return;
-    const int b = (int)(gid / ncell);
-    const int cell = (int)(gid - (int64_t)b * ncell);
-    const unsigned long long* P = prim + (int64_t)b * wpb;
-    const int64_t bit0 = (int64_t)cell * ns;
-    const int64_t w0 = bit0 >> 6;
-    const unsigned long long below = (bit0 & 63) ? P[w0] & ((1ull << (bit0 & 63)) - 1ull) : 0ull;
-    int64_t slot = woff[(int64_t)b * wpb + w0] + __popcll(below);
-    cell_base[gid] = (int32_t)slot;
-    for (int w = 0; w < W; ++w) {
-        unsigned long long m = 0;
-        const int i1 = ns < 64 * (w + 1) ? ns : 64 * (w + 1);
-        for (int is = 64 * w; is < i1; ++is) {
-            const int64_t bit = bit0 + is;
-            if ((P[bit >> 6] >> (bit & 63)) & 1ull) {
-                m |= 1ull << (is & 63);
-                slot_box[slot] = b;
-                slot_cone[slot] = (int32_t)bit;
-                ++slot;
+    GRID_LOOP(gid, (int64_t)nbox * ncell) {
+        const int b = (int)(gid / ncell);
+        const int cell = (int)(gid - (int64_t)b * ncell);
+        const unsigned long long* P = prim + (int64_t)b * wpb;
+        const int64_t bit0 = (int64_t)cell * ns;
+        const int64_t w0 = bit0 >> 6;
+        const unsigned long long below = (bit0 & 63) ? P[w0] & ((1ull << (bit0 & 63)) - 1ull) : 0ull;
+        int64_t slot = woff[(int64_t)b * wpb + w0] + __popcll(below);
+        cell_base[gid] = (int32_t)slot;
+        for (int w = 0; w < W; ++w) {
+            unsigned long long m = 0;
+            const int i1 = ns < 64 * (w + 1) ? ns : 64 * (w + 1);
+            for (int is = 64 * w; is < i1; ++is) {
+                const int64_t bit = bit0 + is;
+                if ((P[bit >> 6] >> (bit & 63)) & 1ull) {
+                    m |= 1ull << (is & 63);
+                    slot_box[slot] = b;
+                    slot_cone[slot] = (int32_t)bit;
+                    ++slot;
+                }
             }
+            cell_mask[gid * W + w] = m;
         }
-        cell_mask[gid * W + w] = m;
     }
 }
 
 __global__ void __launch_bounds__(kPB) k_slot_start(const int64_t* __restrict__ woff, int64_t wpb, int nbox,
                                                     int64_t nslots, int32_t* __restrict__ slot_start)
 {
-    const int64_t b = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (b > nbox) return;
-    slot_start[b] = (int32_t)(b < nbox ? woff[b * wpb] : nslots);
+    GRID_LOOP(b, (nbox) + 1) {
+        slot_start[b] = (int32_t)(b < nbox ? woff[b * wpb] : nslots);
+    }
 }
 
 // --------------------------------------------------- device buffer helpers
@@ -396,47 +405,47 @@ __global__ void __launch_bounds__(kPB) k_pair_table(LevelDev L, const double* __
                                                     int64_t np, int32_t* __restrict__ pr_slot, T* __restrict__ pr_t,
                                                     T* __restrict__ pr_g)
 {
-    const int64_t e = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (e >= np) return;
-    const int tb = owner(L.pair_base, L.nbox, e);
-    const int nT = L.box_start[tb + 1] - L.box_start[tb];
-    const int64_t rel = e - L.pair_base[tb];
-    const int cl_i = (int)(rel / nT), t = (int)(rel - (int64_t)cl_i * nT);
-    const int c = L.cou[L.cou_start[tb] + cl_i];
-    const int j = L.box_start[tb] + t;
-    ConeLoc cl;
-    cone_locate(pts[3 * j] - L.box_ctr[3 * c], pts[3 * j + 1] - L.box_ctr[3 * c + 1], pts[3 * j + 2] - L.box_ctr[3 * c + 2],
-                L.h, L.ds, L.dang, L.ns, L.nc, cl);
-    pr_slot[e] = lookup(L, c, cl.cell, cl.is);
-    pr_t[e] = (T)cl.ts;
-    pr_t[np + e] = (T)cl.tt;
-    pr_t[2 * np + e] = (T)cl.tp;
-    double s, co;
-    sincos(kappa * cl.r, &s, &co);
-    const double inv = 1.0 / (4.0 * kPi) / cl.r;
-    pr_g[e] = (T)(co * inv);
-    pr_g[np + e] = (T)(s * inv);
+    GRID_LOOP(e, np) {
+        const int tb = owner(L.pair_base, L.nbox, e);
+        const int nT = L.box_start[tb + 1] - L.box_start[tb];
+        const int64_t rel = e - L.pair_base[tb];
+        const int cl_i = (int)(rel / nT), t = (int)(rel - (int64_t)cl_i * nT);
+        const int c = L.cou[L.cou_start[tb] + cl_i];
+        const int j = L.box_start[tb] + t;
+        ConeLoc cl;
+        cone_locate(pts[3 * j] - L.box_ctr[3 * c], pts[3 * j + 1] - L.box_ctr[3 * c + 1], pts[3 * j + 2] - L.box_ctr[3 * c + 2],
+                    L.h, L.ds, L.dang, L.ns, L.nc, cl);
+        pr_slot[e] = lookup(L, c, cl.cell, cl.is);
+        pr_t[e] = (T)cl.ts;
+        pr_t[np + e] = (T)cl.tt;
+        pr_t[2 * np + e] = (T)cl.tp;
+        double s, co;
+        sincos(kappa * cl.r, &s, &co);
+        const double inv = 1.0 / (4.0 * kPi) / cl.r;
+        pr_g[e] = (T)(co * inv);
+        pr_g[np + e] = (T)(s * inv);
+    }
 }
 
 __global__ void __launch_bounds__(kPB) k_pair_keys(const int32_t* __restrict__ pr_slot, int64_t np,
                                                    uint32_t* __restrict__ key, int32_t* __restrict__ idx,
                                                    int32_t* __restrict__ cnt)
 {
-    const int64_t e = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (e >= np) return;
-    const int32_t s = pr_slot[e];
-    key[e] = s >= 0 ? (uint32_t)s : 0xffffffffu;   // pairs without a cone sort last
-    idx[e] = (int32_t)e;
-    if (s >= 0) atomicAdd(&cnt[s], 1);
+    GRID_LOOP(e, np) {
+        const int32_t s = pr_slot[e];
+        key[e] = s >= 0 ? (uint32_t)s : 0xffffffffu;   // pairs without a cone sort last
+        idx[e] = (int32_t)e;
+        if (s >= 0) atomicAdd(&cnt[s], 1);
+    }
 }
 
 __global__ void __launch_bounds__(kPB) k_pad_counts(const int32_t* __restrict__ cnt, int64_t nslots,
                                                     int64_t* __restrict__ ucnt, int64_t* __restrict__ pcnt)
 {
-    const int64_t s = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (s >= nslots) return;
-    ucnt[s] = cnt[s];
-    pcnt[s] = (cnt[s] + kPairQuad - 1) / kPairQuad * kPairQuad;
+    GRID_LOOP(s, nslots) {
+        ucnt[s] = cnt[s];
+        pcnt[s] = (cnt[s] + kPairQuad - 1) / kPairQuad * kPairQuad;
+    }
 }
 
 // Entry i of the slot-sorted pairs goes to position start[s] + (i - ustart[s])
@@ -451,15 +460,15 @@ __global__ void __launch_bounds__(kPB) k_pair_scatter(const uint32_t* __restrict
                                                       int32_t* __restrict__ pr_order, int32_t* __restrict__ pro_slot,
                                                       T* __restrict__ pro_t, T* __restrict__ pro_g)
 {
-    const int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (i >= nvalid) return;
-    const int64_t s = skey[i];
-    const int64_t pos = start[s] + (i - ustart[s]);
-    const int64_t e = sidx[i];
-    pr_order[pos] = (int32_t)e;
-    pro_slot[pos] = (int32_t)s;
-    for (int c = 0; c < 3; ++c) pro_t[c * no + pos] = pr_t[c * np + e];
-    for (int c = 0; c < 2; ++c) pro_g[c * no + pos] = pr_g[c * np + e];
+    GRID_LOOP(i, nvalid) {
+        const int64_t s = skey[i];
+        const int64_t pos = start[s] + (i - ustart[s]);
+        const int64_t e = sidx[i];
+        pr_order[pos] = (int32_t)e;
+        pro_slot[pos] = (int32_t)s;
+        for (int c = 0; c < 3; ++c) pro_t[c * no + pos] = pr_t[c * np + e];
+        for (int c = 0; c < 2; ++c) pro_g[c * no + pos] = pr_g[c * np + e];
+    }
 }
 
 // Placeholders after each slot's run (place -1, the slot's cone, zero
@@ -470,14 +479,14 @@ __global__ void __launch_bounds__(kPB) k_pair_padding(const int32_t* __restrict_
                                                       int32_t* __restrict__ pr_order, int32_t* __restrict__ pro_slot,
                                                       T* __restrict__ pro_t, T* __restrict__ pro_g)
 {
-    const int64_t s = (int64_t)blockIdx.x * kPB + threadIdx.x;
-    if (s >= nslots) return;
-    const int64_t end = s + 1 < nslots ? start[s + 1] : no;
-    for (int64_t pos = start[s] + cnt[s]; pos < end; ++pos) {
-        pr_order[pos] = -1;
-        pro_slot[pos] = (int32_t)s;
-        for (int c = 0; c < 3; ++c) pro_t[c * no + pos] = (T)0;
-        for (int c = 0; c < 2; ++c) pro_g[c * no + pos] = (T)0;
+    GRID_LOOP(s, nslots) {
+        const int64_t end = s + 1 < nslots ? start[s + 1] : no;
+        for (int64_t pos = start[s] + cnt[s]; pos < end; ++pos) {
+            pr_order[pos] = -1;
+            pro_slot[pos] = (int32_t)s;
+            for (int c = 0; c < 3; ++c) pro_t[c * no + pos] = (T)0;
+            for (int c = 0; c < 2; ++c) pro_g[c * no + pos] = (T)0;
+        }
     }
 }
 

@@ -665,8 +665,10 @@ def test_gpu_plan_counts_match_oracle(torch, case):
 def test_gpu_plan_equals_host_plan(torch, monkeypatch, prec, nrhs):
     """The plan built on the GPU (relevant cones, slot tables, cousin-pair
     tables in target and cone order) and the one built on the host
-    (IFGF_HOST_PLAN=1) have the same counts and give bitwise equal results,
-    forward and adjoint, on a sphere and on a ragged cloud."""
+    (IFGF_HOST_PLAN=1) have the same counts and the same results, forward
+    and adjoint, on a sphere and on a ragged cloud: equal up to the last bits
+    of the centred factors G(x_t, x_c) in the pair tables (the device's FP64
+    sine and cosine against the host library's)."""
     for pts, k in ((inputs.cube_sphere(24), 6.0 * math.pi), (inputs.random_box_points(5000, 8), 12.0)):
         a = dev(torch, inputs.densities(42, nrhs, pts.shape[0]), prec)
         res = {}
@@ -681,5 +683,6 @@ def test_gpu_plan_equals_host_plan(torch, monkeypatch, prec, nrhs):
         for key in ("n_cones", "n_dilated", "pairs_tabulated", "n_frames"):
             assert s0[key] == s1[key], key
         assert sum(s0["pairs_tabulated"]) > 0
-        assert np.array_equal(o0, o1) and np.array_equal(j0, j1)
+        tol = 1e-14 if prec == "fp64" else 1e-6
+        assert par(o0, o1) < tol and par(j0, j1) < tol
     monkeypatch.delenv("IFGF_HOST_PLAN")
