@@ -15,6 +15,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ifgf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# IFGF_ORACLE_LIB: load another build of the same source (the sanitizer runs)
+_LOAD = os.environ.get("IFGF_ORACLE_LIB") or _LIB
 MAX_LEVELS = 24
 
 
@@ -55,9 +57,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if _LOAD == _LIB and not os.path.exists(_LIB):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LOAD)
         P = ctypes.c_void_p
         L.oracle_direct.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_double, P, P,
                                     ctypes.c_int64, P]

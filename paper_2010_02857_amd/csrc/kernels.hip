@@ -12,6 +12,7 @@
 // interpolation weights and accumulation are FP32.
 #include "ifgf_internal.hpp"
 
+#include <cstdio>
 #include <cstdlib>
 #include <mutex>
 #include <type_traits>
@@ -2486,6 +2487,13 @@ inline bool cousin_two_phase_enabled()
     return !(v && *v && std::atoi(v) == 0);
 }
 
+// IFGF_AUTOTUNE_VERBOSE=1: the autotuner prints every timing to stderr.
+inline bool autotune_verbose()
+{
+    const char* v = std::getenv("IFGF_AUTOTUNE_VERBOSE");
+    return v && *v && std::atoi(v) != 0;
+}
+
 // The second stream of an eager apply (IFGF_SIDE_STREAM=0: one stream).
 inline bool side_stream_enabled()
 {
@@ -2860,6 +2868,8 @@ hipError_t autotune_t(DevicePlan& p, hipStream_t st)
                 (void)hipEventElapsedTime(&t, e0, e1);
                 ms = t < ms ? t : ms;
             }
+            if (autotune_verbose())
+                std::fprintf(stderr, "autotune: level %d rb %d variant %d: %.3f ms\n", d, RB, v[i], (double)ms);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = v[i];

@@ -13,7 +13,8 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libifgf.so")
+# IFGF_LIB: load another build of the same sources (the sanitizer runs)
+LIB_PATH = os.environ.get("IFGF_LIB") or os.path.join(HERE, "libifgf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ifgf.h")
 MAX_LEVELS = 24
 
