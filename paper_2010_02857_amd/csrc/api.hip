@@ -135,6 +135,17 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
         if (parent_of_interp) {
             if ((e = upload(p, H.chl_start, &L.chl_start)) != hipSuccess) return e;
         }
+        if (interp_level) {
+            // pair offsets of every level (the two-phase cousin evaluation)
+            std::vector<long long> off(H.nbox + 1, 0);
+            for (int64_t T = 0; T < H.nbox; ++T)
+                off[T + 1] = off[T] + (long long)(H.box_start[T + 1] - H.box_start[T]) *
+                                          (H.cou_start[T + 1] - H.cou_start[T]);
+            p.npairs_all[d] = off[H.nbox];
+            const long long* po = nullptr;
+            if ((e = upload(p, off, &po)) != hipSuccess) return e;
+            p.pair_off[d] = po;
+        }
         L.use_pairs = H.use_pairs ? 1 : 0;
         if (H.use_pairs && H.pairs_device) {
             // computed in device memory from this level's tables (uploaded above)

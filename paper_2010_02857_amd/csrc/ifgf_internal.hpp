@@ -325,6 +325,12 @@ struct DevicePlan {
     unsigned long long* miss = nullptr;
     void* zero_cone = nullptr;  // [P][kMaxRhsPass] complex zeros (FP32 view)
     int64_t max_pairs = 0;      // largest cousin-pair table of a level (0: none)
+    // (target box, cousin, target) pair offsets of every level d >= 3 (device,
+    // [nbox + 1]) and their counts, for the two-phase evaluation with
+    // per-pair geometry where no pair table is kept
+    const long long* pair_off[IFGF_MAX_LEVELS + 1] = {};
+    int64_t npairs_all[IFGF_MAX_LEVELS + 1] = {};
+    int64_t pval_pairs = 0;     // pairs the pval workspace holds
     std::vector<void*> allocs;
     size_t tree_bytes = 0;
     // workspaces, sized for `ws_rb` right-hand sides per pass

@@ -542,6 +542,108 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_sum(KernelConsts kc, Le
 }
 
 
+// Largest b in [0, n) with start[b] <= x (start ascending, start[0] <= x).
+__device__ inline int box_of_pair(const long long* start, int n, long long x)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Cousin-target interpolation in two phases on levels without tabulated
+// pairs.  Phase 1: one thread per (target box T, cousin c, target t) pair,
+// in the order of the pair tables (entry pair_off[T] + c n_T + t), computes
+// the target's cone of the cousin box, the interpolant there and the centred
+// factor G(x_t, x_c), and stores the product.  Neighbouring threads share T
+// and c, and mostly one cone, so their reads of the cone values coalesce
+// (the one-kernel form reads each pair's 75 x RB values in its own thread).
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_geo(KernelConsts kc, LevelDev L,
+                                                             const double* __restrict__ pts,
+                                                             const long long* __restrict__ pair_off, long long np,
+                                                             const cpx<T>* __restrict__ F,
+                                                             cpx<T>* __restrict__ pval)
+{
+    constexpr int P = PS * PA * PA;
+    const long long e = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (e >= np) return;
+    const int tb = box_of_pair(pair_off, L.nbox, e);
+    const int b0 = L.box_start[tb];
+    const int nT = L.box_start[tb + 1] - b0;
+    const long long rel = e - pair_off[tb];
+    const int ci = (int)(rel / nT), t = (int)(rel - (long long)ci * nT);
+    const int k = L.cou[L.cou_start[tb] + ci];
+    const int i = b0 + t;
+    ConeLoc cl;
+    cone_locate(pts[3 * i] - L.box_ctr[3 * k], pts[3 * i + 1] - L.box_ctr[3 * k + 1], pts[3 * i + 2] - L.box_ctr[3 * k + 2],
+                L.h, L.ds, L.dang, L.ns, L.nc, cl);
+    const int slot = lookup(L, k, cl.cell, cl.is);
+    cpx<T> v[RB];
+    if (slot < 0) {
+        atomicAdd(kc.miss, 1ull);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) v[r].x = v[r].y = (T)0;
+    } else {
+        T Ls[PS], Lt[PA], Lp[PA];
+        lagrange<T, PS>(cl.ts, kc.cs, Ls);
+        lagrange<T, PA>(cl.tt, kc.ca, Lt);
+        lagrange<T, PA>(cl.tp, kc.ca, Lp);
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
+        T c, s;
+        expi<T>(kc.kappa * cl.r, c, s);
+        const T inv = (T)(kInv4Pi / cl.r);
+        const T gr = c * inv, gi = s * inv;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const T x = v[r].x * gr - v[r].y * gi, y = v[r].x * gi + v[r].y * gr;
+            v[r].x = x;
+            v[r].y = y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) pval[e * RB + r] = v[r];
+}
+
+// Phase 2: every target adds its pairs' values in cousin order (one thread
+// per target, no atomics, so the result does not depend on scheduling).
+template <typename T, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_sum_geo(KernelConsts kc, LevelDev L,
+                                                                 const long long* __restrict__ pair_off,
+                                                                 const cpx<T>* __restrict__ pval,
+                                                                 cpx<T>* __restrict__ out)
+{
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int tb = L.pt_box[i];
+    const int b0 = L.box_start[tb];
+    const long long nT = L.box_start[tb + 1] - b0;
+    const long long base = pair_off[tb] + (i - b0);
+    const int nc = L.cou_start[tb + 1] - L.cou_start[tb];
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
+    for (int c = 0; c < nc; ++c) {
+        const long long e = base + c * nT;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cpx<T> v = pval[e * RB + r];
+            acc[r].x += v.x;
+            acc[r].y += v.y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        cpx<T> o = out[(size_t)i * RB + r];
+        o.x += acc[r].x;
+        o.y += acc[r].y;
+        out[(size_t)i * RB + r] = o;
+    }
+}
+
 // Child-to-parent interpolation, children at level d (Algorithm 1, second
 // inner loop): for every interpolation point x of every relevant cone of a
 // level-(d-1) box j,
@@ -851,15 +953,44 @@ template <> struct MfmaVec<double> { typedef md4 type; };
 template <typename T>
 using mvec = typename MfmaVec<T>::type;
 __device__ inline mf4 mfma16(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline md4 mfma16(double a, double b, md4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 // Row of element i of a 16 x 16 x 4 result in lane quarter q.
 template <typename T>
 __device__ inline int mfma_row(int q, int i)
 {
     return sizeof(T) == 8 ? q + 4 * i : 4 * q + i;
 }
-__device__ inline md4 mfma16(double a, double b, md4 c)
+
+// Tiles of CW columns: CW = 16 uses the 16 x 16 x 4 instruction; CW = 4 (FP64
+// with at most 8 real columns) uses v_mfma_f64_4x4x4_4b_f64 with the four
+// blocks as four groups of four rows sharing one B, which leaves no column
+// of the instruction empty.  That instruction takes A[lane % 16][lane / 16]
+// as the 16 x 16 x 4 one does and B[lane / 16][lane % 4], and returns row
+// 4 ((lane % 16) / 4) + lane / 16, column lane % 4 (checked on the device);
+// its FMA rate equals the 16 x 16 x 4 one's.
+template <typename T, int CW>
+using macc = typename std::conditional<CW == 16, mvec<T>, T>::type;
+
+template <int CW, typename T>
+__device__ inline macc<T, CW> mfma_step(T a, T b, macc<T, CW> c)
 {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    if constexpr (CW == 16) {
+        return mfma16(a, b, c);
+    } else {
+        static_assert(sizeof(T) == 8, "four-column tiles are FP64 only");
+        return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+    }
+}
+
+// Row (within the tile) of output element i of this lane.
+template <int CW, typename T>
+__device__ inline int mfma_out_row(int lane, int i)
+{
+    if constexpr (CW == 16) return mfma_row<T>(lane >> 4, i);
+    else return 4 * ((lane & 15) >> 2) + (lane >> 4);
 }
 
 // v[i] for a lane-dependent i, as a chain of selects on register values.
@@ -883,22 +1014,25 @@ __device__ inline T pick(const T* v, int i)
 // columns the NC real values of the RB right-hand sides in NT tiles of 16.
 // `b` holds the child cone's values as B operands (K ordering as described
 // above); Ls/Lt/Lpv are the Chebyshev weights of this lane's row.
-template <int PS, int PA, int NT, typename T>
+template <int PS, int PA, int NT, int CW = 16, typename T>
 __device__ inline void mfma_tile(const T (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4], const T* Ls,
-                                 const T* Lt, const T* Lpv, int q, mvec<T>* c)
+                                 const T* Lt, const T* Lpv, int q, macc<T, CW>* c)
 {
     constexpr int NAB = PS * PA;
     constexpr int NREM = NAB * (PA - 4);
     constexpr int KTAIL = (NREM + 3) / 4;
     const T lq = pick<4>(Lpv, q);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) c[t] = mvec<T>{(T)0, (T)0, (T)0, (T)0};
+    for (int t = 0; t < NT; ++t) {
+        if constexpr (CW == 16) c[t] = mvec<T>{(T)0, (T)0, (T)0, (T)0};
+        else c[t] = (T)0;
+    }
 #pragma unroll
     for (int ab = 0; ab < NAB; ++ab) {
         const int a = ab / PA, bb = ab - a * PA;
         const T w = Ls[a] * Lt[bb] * lq;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) c[t] = mfma16(w, b[t][ab], c[t]);
+        for (int t = 0; t < NT; ++t) c[t] = mfma_step<CW>(w, b[t][ab], c[t]);
     }
 #pragma unroll
     for (int jt = 0; jt < KTAIL; ++jt) {
@@ -910,13 +1044,13 @@ __device__ inline void mfma_tile(const T (*b)[PS * PA + (PS * PA * (PA - 4) + 3)
             w = pick<PS>(Ls, a) * pick<PA>(Lt, bb) * pick<PA>(Lpv, cc);
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) c[t] = mfma16(w, b[t][NAB + jt], c[t]);
+        for (int t = 0; t < NT; ++t) c[t] = mfma_step<CW>(w, b[t][NAB + jt], c[t]);
     }
 }
 
 // B operands of a child cone: lane (q, col) takes K entries (a, b, c = q)
 // and the tail entries c >= 4, column 16 t + col of every tile t.
-template <int PS, int PA, int NC, int NT, typename T>
+template <int PS, int PA, int NC, int NT, int CW = 16, typename T>
 __device__ inline void mfma_load_b(const T* __restrict__ Fcs, int q, int col,
                                    T (*b)[PS * PA + (PS * PA * (PA - 4) + 3) / 4])
 {
@@ -925,7 +1059,7 @@ __device__ inline void mfma_load_b(const T* __restrict__ Fcs, int q, int col,
     constexpr int KTAIL = (NREM + 3) / 4;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int cg = 16 * t + col;
+        const int cg = CW * t + col;
         const bool ok = cg < NC;
 #pragma unroll
         for (int ab = 0; ab < NAB; ++ab) b[t][ab] = ok ? Fcs[(size_t)(ab * PA + q) * NC + cg] : (T)0;
@@ -945,18 +1079,21 @@ __device__ inline void mfma_load_b(const T* __restrict__ Fcs, int q, int col,
 // Epilogue of a tile: rows mfma_row(q, i), column col of each tile; multiply by the
 // row's ratio (complex: columns 2r, 2r+1 are re, im of right-hand side r) and
 // accumulate into the wavefront's LDS values of the parent slot.
-template <int NC, int NT, typename T>
-__device__ inline void mfma_epilogue(const mvec<T>* c, int q, int col, int t0, int cnt, const int* rownode,
+template <int NC, int NT, int CW = 16, typename T>
+__device__ inline void mfma_epilogue(const macc<T, CW>* c, int lane, int t0, int cnt, const int* rownode,
                                      const T* ratio_re, const T* ratio_im, T* acc)
 {
+    const int col = lane % CW;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int ri = t0 + mfma_row<T>(q, i);
+    for (int i = 0; i < (CW == 16 ? 4 : 1); ++i) {
+        const int ri = t0 + mfma_out_row<CW, T>(lane, i);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const T v = c[t][i];
+            T v;
+            if constexpr (CW == 16) v = c[t][i];
+            else v = c[t];
             const T pv = __shfl_xor(v, 1, 64);
-            const int cg = 16 * t + col;
+            const int cg = CW * t + col;
             if (ri < cnt && cg < NC) {
                 const int nu = rownode[ri];
                 const T gr = ratio_re[ri], gi = ratio_im[ri];
@@ -974,7 +1111,9 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
 {
     constexpr int P = PS * PA * PA;
     constexpr int NC = 2 * RB;                 // real columns
-    constexpr int NT = (NC + 15) / 16;         // 16-column tiles
+    constexpr int CW = 16;                     // columns per tile (the prefetched
+                                               // operands of four-column tiles would spill)
+    constexpr int NT = (NC + CW - 1) / CW;     // tiles
     constexpr int G = kMaxFrameGroups;
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
@@ -999,7 +1138,7 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
     const T* frt = (const T*)Lc.fr_t;
     const T* frr = (const T*)Lc.fr_ratio;
     const T conj_sign = kc.adj ? (T)-1 : (T)1;
-    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int row = lane & 15, q = lane >> 4, col = lane % CW;
     const int j = Lp.slot_box[sp];
 
     // entries (octant, group) of this slot: lanes 0..7 hold the octants
@@ -1028,7 +1167,7 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
     auto fetch = [&](int e) {
         const int f = entf[wv][e];
         const int cs = entcs[wv][e];
-        mfma_load_b<PS, PA, NC, NT>(F + (size_t)(cs >= 0 ? cs : 0) * P * NC, q, col, bn);
+        mfma_load_b<PS, PA, NC, NT, CW>(F + (size_t)(cs >= 0 ? cs : 0) * P * NC, q, col, bn);
         const uint8_t* ord = Lc.fr_order + (size_t)f * P;
         const int g0 = entr[wv][e] & 255, cnt = entr[wv][e] >> 8;
 #pragma unroll
@@ -1103,9 +1242,9 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
 #pragma unroll
                 for (int i = 0; i < PS; ++i) Ls[i] = (T)0;
             }
-            mvec<T> c[NT];
-            mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
-            mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
+            macc<T, CW> c[NT];
+            mfma_tile<PS, PA, NT, CW>(b, Ls, Lt, Lpv, q, c);
+            mfma_epilogue<NC, NT, CW>(c, lane, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
         }
         wave_lds_fence();
     }
@@ -1116,8 +1255,10 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
 
 // The same on levels without tabulated frames: every lane computes the
 // child-frame geometry of its interpolation points in FP64 (as
-// k_child_to_parent does), and the wavefront groups the points by child cone
-// with ballots before running the MFMA tiles.
+// k_child_to_parent does); the wavefront then sorts the octant's points by
+// child cone with ballots ("groups"), looks the groups' cones up in
+// parallel, and runs the groups' MFMA tiles with the next group's B operands
+// loaded while the current group's tiles run.
 template <typename T, int PS, int PA, int RB, int W>
 __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                       const cpx<T>* __restrict__ Fc,
@@ -1125,15 +1266,19 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
 {
     constexpr int P = PS * PA * PA;
     constexpr int NC = 2 * RB;
-    constexpr int NT = (NC + 15) / 16;
+    constexpr int CW = 16;                     // columns per tile
+    constexpr int NT = (NC + CW - 1) / CW;
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
     static_assert(P <= 128, "two passes of 64 points");
     __shared__ T accs[W][P * NC];
     __shared__ T nt[W][P][3];                  // local coordinates of every point
     __shared__ T nrr[W][P], nri[W][P];         // ratio of every point
-    __shared__ int rown[W][P];
-    __shared__ T rre[W][P], rim[W][P];
+    __shared__ int rown[W][P];                 // points in group order
+    __shared__ T rre[W][P], rim[W][P];         // their ratios
+    __shared__ unsigned gkey[W][P];            // child cone of each group
+    __shared__ int goff[W][P + 1];             // first row of each group
+    __shared__ int gcs[W][P];                  // child slot of each group, -1 missing
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1143,7 +1288,7 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
     for (int i = lane; i < P * NC; i += 64) acc[i] = (T)0;
 
     const T* F = (const T*)Fc;
-    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int row = lane & 15, q = lane >> 4, col = lane % CW;
     const int j = Lp.slot_box[sp];
     const int pcone = Lp.slot_cone[sp];
     const int pcell = pcone / Lp.ns, pis = pcone - pcell * Lp.ns;
@@ -1183,8 +1328,10 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
                 nri[wv][nu] = mag * sph;
             }
         }
-        __threadfence_block();
+        wave_lds_fence();
+        // the groups: points sorted by child cone, in order of first appearance
         bool un0 = lane < P, un1 = lane + 64 < P;
+        int ng = 0, base = 0;
         for (;;) {
             const unsigned long long m0 = __ballot(un0), m1 = __ballot(un1);
             if (!m0 && !m1) break;
@@ -1193,35 +1340,62 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
             const bool in0 = un0 && key[0] == lkey, in1 = un1 && key[1] == lkey;
             const unsigned long long g0 = __ballot(in0), g1 = __ballot(in1);
             const int c0n = __popcll(g0);
-            const int cnt = c0n + __popcll(g1);
             if (in0) {
-                const int r = __popcll(g0 & lt_mask);
+                const int r = base + __popcll(g0 & lt_mask);
                 rown[wv][r] = lane;
                 rre[wv][r] = nrr[wv][lane];
                 rim[wv][r] = nri[wv][lane];
             }
             if (in1) {
-                const int r = c0n + __popcll(g1 & lt_mask);
+                const int r = base + c0n + __popcll(g1 & lt_mask);
                 rown[wv][r] = lane + 64;
                 rre[wv][r] = nrr[wv][lane + 64];
                 rim[wv][r] = nri[wv][lane + 64];
             }
+            if (lane == 0) {
+                gkey[wv][ng] = lkey;
+                goff[wv][ng] = base;
+            }
+            base += c0n + __popcll(g1);
+            ++ng;
             un0 = un0 && !in0;
             un1 = un1 && !in1;
-            const int cell = (int)(lkey / (unsigned)Lc.ns), is = (int)(lkey - (unsigned)cell * Lc.ns);
+        }
+        if (lane == 0) goff[wv][ng] = base;
+        wave_lds_fence();
+        // the groups' child slots, looked up together
+        for (int g = lane; g < ng; g += 64) {
+            const unsigned kk = gkey[wv][g];
+            const int cell = (int)(kk / (unsigned)Lc.ns), is = (int)(kk - (unsigned)cell * Lc.ns);
             const int cs = lookup(Lc, k, cell, is);
-            __threadfence_block();
-            if (cs < 0) {
-                if (lane == 0) atomicAdd(kc.miss, (unsigned long long)cnt);
-                continue;
-            }
+            gcs[wv][g] = cs;
+            if (cs < 0) atomicAdd(kc.miss, (unsigned long long)(goff[wv][g + 1] - goff[wv][g]));
+        }
+        wave_lds_fence();
+        // the tiles, group by group, with the next group's operands in flight
+        T bn[NT][NK];
+        auto fetch = [&](int g) {
+            const int cs = gcs[wv][g];
+            mfma_load_b<PS, PA, NC, NT, CW>(F + (size_t)(cs >= 0 ? cs : 0) * P * NC, q, col, bn);
+        };
+        fetch(0);
+        for (int g = 0; g < ng; ++g) {
             T b[NT][NK];
-            mfma_load_b<PS, PA, NC, NT>(F + (size_t)cs * P * NC, q, col, b);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int kk = 0; kk < NK; ++kk) {
+                    b[t][kk] = bn[t][kk];
+                    asm volatile("" : "+v"(b[t][kk]));
+                }
+            fetch(g + 1 < ng ? g + 1 : g);
+            if (gcs[wv][g] < 0) continue;
+            const int g0 = goff[wv][g], cnt = goff[wv][g + 1] - g0;
             for (int t0 = 0; t0 < cnt; t0 += 16) {
                 T Ls[PS], Lt[PA], Lpv[PA];
                 const int rr = t0 + row;
                 if (rr < cnt) {
-                    const int nu = rown[wv][rr];
+                    const int nu = rown[wv][g0 + rr];
                     lagrange<T, PS>((double)nt[wv][nu][0], kc.cs, Ls);
                     lagrange<T, PA>((double)nt[wv][nu][1], kc.ca, Lt);
                     lagrange<T, PA>((double)nt[wv][nu][2], kc.ca, Lpv);
@@ -1231,12 +1405,12 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
 #pragma unroll
                     for (int i = 0; i < PA; ++i) Lt[i] = Lpv[i] = (T)0;
                 }
-                mvec<T> c[NT];
-                mfma_tile<PS, PA, NT>(b, Ls, Lt, Lpv, q, c);
-                mfma_epilogue<NC, NT>(c, q, col, t0, cnt, rown[wv], rre[wv], rim[wv], acc);
-                __threadfence_block();
+                macc<T, CW> c[NT];
+                mfma_tile<PS, PA, NT, CW>(b, Ls, Lt, Lpv, q, c);
+                mfma_epilogue<NC, NT, CW>(c, lane, t0, cnt, &rown[wv][g0], &rre[wv][g0], &rim[wv][g0], acc);
             }
         }
+        wave_lds_fence();
     }
     T* out = (T*)(Fp + (size_t)sp * P * RB);
     for (int i = lane; i < P * NC; i += 64) out[i] = acc[i];
@@ -2257,6 +2431,20 @@ inline Window target_window(const DevicePlan& p)
 
 inline int rb_for(int nrhs) { return nrhs >= 5 ? 16 : (nrhs >= 2 ? 4 : 1); }
 
+// Pairs the per-pair value buffer holds: those of the largest tabulated level,
+// and of the largest untabulated one when that fits the budget
+// (IFGF_PVAL_BUDGET_MB, default 32768) at rb right-hand sides.
+inline int64_t pval_pairs_for(const DevicePlan& p, int rb, size_t ce)
+{
+    int64_t geo = 0;
+    for (int d = 3; d <= p.hp.D; ++d)
+        if (!p.hp.L[d].use_pairs) geo = std::max<int64_t>(geo, p.npairs_all[d]);
+    const char* v = std::getenv("IFGF_PVAL_BUDGET_MB");
+    const double budget = (v && *v ? std::atof(v) : 32768.0) * 1024.0 * 1024.0;
+    if ((double)geo * rb * ce > budget) geo = 0;
+    return std::max<int64_t>(p.max_pairs, geo);
+}
+
 // Workspaces for `rb` right-hand sides per pass; cone values either for every
 // level (store) or in two buffers used alternately.  Sets *fresh when the
 // buffers were (re)allocated, which discards stored cone values.
@@ -2285,7 +2473,8 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
         maxs = std::max(maxs, (size_t)hp.L[d].nslots);
         tot += (size_t)hp.L[d].nslots;
     }
-    need += (store ? tot : 2 * maxs) * hp.P * rb * ce + (size_t)p.max_pairs * rb * ce;
+    const int64_t pv_pairs = pval_pairs_for(p, rb, ce);
+    need += (store ? tot : 2 * maxs) * hp.P * rb * ce + (size_t)pv_pairs * rb * ce;
     if (p.ws_limit && p.tree_bytes + need > p.ws_limit) return hipErrorOutOfMemory;
     auto alloc = [&](size_t bytes, void** out) -> hipError_t {
         if (bytes == 0) bytes = 16;
@@ -2303,7 +2492,9 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     if ((e = alloc((size_t)hp.n * 3 * sizeof(double), &gm)) != hipSuccess) return e;
     p.grad_m = (double*)gm;
     p.pval = nullptr;
-    if (p.max_pairs > 0 && (e = alloc((size_t)p.max_pairs * rb * ce, &p.pval)) != hipSuccess) return e;
+    p.pval_pairs = 0;
+    if (pv_pairs > 0 && (e = alloc((size_t)pv_pairs * rb * ce, &p.pval)) != hipSuccess) return e;
+    p.pval_pairs = pv_pairs;
     if (store) {
         for (int d = 3; d <= D; ++d)
             if ((e = alloc((size_t)hp.L[d].nslots * hp.P * rb * ce, &p.F[d])) != hipSuccess) return e;
@@ -2479,6 +2670,14 @@ inline bool cousin_mfma_enabled()
     return v && *v && std::atoi(v) != 0;
 }
 
+// Two-phase cousin evaluation with per-pair geometry on levels without pair
+// tables: on unless IFGF_COUSIN_GEO_PAIRS=0.
+inline bool cousin_geo_pairs_enabled()
+{
+    const char* v = std::getenv("IFGF_COUSIN_GEO_PAIRS");
+    return !(v && *v && std::atoi(v) == 0);
+}
+
 // Two-phase cousin evaluation for one right-hand side: on unless
 // IFGF_COUSIN_TWO_PHASE=0.
 inline bool cousin_two_phase_enabled()
@@ -2558,12 +2757,19 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
             k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
     }
     if (done) {
-    } else if (p.L[d].use_pairs)
+    } else if (p.L[d].use_pairs) {
         k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
                                                                            (C*)p.out_m);
-    else
+    } else if (p.pval && p.pair_off[d] && p.npairs_all[d] <= p.pval_pairs && cousin_geo_pairs_enabled()) {
+        // two phases with the geometry computed per pair
+        k_cousin_pairs_geo<T, PS, PA, RB><<<grid_for((size_t)p.npairs_all[d]), kBlock, 0, st>>>(
+            kc, p.L[d], p.pts, p.pair_off[d], p.npairs_all[d], (const C*)p.F[d], (C*)p.pval);
+        k_cousin_pairs_sum_geo<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pair_off[d], (const C*)p.pval,
+                                                                      (C*)p.out_m);
+    } else {
         k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
                                                                      (C*)p.out_m);
+    }
 }
 
 // Leaf values, then for d = D..3 the cousin evaluation of level d and the
@@ -2777,6 +2983,7 @@ hipError_t apply_noalloc_t(DevicePlan& p, const void* dens, int nrhs, void* out,
     void* s_dens = p.dens_m;
     void* s_out = p.out_m;
     void* s_pval = p.pval;
+    const int64_t s_pval_pairs = p.pval_pairs;
     void* s_F[IFGF_MAX_LEVELS + 1];
     for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) s_F[d] = p.F[d];
     const bool s_prof = p.profiling;
@@ -2785,6 +2992,7 @@ hipError_t apply_noalloc_t(DevicePlan& p, const void* dens, int nrhs, void* out,
     p.out_m = q + b_dens;
     void* cone[2] = {q + 2 * b_dens, q + 2 * b_dens + b_cone};
     p.pval = p.max_pairs > 0 ? (void*)(q + 2 * b_dens + 2 * b_cone) : nullptr;
+    p.pval_pairs = p.max_pairs;   // the scratch holds the tabulated levels' pairs only
     for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) p.F[d] = d >= 3 && d <= hp.D ? cone[d & 1] : nullptr;
     p.no_alloc = true;
     p.profiling = false;   // stage timers would create events
@@ -2800,6 +3008,7 @@ hipError_t apply_noalloc_t(DevicePlan& p, const void* dens, int nrhs, void* out,
     p.dens_m = s_dens;
     p.out_m = s_out;
     p.pval = s_pval;
+    p.pval_pairs = s_pval_pairs;
     for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) p.F[d] = s_F[d];
     return e;
 }

@@ -686,3 +686,32 @@ def test_gpu_plan_equals_host_plan(torch, monkeypatch, prec, nrhs):
         tol = 1e-14 if prec == "fp64" else 1e-6
         assert par(o0, o1) < tol and par(j0, j1) < tol
     monkeypatch.delenv("IFGF_HOST_PLAN")
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp64", 4), ("mixed", 1), ("mixed", 4), ("mixed", 16)])
+def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs):
+    """Levels without cousin-pair tables (IFGF_PAIR_BUDGET_MB=0): the
+    two-phase evaluation with the geometry computed per pair and the
+    one-kernel evaluation both match the oracle, forward and adjoint, and
+    each other."""
+    monkeypatch.setenv("IFGF_PAIR_BUDGET_MB", "0")
+    p = inputs.cube_sphere(20)
+    k = 5.0 * math.pi
+    a = inputs.densities(43, nrhs, p.shape[0])
+    ac = a if prec == "fp64" else as_c64(a)
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    ref = oracle.ifgf(p, ac, k)["out"]
+    ref_adj = np.conj(oracle.ifgf(p, np.conj(ac), k)["out"])
+    outs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("IFGF_COUSIN_GEO_PAIRS", flag)
+        plan = make_plan(p, k, prec, max_nrhs=16)
+        assert sum(plan.stats()["pairs_tabulated"]) == 0
+        outs[flag] = plan.apply(dev(torch, a, prec)).cpu().numpy()
+        adj = plan.adjoint(dev(torch, a, prec)).cpu().numpy()
+        assert par(outs[flag], ref) < tol
+        assert par(adj, ref_adj) < tol
+        assert plan.misses() == 0
+    assert par(outs["1"], outs["0"]) < (1e-13 if prec == "fp64" else 1e-6)
+    monkeypatch.delenv("IFGF_COUSIN_GEO_PAIRS")
+    monkeypatch.delenv("IFGF_PAIR_BUDGET_MB")
