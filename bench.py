@@ -58,10 +58,25 @@ def kernel_source_hash() -> str:
 # the profiled configuration: the headline (workload 5, FP64, its 4 RHS)
 PROFILE_WORKLOAD = 5
 PROFILE_PRECISION = "fp64"
-WORKLOAD_TAG = "sphere6291456_fp64_4rhs"
 TRACE_ARGS = "--steps 2 --warmup 1 --no-extras --no-cpu-baseline --no-eps"
 PMC_ARGS = "--steps 1 --warmup 1 --no-extras --no-cpu-baseline --no-eps --copy-calibration"
 SQ_ARGS = "--steps 1 --warmup 1 --no-extras --no-cpu-baseline --no-eps"
+# the profiled configuration: the headline by default; the profiling and
+# summary commands take --workload / --precision / --nrhs too
+PROFILE = {"workload": PROFILE_WORKLOAD, "precision": PROFILE_PRECISION, "nrhs": 0, "autotune": False}
+
+
+def workload_tag(workload: int, precision: str, nrhs: int) -> str:
+    n = {2: 393216, 5: 6291456}[workload]
+    if nrhs <= 0:
+        nrhs = {2: 1, 5: 4}[workload]
+    return f"sphere{n}_{precision}_{nrhs}rhs"
+
+
+def config_args() -> str:
+    a = f" --workload {PROFILE['workload']} --precision {PROFILE['precision']}"
+    a += f" --nrhs {PROFILE['nrhs']}" if PROFILE["nrhs"] > 0 else ""
+    return a + (" --autotune" if PROFILE["autotune"] else "")
 SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VALU_MFMA_F32 SQ_INSTS_VALU_MFMA_F64 "
                "SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_LDS")
 SIMDS = 1024                   # 256 CUs x 4 SIMDs
@@ -72,12 +87,13 @@ MFMA_VARIANTS = ("mfma", "mfma_geometry", "boxes", "box_acc")
 
 
 def profile_commands(d: str) -> list[str]:
+    c = config_args()
     return [
-        f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- python3 bench.py {TRACE_ARGS} "
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- python3 bench.py {TRACE_ARGS}{c} "
         f"--stats-out {d}/plan_stats.json",
-        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- python3 bench.py {PMC_ARGS}",
-        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- python3 bench.py {PMC_ARGS}",
-        f"rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d {d}/sq -o run -- python3 bench.py {SQ_ARGS}",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- python3 bench.py {PMC_ARGS}{c}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- python3 bench.py {PMC_ARGS}{c}",
+        f"rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d {d}/sq -o run -- python3 bench.py {SQ_ARGS}{c}",
     ]
 
 
@@ -117,6 +133,7 @@ def _timed(rows: list, steps: int) -> list:
 
 
 def summarize(d: str) -> int:
+    WORKLOAD_TAG = workload_tag(PROFILE["workload"], PROFILE["precision"], PROFILE["nrhs"])
     """Writes profiles/<stage>_<workload>_kernel_trace.md and, from the two
     counter runs, profiles/traffic_<stage>_<workload>.{json,md}; only the
     launches of the timed matvecs are counted."""
@@ -135,7 +152,7 @@ def summarize(d: str) -> int:
         a[0] += 1
         a[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
     total = sum(v[1] for v in agg.values())
-    lines = [f"# Kernel trace, {WORKLOAD_TAG}: {TRACE_ARGS}", "",
+    lines = [f"# Kernel trace, {WORKLOAD_TAG}: {TRACE_ARGS}{config_args()}", "",
              "Command (repository root):", "", "    " + cmds[0], "",
              f"Launches of the {steps} timed matvecs (autotuning and warm-up launches excluded).", "",
              "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
@@ -206,6 +223,7 @@ def summarize(d: str) -> int:
 
 
 def summarize_sq(d: str, cmd: str, trace_rows: list) -> None:
+    WORKLOAD_TAG = workload_tag(PROFILE["workload"], PROFILE["precision"], PROFILE["nrhs"])
     """profiles/sq_child_to_parent_<workload>.md: instruction counts of each
     child-to-parent launch of one timed matvec (SQ counters, summed over the
     chip), per evaluation and as a fraction of the chip's issue capacity over
@@ -340,6 +358,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=PROFILE_WORKLOAD, choices=(2, 5))
     ap.add_argument("--precision", default=PROFILE_PRECISION, choices=("fp64", "mixed"))
+    ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides (0: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--no-eps", action="store_true", help="skip the direct-sum accuracy check (profiling runs)")
@@ -350,6 +369,7 @@ def main() -> int:
     ap.add_argument("--profile-commands", metavar="DIR", help="print the profiling commands and exit")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from profiling outputs and exit")
     args = ap.parse_args()
+    PROFILE.update(workload=args.workload, precision=args.precision, nrhs=args.nrhs, autotune=args.autotune)
     if args.profile_commands:
         print("\n".join(profile_commands(args.profile_commands)))
         return 0
@@ -379,11 +399,11 @@ def main() -> int:
     w = inputs.WORKLOADS[args.workload]
     p = w.points()
     n = p.shape[0]
-    nrhs = w.nrhs
+    nrhs = args.nrhs if args.nrhs > 0 else w.nrhs
     prec = args.precision
     fp64 = prec == "fp64"
     cdt = torch.complex128 if fp64 else torch.complex64
-    a = w.densities()
+    a = w.densities(nrhs)
     P = 75
 
     def time_fn(fn, reps):
@@ -457,8 +477,8 @@ def main() -> int:
 
     # ---- roofline of the dominant kernel stage (child-to-parent)
     traffic = None
-    tf = os.path.join(ROOT, "profiles", f"traffic_child_to_parent_{WORKLOAD_TAG}.json")
-    if (args.workload, prec) == (PROFILE_WORKLOAD, PROFILE_PRECISION) and os.path.exists(tf):
+    tf = os.path.join(ROOT, "profiles", f"traffic_child_to_parent_{workload_tag(args.workload, prec, nrhs)}.json")
+    if os.path.exists(tf):
         rec = json.load(open(tf))
         if rec.get("kernel_source_hash") == kernel_source_hash():
             traffic = rec.get("hbm_bytes_per_launch")

@@ -608,6 +608,46 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_geo(KernelConsts kc, Le
     for (int r = 0; r < RB; ++r) pval[e * RB + r] = v[r];
 }
 
+// The same phase 1 through a level's pair table (slot, local coordinates and
+// centred factor tabulated in target order): one thread per pair, so that
+// neighbouring threads read the same cone values (the one-kernel form,
+// k_cousin_eval_pairs, walks one target's cousins per thread).  Phase 2 is
+// k_cousin_pairs_sum.
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_tab(KernelConsts kc, LevelDev L,
+                                                             const cpx<T>* __restrict__ F,
+                                                             cpx<T>* __restrict__ pval)
+{
+    constexpr int P = PS * PA * PA;
+    const long long e = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const long long np = L.npairs_cou;
+    if (e >= np) return;
+    const int slot = L.pr_slot[e];
+    cpx<T> v[RB];
+    if (slot < 0) {
+        // counted by the sum
+#pragma unroll
+        for (int r = 0; r < RB; ++r) v[r].x = v[r].y = (T)0;
+    } else {
+        const T* pt = (const T*)L.pr_t;
+        const T* pg = (const T*)L.pr_g;
+        T Ls[PS], Lt[PA], Lp[PA];
+        lagrange<T, PS>((double)pt[e], kc.cs, Ls);
+        lagrange<T, PA>((double)pt[np + e], kc.ca, Lt);
+        lagrange<T, PA>((double)pt[2 * np + e], kc.ca, Lp);
+        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
+        const T gr = pg[e], gi = (kc.adj ? (T)-1 : (T)1) * pg[np + e];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const T x = v[r].x * gr - v[r].y * gi, y = v[r].x * gi + v[r].y * gr;
+            v[r].x = x;
+            v[r].y = y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) pval[e * RB + r] = v[r];
+}
+
 // Phase 2: every target adds its pairs' values in cousin order (one thread
 // per target, no atomics, so the result does not depend on scheduling).
 template <typename T, int RB>
@@ -1257,8 +1297,9 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
 // child-frame geometry of its interpolation points in FP64 (as
 // k_child_to_parent does); the wavefront then sorts the octant's points by
 // child cone with ballots ("groups"), looks the groups' cones up in
-// parallel, and runs the groups' MFMA tiles with the next group's B operands
-// loaded while the current group's tiles run.
+// parallel (one lane per group), and runs the groups' MFMA tiles.  (Also
+// loading the next group's operands during the current group's tiles was
+// measured 20% slower in FP64 at 4 RHS: its registers cost a wave per SIMD.)
 template <typename T, int PS, int PA, int RB, int W>
 __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                       const cpx<T>* __restrict__ Fc,
@@ -1266,7 +1307,7 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
 {
     constexpr int P = PS * PA * PA;
     constexpr int NC = 2 * RB;
-    constexpr int CW = 16;                     // columns per tile
+    constexpr int CW = (sizeof(T) == 8 && NC <= 8) ? 4 : 16;   // columns per tile
     constexpr int NT = (NC + CW - 1) / CW;
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
@@ -1372,24 +1413,12 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
             if (cs < 0) atomicAdd(kc.miss, (unsigned long long)(goff[wv][g + 1] - goff[wv][g]));
         }
         wave_lds_fence();
-        // the tiles, group by group, with the next group's operands in flight
-        T bn[NT][NK];
-        auto fetch = [&](int g) {
-            const int cs = gcs[wv][g];
-            mfma_load_b<PS, PA, NC, NT, CW>(F + (size_t)(cs >= 0 ? cs : 0) * P * NC, q, col, bn);
-        };
-        fetch(0);
+        // the tiles, group by group
         for (int g = 0; g < ng; ++g) {
+            const int cs = gcs[wv][g];
+            if (cs < 0) continue;
             T b[NT][NK];
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int kk = 0; kk < NK; ++kk) {
-                    b[t][kk] = bn[t][kk];
-                    asm volatile("" : "+v"(b[t][kk]));
-                }
-            fetch(g + 1 < ng ? g + 1 : g);
-            if (gcs[wv][g] < 0) continue;
+            mfma_load_b<PS, PA, NC, NT, CW>(F + (size_t)cs * P * NC, q, col, b);
             const int g0 = goff[wv][g], cnt = goff[wv][g + 1] - g0;
             for (int t0 = 0; t0 < cnt; t0 += 16) {
                 T Ls[PS], Lt[PA], Lpv[PA];
@@ -2670,8 +2699,9 @@ inline bool cousin_mfma_enabled()
     return v && *v && std::atoi(v) != 0;
 }
 
-// Two-phase cousin evaluation with per-pair geometry on levels without pair
-// tables: on unless IFGF_COUSIN_GEO_PAIRS=0.
+// Two-phase cousin evaluation with one thread per pair (through the pair
+// table where a level has one without a cone-ordered copy, else with the
+// geometry per pair): on unless IFGF_COUSIN_GEO_PAIRS=0.
 inline bool cousin_geo_pairs_enabled()
 {
     const char* v = std::getenv("IFGF_COUSIN_GEO_PAIRS");
@@ -2757,6 +2787,14 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
             k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
     }
     if (done) {
+    } else if (p.L[d].use_pairs && p.pval && p.L[d].npairs_cou <= p.pval_pairs && cousin_geo_pairs_enabled() &&
+               hp.n < 64 * (int64_t)hp.L[d].nbox) {
+        // two phases through the pair table, where boxes hold few targets (in
+        // large boxes the threads of one target box already walk the same
+        // cousins together, and the one-kernel form measured faster)
+        k_cousin_pairs_tab<T, PS, PA, RB><<<grid_for((size_t)p.L[d].npairs_cou), kBlock, 0, st>>>(
+            kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+        k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
     } else if (p.L[d].use_pairs) {
         k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
                                                                            (C*)p.out_m);

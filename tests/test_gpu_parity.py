@@ -297,7 +297,8 @@ def test_small_and_degenerate(torch, case):
     assert plan.misses() == 0
 
 
-@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("mixed", 1), ("mixed", 4), ("mixed", 16)])
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp64", 4), ("fp64", 16), ("mixed", 1), ("mixed", 4),
+                                       ("mixed", 16)])
 def test_without_frame_tables(torch, monkeypatch, prec, nrhs):
     """The kernels that compute the child-to-parent geometry themselves (used
     where the frame tables would not fit) give the same results."""
@@ -688,13 +689,19 @@ def test_gpu_plan_equals_host_plan(torch, monkeypatch, prec, nrhs):
     monkeypatch.delenv("IFGF_HOST_PLAN")
 
 
+@pytest.mark.parametrize("tables", [False, True])
 @pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp64", 4), ("mixed", 1), ("mixed", 4), ("mixed", 16)])
-def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs):
-    """Levels without cousin-pair tables (IFGF_PAIR_BUDGET_MB=0): the
-    two-phase evaluation with the geometry computed per pair and the
-    one-kernel evaluation both match the oracle, forward and adjoint, and
-    each other."""
-    monkeypatch.setenv("IFGF_PAIR_BUDGET_MB", "0")
+def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs, tables):
+    """The two-phase cousin evaluation with one thread per pair and the
+    one-kernel evaluation (IFGF_COUSIN_GEO_PAIRS=0) both match the oracle,
+    forward and adjoint, and each other: on levels without cousin-pair
+    tables (IFGF_PAIR_BUDGET_MB=0, geometry per pair) and through the tables
+    (two-phase cone-ordered form off, so the per-pair form reads the tables
+    in target order)."""
+    if tables:
+        monkeypatch.setenv("IFGF_COUSIN_TWO_PHASE", "0")
+    else:
+        monkeypatch.setenv("IFGF_PAIR_BUDGET_MB", "0")
     p = inputs.cube_sphere(20)
     k = 5.0 * math.pi
     a = inputs.densities(43, nrhs, p.shape[0])
@@ -706,7 +713,7 @@ def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs):
     for flag in ("1", "0"):
         monkeypatch.setenv("IFGF_COUSIN_GEO_PAIRS", flag)
         plan = make_plan(p, k, prec, max_nrhs=16)
-        assert sum(plan.stats()["pairs_tabulated"]) == 0
+        assert (sum(plan.stats()["pairs_tabulated"]) > 0) == tables
         outs[flag] = plan.apply(dev(torch, a, prec)).cpu().numpy()
         adj = plan.adjoint(dev(torch, a, prec)).cpu().numpy()
         assert par(outs[flag], ref) < tol
@@ -714,4 +721,3 @@ def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs):
         assert plan.misses() == 0
     assert par(outs["1"], outs["0"]) < (1e-13 if prec == "fp64" else 1e-6)
     monkeypatch.delenv("IFGF_COUSIN_GEO_PAIRS")
-    monkeypatch.delenv("IFGF_PAIR_BUDGET_MB")
