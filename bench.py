@@ -426,6 +426,7 @@ def main() -> int:
     log(f"plan: {w.name} N={n} D={st['D']} {prec} cones/level={st['n_cones'][3:]} {t_plan:.1f}s "
         f"device {st['device_bytes'] / 1e9:.2f} GB")
     if args.stats_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.stats_out)), exist_ok=True)
         with open(args.stats_out, "w") as fh:
             json.dump(st, fh)
     t_tune = 0.0

@@ -46,6 +46,8 @@ class _Stats(ctypes.Structure):
         ("n_parent_evals", ctypes.c_int64 * (MAX_LEVELS + 1)),
         ("n_far_pairs", ctypes.c_int64 * (MAX_LEVELS + 1)),
         ("n_near_pairs", ctypes.c_int64),
+        ("n_src_boxes", ctypes.c_int64 * (MAX_LEVELS + 1)),
+        ("n_leaf_boxes", ctypes.c_int64 * (MAX_LEVELS + 1)),
         ("t_pre", ctypes.c_double),
         ("t_acc", ctypes.c_double),
     ]
@@ -67,6 +69,9 @@ def lib():
         L.oracle_ifgf.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
                                   ctypes.c_int64, P, P, P, ctypes.POINTER(_Stats)]
+        L.oracle_ifgf_ex.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, P, P, ctypes.c_int64, P, P, P, ctypes.POINTER(_Stats)]
         L.oracle_green.argtypes = [ctypes.c_double, P, P, P]
         L.oracle_analytic_factor.argtypes = [ctypes.c_double, P, P, P, P]
         L.oracle_cheb_nodes.argtypes = [ctypes.c_int32, P]
@@ -74,7 +79,7 @@ def lib():
                                           ctypes.c_double, ctypes.c_double, P]
         L.oracle_cone_coords.argtypes = [P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
         L.oracle_cone_point.argtypes = [P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P]
-        for f in (L.oracle_direct, L.oracle_direct_grad, L.oracle_ifgf):
+        for f in (L.oracle_direct, L.oracle_direct_grad, L.oracle_ifgf, L.oracle_ifgf_ex):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -138,9 +143,10 @@ def direct_grad(pts, dens, kappa, targets=None, skip=None):
 
 
 def ifgf(pts, dens, kappa, levels=0, degrees=(3, 5), leaf=(1, 2), targets=None, skip=None,
-         grad=False, sig=False):
+         grad=False, sig=False, leaf_max=0):
     """Plain FP64 IFGF.  Returns a dict with 'out' (nrhs, m), optional 'grad'
-    (nrhs, m, 3), 'sig' (m,) and 'stats' (per-level counts)."""
+    (nrhs, m, 3), 'sig' (m,) and 'stats' (per-level counts).  leaf_max > 0:
+    adaptive octree (boxes holding at most leaf_max points are not split)."""
     pts = _f64(pts).reshape(-1, 3)
     a = _dens(dens, pts.shape[0])
     if targets is None:
@@ -152,9 +158,9 @@ def ifgf(pts, dens, kappa, levels=0, degrees=(3, 5), leaf=(1, 2), targets=None, 
     g = np.zeros((a.shape[0], m, 3), np.complex128) if grad else None
     sg = np.zeros(m, np.uint64) if sig else None
     st = _Stats()
-    rc = lib().oracle_ifgf(_p(pts), pts.shape[0], _p(a), a.shape[0], float(kappa), int(levels),
-                           int(degrees[0]), int(degrees[1]), int(leaf[0]), int(leaf[1]), _p(t), _p(s),
-                           m, _p(out), _p(g), _p(sg), ctypes.byref(st))
+    rc = lib().oracle_ifgf_ex(_p(pts), pts.shape[0], _p(a), a.shape[0], float(kappa), int(levels),
+                              int(degrees[0]), int(degrees[1]), int(leaf[0]), int(leaf[1]), int(leaf_max),
+                              _p(t), _p(s), m, _p(out), _p(g), _p(sg), ctypes.byref(st))
     if rc != 0:
         raise ValueError(f"oracle_ifgf failed ({rc})")
     D = st.D
@@ -163,7 +169,7 @@ def ifgf(pts, dens, kappa, levels=0, degrees=(3, 5), leaf=(1, 2), targets=None, 
         "t_pre": st.t_pre, "t_acc": st.t_acc,
     }
     for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes",
-                "n_cousin_evals", "n_parent_evals", "n_far_pairs"):
+                "n_cousin_evals", "n_parent_evals", "n_far_pairs", "n_src_boxes", "n_leaf_boxes"):
         arr = getattr(st, key)
         stats[key] = [int(arr[d]) for d in range(D + 1)]
     res = {"out": out, "stats": stats}

@@ -36,6 +36,17 @@
  *   R10 Levels: D = 1 + round(log2(4 H_1 / lambda)) so that H_D ~ lambda/4
  *       (Sec. 4); for kappa = 0 the smallest D >= 2 with at most 8 points per
  *       relevant leaf box.
+ *   R16 Adaptive octree (named in Sec. 4 and Sec. 5 as the remedy for uneven
+ *       point counts per box, with no algorithm given): with leaf_max > 0 a
+ *       box of level d >= 2 holding at most leaf_max points (sources and
+ *       distinct targets together) is a leaf and is split no further; the
+ *       boxes below it take no part as sources.  Its sources reach the
+ *       targets of its neighbour boxes on its own level directly, its
+ *       relevant cones (rules (i) and (ii) as for any box) get their node
+ *       values directly from its sources, and from there on it is treated
+ *       like any box of its level.  Targets keep their boxes on every level,
+ *       so that the cousin relation of eq. (defcousinboxes) stays as it is.
+ *       leaf_max = 0 is the tree of Sec. 3.3.1 (every leaf on level D).
  */
 #include "ifgf_oracle.h"
 
@@ -347,6 +358,8 @@ typedef struct {
     int ns, nc;          /* cone intervals n_{s,d}, n_{C,d}                     */
     int64_t* cone_off;   /* R_C B: sorted relevant cone ids per box             */
     int64_t* cone;
+    uint8_t* active;     /* the box is part of the (adaptive) source tree       */
+    uint8_t* leaf;       /* an active box that is not split further             */
 } level_t;
 
 static uint64_t pack3(const int64_t* k) { return ((uint64_t)k[0] << 42) | ((uint64_t)k[1] << 21) | (uint64_t)k[2]; }
@@ -434,6 +447,8 @@ static void free_level(level_t* L)
     free(L->cou);
     free(L->cone_off);
     free(L->cone);
+    free(L->active);
+    free(L->leaf);
 }
 
 /* Slot of cone `id` of box b: position of id in the sorted list R_C B. */
@@ -477,14 +492,51 @@ static void node_loc(int pa, int nu, const double* ts, const double* ta, double*
 
 /* ------------------------------------------------------------- the method */
 
+/* The node values F_k^d (eq. I_k) of every relevant cone of box b of level
+ * Ld, summed directly over the box's sources, into vals[slot][node][rhs]. */
+static void direct_node_values(const level_t* Ld, int64_t b, const double* x1, double H1, int P, int pang,
+                               const double* tsn, const double* tan_, const double* pts, int64_t n,
+                               const cplx* a, int32_t nrhs, double kappa, cplx* vals)
+{
+    double ctr[3];
+    box_centre(x1, H1, Ld->H, Ld->key[b], ctr);
+    for (int64_t gi = Ld->cone_off[b]; gi < Ld->cone_off[b + 1]; ++gi) {
+        int32_t idx[3];
+        cone_idx(Ld->cone[gi], Ld->nc, idx);
+        for (int nu = 0; nu < P; ++nu) {
+            double loc[3], x[3];
+            node_loc(pang, nu, tsn, tan_, loc);
+            oracle_cone_point(ctr, Ld->H, Ld->ns, Ld->nc, idx, loc, x);
+            for (int32_t r = 0; r < nrhs; ++r) {
+                cplx F = 0.0;
+                for (int64_t si = Ld->src_off[b]; si < Ld->src_off[b + 1]; ++si) {
+                    int64_t j = Ld->src[si];
+                    F += a[(int64_t)r * n + j] * analytic_factor(kappa, ctr, x, &pts[3 * j]);
+                }
+                vals[((size_t)gi * P + nu) * nrhs + r] = F;
+            }
+        }
+    }
+}
+
 int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, double kappa, int32_t levels,
                 int32_t ps, int32_t pang, int32_t leaf_ns, int32_t leaf_nc, const double* tpos,
                 const int64_t* skip_in, int64_t m, double* out, double* grad, uint64_t* sig,
                 oracle_stats* stats)
 {
+    return oracle_ifgf_ex(pts, n, dens, nrhs, kappa, levels, ps, pang, leaf_ns, leaf_nc, 0, tpos, skip_in, m,
+                          out, grad, sig, stats);
+}
+
+int oracle_ifgf_ex(const double* pts, int64_t n, const double* dens, int32_t nrhs, double kappa, int32_t levels,
+                   int32_t ps, int32_t pang, int32_t leaf_ns, int32_t leaf_nc, int32_t leaf_max,
+                   const double* tpos, const int64_t* skip_in, int64_t m, double* out, double* grad,
+                   uint64_t* sig, oracle_stats* stats)
+{
     if (!pts || !dens || !out || n < 2 || nrhs < 1 || ps < 1 || pang < 1 || ps > 16 || pang > 16 ||
-        leaf_ns < 1 || leaf_nc < 1 || levels < 0 || levels > ORACLE_MAX_LEVELS)
+        leaf_ns < 1 || leaf_nc < 1 || levels < 0 || levels > ORACLE_MAX_LEVELS || leaf_max < 0)
         return -1;
+    const int distinct_targets = tpos != NULL;
     int64_t* skip_own = NULL;
     const int64_t* skip = skip_in;
     if (!tpos) {
@@ -669,6 +721,26 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
         Ld->cou = tmp;
     }
 
+    /* The source tree (reading R16): the root is split; below it a box is
+     * active when its parent is active and not a leaf, and an active box is
+     * a leaf on level D or when it holds at most leaf_max points. */
+    for (int d = 1; d <= D; ++d) {
+        level_t* Ld = &L[d];
+        Ld->active = (uint8_t*)calloc(Ld->nbox + 1, 1);
+        Ld->leaf = (uint8_t*)calloc(Ld->nbox + 1, 1);
+        for (int64_t b = 0; b < Ld->nbox; ++b) {
+            if (d == 1) {
+                Ld->active[b] = 1;
+                continue;
+            }
+            int64_t p = Ld->parent[b];
+            Ld->active[b] = L[d - 1].active[p] && !L[d - 1].leaf[p];
+            int64_t cnt = Ld->src_off[b + 1] - Ld->src_off[b];
+            if (distinct_targets) cnt += Ld->tgt_off[b + 1] - Ld->tgt_off[b];
+            Ld->leaf[b] = Ld->active[b] && (d == D || (leaf_max > 0 && cnt <= leaf_max));
+        }
+    }
+
     /* Cone intervals per level (reading R5). */
     L[D].ns = leaf_ns;
     L[D].nc = leaf_nc;
@@ -695,6 +767,7 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
         int64_t* lens = (int64_t*)calloc(Ld->nbox, sizeof(int64_t));
 #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t b = 0; b < Ld->nbox; ++b) {
+            if (!Ld->active[b]) continue;   /* not a source box: no cones */
             double ctr[3];
             box_centre(x1, H1, Ld->H, Ld->key[b], ctr);
             int64_t cap = 64, cnt = 0;
@@ -772,86 +845,79 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
     int64_t far_pairs[ORACLE_MAX_LEVELS + 1] = {0}, cousin_evals[ORACLE_MAX_LEVELS + 1] = {0},
             parent_evals[ORACLE_MAX_LEVELS + 1] = {0};
 
-    /* Level D: direct evaluations (Algorithm 1, first box loop). */
-    const level_t* LD = &L[D];
-    int64_t ncD = LD->cone_off[LD->nbox];
-    cplx* coef = (cplx*)calloc((size_t)ncD * P * nrhs + 1, sizeof(cplx));
+    /* Direct evaluations (Algorithm 1, first box loop): the sources of every
+     * leaf box at the targets of its neighbourhood U B, on the leaf's own
+     * level (level D only, unless the tree is adaptive). */
     int64_t np_acc = 0;
+    for (int d = 2; d <= D; ++d) {
+        const level_t* Ld = &L[d];
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : np_acc)
-    for (int64_t b = 0; b < LD->nbox; ++b) {
-        double ctr[3];
-        box_centre(x1, H1, LD->H, LD->key[b], ctr);
-        /* I_k^D at every target of the neighbourhood U B, sources of B only */
-        for (int64_t qi = LD->nbr_off[b]; qi < LD->nbr_off[b + 1]; ++qi) {
-            int64_t q = LD->nbr[qi];
-            for (int64_t ti = LD->tgt_off[q]; ti < LD->tgt_off[q + 1]; ++ti) {
-                int64_t t = LD->tgt[ti];
-                const double* xt = &tpos[3 * t];
-                for (int32_t r = 0; r < nrhs; ++r) {
-                    cplx v = 0.0, gv[3] = {0.0, 0.0, 0.0};
-                    for (int64_t si = LD->src_off[b]; si < LD->src_off[b + 1]; ++si) {
-                        int64_t j = LD->src[si];
-                        if (skip && skip[t] == j) continue;
-                        v += a[(int64_t)r * n + j] * green_r(kappa, dist3(xt, &pts[3 * j]));
-                        if (gacc) {
-                            cplx g[3];
-                            green_grad(kappa, xt, &pts[3 * j], g);
-                            for (int c = 0; c < 3; ++c) gv[c] += a[(int64_t)r * n + j] * g[c];
+        for (int64_t b = 0; b < Ld->nbox; ++b) {
+            if (!Ld->leaf[b]) continue;
+            for (int64_t qi = Ld->nbr_off[b]; qi < Ld->nbr_off[b + 1]; ++qi) {
+                int64_t q = Ld->nbr[qi];
+                for (int64_t ti = Ld->tgt_off[q]; ti < Ld->tgt_off[q + 1]; ++ti) {
+                    int64_t t = Ld->tgt[ti];
+                    const double* xt = &tpos[3 * t];
+                    for (int32_t r = 0; r < nrhs; ++r) {
+                        cplx v = 0.0, gv[3] = {0.0, 0.0, 0.0};
+                        for (int64_t si = Ld->src_off[b]; si < Ld->src_off[b + 1]; ++si) {
+                            int64_t j = Ld->src[si];
+                            if (skip && skip[t] == j) continue;
+                            v += a[(int64_t)r * n + j] * green_r(kappa, dist3(xt, &pts[3 * j]));
+                            if (gacc) {
+                                cplx g[3];
+                                green_grad(kappa, xt, &pts[3 * j], g);
+                                for (int c = 0; c < 3; ++c) gv[c] += a[(int64_t)r * n + j] * g[c];
+                            }
+                            if (r == 0) np_acc++;
                         }
-                        if (r == 0) np_acc++;
+                        atomic_add_c(&acc[2 * (t * nrhs + r)], v);
+                        if (gacc)
+                            for (int c = 0; c < 3; ++c) atomic_add_c(&gacc[2 * ((t * nrhs + r) * 3 + c)], gv[c]);
                     }
-                    atomic_add_c(&acc[2 * (t * nrhs + r)], v);
-                    if (gacc)
-                        for (int c = 0; c < 3; ++c) atomic_add_c(&gacc[2 * ((t * nrhs + r) * 3 + c)], gv[c]);
-                }
-                if (sig && LD->src_off[b + 1] > LD->src_off[b]) {
-                    uint64_t h = mix64(((uint64_t)D << 56) ^ LD->key[b] ^ 0x5555ull);
+                    if (sig && Ld->src_off[b + 1] > Ld->src_off[b]) {
+                        uint64_t h = mix64(((uint64_t)d << 56) ^ Ld->key[b] ^ 0x5555ull);
 #pragma omp atomic
-                    sg[t] += h;
-                }
-            }
-        }
-        /* F_k^D at all interpolation points of all relevant leaf cones */
-        for (int64_t gi = LD->cone_off[b]; gi < LD->cone_off[b + 1]; ++gi) {
-            int32_t idx[3];
-            cone_idx(LD->cone[gi], LD->nc, idx);
-            for (int nu = 0; nu < P; ++nu) {
-                double loc[3], x[3];
-                node_loc(pang, nu, tsn, tan_, loc);
-                oracle_cone_point(ctr, LD->H, LD->ns, LD->nc, idx, loc, x);
-                for (int32_t r = 0; r < nrhs; ++r) {
-                    cplx F = 0.0;
-                    for (int64_t si = LD->src_off[b]; si < LD->src_off[b + 1]; ++si) {
-                        int64_t j = LD->src[si];
-                        F += a[(int64_t)r * n + j] * analytic_factor(kappa, ctr, x, &pts[3 * j]);
+                        sg[t] += h;
                     }
-                    coef[((size_t)gi * P + nu) * nrhs + r] = F;
                 }
             }
         }
     }
     near_pairs = np_acc;
 
-    /* Interpolants of level D: node values -> Chebyshev coefficients. */
-#pragma omp parallel for schedule(static)
-    for (int64_t gi = 0; gi < ncD; ++gi) {
-        cplx u[16 * 16 * 16], A[16 * 16 * 16];
-        for (int32_t r = 0; r < nrhs; ++r) {
-            for (int nu = 0; nu < P; ++nu) u[nu] = coef[((size_t)gi * P + nu) * nrhs + r];
-            cheb_coeffs_3d(ps, pang, u, A);
-            for (int nu = 0; nu < P; ++nu) coef[((size_t)gi * P + nu) * nrhs + r] = A[nu];
-        }
-    }
+    /* Node values of level D; the levels above receive theirs from their
+     * children (pvals below). */
+    cplx* coef = (cplx*)calloc((size_t)L[D].cone_off[L[D].nbox] * P * nrhs + 1, sizeof(cplx));
 
     /* Interpolation, d = D..3 (Algorithm 1, second loop). */
     for (int d = D; d >= 3; --d) {
         const level_t* Ld = &L[d];
         const level_t* Lp = &L[d - 1];
+        /* F_k^d at all interpolation points of the relevant cones of the leaf
+         * boxes of level d, directly from their sources (eq. I_k) */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t b = 0; b < Ld->nbox; ++b)
+            if (Ld->leaf[b])
+                direct_node_values(Ld, b, x1, H1, P, pang, tsn, tan_, pts, n, a, nrhs, kappa, coef);
+        /* interpolants of level d: node values -> Chebyshev coefficients */
+        const int64_t ncd = Ld->cone_off[Ld->nbox];
+#pragma omp parallel for schedule(static)
+        for (int64_t gi = 0; gi < ncd; ++gi) {
+            cplx u[16 * 16 * 16], A[16 * 16 * 16];
+            for (int32_t r = 0; r < nrhs; ++r) {
+                for (int nu = 0; nu < P; ++nu) u[nu] = coef[((size_t)gi * P + nu) * nrhs + r];
+                cheb_coeffs_3d(ps, pang, u, A);
+                for (int nu = 0; nu < P; ++nu) coef[((size_t)gi * P + nu) * nrhs + r] = A[nu];
+            }
+        }
         int64_t ncp = (d > 3) ? Lp->cone_off[Lp->nbox] : 0;
         double* pvals = (d > 3) ? (double*)calloc((size_t)2 * ncp * P * nrhs + 2, sizeof(double)) : NULL;
         int64_t fp = 0, ce = 0, pe = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : fp, ce, pe)
         for (int64_t b = 0; b < Ld->nbox; ++b) {
+            if (!Ld->active[b]) continue;   /* not a source box */
             double ctr[3];
             box_centre(x1, H1, Ld->H, Ld->key[b], ctr);
             int64_t nsrc = Ld->src_off[b + 1] - Ld->src_off[b];
@@ -963,19 +1029,7 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
         cousin_evals[d] = ce;
         parent_evals[d] = pe;
         free(coef);
-        coef = NULL;
-        if (d > 3) {
-            coef = (cplx*)pvals;
-#pragma omp parallel for schedule(static)
-            for (int64_t gi = 0; gi < ncp; ++gi) {
-                cplx u[16 * 16 * 16], A[16 * 16 * 16];
-                for (int32_t r = 0; r < nrhs; ++r) {
-                    for (int nu = 0; nu < P; ++nu) u[nu] = coef[((size_t)gi * P + nu) * nrhs + r];
-                    cheb_coeffs_3d(ps, pang, u, A);
-                    for (int nu = 0; nu < P; ++nu) coef[((size_t)gi * P + nu) * nrhs + r] = A[nu];
-                }
-            }
-        }
+        coef = (cplx*)pvals;   /* node values of level d - 1 (NULL after level 3) */
     }
     free(coef);
 
@@ -1011,6 +1065,10 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs, 
             stats->n_cousin_evals[d] = cousin_evals[d];
             stats->n_parent_evals[d] = parent_evals[d];
             stats->n_far_pairs[d] = far_pairs[d];
+            for (int64_t b = 0; b < L[d].nbox; ++b) {
+                stats->n_src_boxes[d] += L[d].active[b];
+                stats->n_leaf_boxes[d] += L[d].leaf[b];
+            }
         }
     }
 

@@ -43,6 +43,8 @@ typedef struct {
     int64_t n_far_pairs[ORACLE_MAX_LEVELS + 1];     /* (target, source) pairs
                                                        covered at level d    */
     int64_t n_near_pairs;                     /* pairs summed directly       */
+    int64_t n_src_boxes[ORACLE_MAX_LEVELS + 1];     /* boxes of the source tree*/
+    int64_t n_leaf_boxes[ORACLE_MAX_LEVELS + 1];    /* its leaves on level d   */
     double t_pre;                             /* seconds: hierarchy and
                                                  relevant cones (T_pre)      */
     double t_acc;                             /* seconds: operator
@@ -84,6 +86,16 @@ int oracle_ifgf(const double* pts, int64_t n, const double* dens, int32_t nrhs,
                 int32_t leaf_ns, int32_t leaf_nc,
                 const double* tpos, const int64_t* skip, int64_t m,
                 double* out, double* grad, uint64_t* sig, oracle_stats* stats);
+
+/* oracle_ifgf on an adaptive octree (the reading of Sec. 4 and Sec. 5 stated
+ * in the source as R16): leaf_max > 0 stops splitting a box of level >= 2
+ * that holds at most leaf_max points (sources plus distinct targets);
+ * leaf_max = 0 gives oracle_ifgf exactly.                                   */
+int oracle_ifgf_ex(const double* pts, int64_t n, const double* dens, int32_t nrhs,
+                   double kappa, int32_t levels, int32_t ps, int32_t pang,
+                   int32_t leaf_ns, int32_t leaf_nc, int32_t leaf_max,
+                   const double* tpos, const int64_t* skip, int64_t m,
+                   double* out, double* grad, uint64_t* sig, oracle_stats* stats);
 
 /* The pieces of the method, exposed so that tests can pin them one by one. */
 

@@ -75,6 +75,27 @@ def rough_sphere(n: int, amplitude: float = 0.05, frequency: float = 40.0) -> np
     return np.ascontiguousarray(d * r[:, None])
 
 
+def graded_sphere(n: int, c: float = 0.25) -> np.ndarray:
+    """A locally refined sphere: the cube-sphere mapped by the conformal map
+    that scales the stereographic plane (projected from the south pole) by c.
+    For c < 1 the points crowd towards the north pole (0, 0, 1): the point
+    density there is 1/c^2 times the cube-sphere's, and c^2 times it at the
+    south pole, so box point counts vary by a factor of about 1/c^4 over the
+    surface (the uneven counts that an adaptive octree targets, Sec. 4)."""
+    d = cube_sphere(n)
+    den = 1.0 + d[:, 2]
+    south = den < 1e-12
+    w = np.zeros((d.shape[0], 2))
+    w[~south] = c * d[~south, :2] / den[~south, None]
+    q = (w * w).sum(axis=1)
+    out = np.empty_like(d)
+    out[:, 0] = 2.0 * w[:, 0] / (1.0 + q)
+    out[:, 1] = 2.0 * w[:, 1] / (1.0 + q)
+    out[:, 2] = (1.0 - q) / (1.0 + q)
+    out[south] = d[south]
+    return np.ascontiguousarray(out)
+
+
 @dataclass(frozen=True)
 class Workload:
     """One synthetic workload: geometry, wavenumber, batch and precision."""

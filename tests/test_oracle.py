@@ -446,3 +446,106 @@ def test_ifgf_gradient_on_lattice_pole_reading():
     # the x derivative on the axis is not trivially small: the theta term of
     # the reading carries it (dropping that term would fail the comparison)
     assert np.max(np.abs(g[:, 0])[okx]) > 1e-2 * scale
+
+
+# ------------------------------------------- adaptive octree (reading R16)
+
+def _adaptive_leaf_counts(p, H1, x1, D, leaf_max):
+    """Leaves per level of the adaptive tree, counted by brute force from the
+    box of every point on every level (the rule of the reading: a box of
+    level >= 2 with at most leaf_max points is not split)."""
+    corner = np.asarray(x1) - H1 / 2.0
+    leaves = [0] * (D + 1)
+    alive = np.ones(p.shape[0], bool)          # points still under a split box
+    for d in range(2, D + 1):
+        nb = 1 << (d - 1)
+        k = np.clip(np.floor((p - corner) / ldexp(H1, -(d - 1))), 0, nb - 1).astype(np.int64)
+        key = (k[:, 0] * nb + k[:, 1]) * nb + k[:, 2]
+        keys, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+        in_tree = np.zeros(keys.size, bool)
+        in_tree[inv[alive]] = True
+        leaf = in_tree & ((cnt <= leaf_max) | (d == D))
+        leaves[d] = int(leaf.sum())
+        alive &= ~leaf[inv]
+    return leaves
+
+
+@pytest.fixture(scope="module")
+def graded():
+    p = inputs.graded_sphere(18)
+    a = inputs.densities(1, 1, p.shape[0])
+    return p, a, 10.0
+
+
+def test_adaptive_all_leaves_on_level_two_is_direct(graded):
+    """leaf_max >= N makes every level-2 box a leaf: all pairs are then summed
+    directly (level-2 boxes all neighbour each other), so the result is the
+    direct sum to rounding."""
+    p, a, kappa = graded
+    r = oracle.ifgf(p, a, kappa, levels=5, leaf_max=p.shape[0])
+    assert rel(r["out"], oracle.direct(p, a, kappa)) < 1e-13
+    assert sum(r["stats"]["n_cones"]) == 0
+    assert r["stats"]["n_leaf_boxes"][2] == r["stats"]["n_boxes"][2]
+
+
+@pytest.mark.parametrize("leaf_max", [2, 6, 20, 60])
+def test_adaptive_pair_coverage_and_tree(graded, leaf_max):
+    """Every pair m != l is summed exactly once, directly or at one level,
+    whatever the leaf levels; the leaves per level follow the splitting rule
+    (brute-force count); leaves sit on several levels for this graded mesh."""
+    p, a, kappa = graded
+    N = p.shape[0]
+    st = oracle.ifgf(p, a, kappa, levels=6, leaf_max=leaf_max)["stats"]
+    assert st["n_near_pairs"] + sum(st["n_far_pairs"]) == N * (N - 1)
+    assert st["n_leaf_boxes"] == _adaptive_leaf_counts(p, st["H1"], st["x1"], st["D"], leaf_max)
+    assert sum(1 for x in st["n_leaf_boxes"] if x > 0) >= 2
+    # a box below a leaf is no source box: the source tree shrinks
+    assert sum(st["n_src_boxes"]) < sum(st["n_boxes"][1:])
+
+
+def test_adaptive_zero_is_the_uniform_tree(graded):
+    """leaf_max = 0 is the tree of Sec. 3.3.1: every leaf on level D."""
+    p, a, kappa = graded
+    st = oracle.ifgf(p, a, kappa, levels=5, leaf_max=0)["stats"]
+    assert st["n_leaf_boxes"][:5] == [0] * 5 and st["n_leaf_boxes"][5] == st["n_boxes"][5]
+    assert st["n_src_boxes"][1:] == st["n_boxes"][1:]
+
+
+@pytest.mark.parametrize("degrees,bound", [((3, 5), 2e-3), ((4, 6), 2e-4)])
+def test_adaptive_accuracy_and_order(graded, degrees, bound):
+    """The adaptive tree keeps the method's accuracy: its error against the
+    direct sum stays at the uniform tree's level (within 2x) and falls with
+    the interpolation order (Thm. errorestimatenested)."""
+    p, a, kappa = graded
+    d = oracle.direct(p, a, kappa)
+    e0 = rel(oracle.ifgf(p, a, kappa, levels=6, degrees=degrees)["out"], d)
+    for lm in (4, 24):
+        e = rel(oracle.ifgf(p, a, kappa, levels=6, degrees=degrees, leaf_max=lm)["out"], d)
+        assert e < bound and e < 2.0 * e0 + 1e-12
+
+
+def test_adaptive_single_source(graded):
+    """One non-zero density gives a_m G(x_l, x_m) at every target to the
+    interpolation accuracy, and nothing at x_m itself."""
+    p, _, kappa = graded
+    N = p.shape[0]
+    for m in (0, N // 2, N - 1):
+        a = np.zeros(N, complex)
+        a[m] = 0.5 + 1.0j
+        r = oracle.ifgf(p, a, kappa, levels=6, leaf_max=8)["out"][0]
+        assert rel(r, oracle.direct(p, a, kappa)[0]) < 3e-3
+        assert r[m] == 0.0
+
+
+def test_adaptive_distinct_targets_gradient_and_laplace(graded):
+    """Distinct targets (the splitting counts sources and targets together),
+    the target gradient, and kappa = 0, all against the direct sums."""
+    p, a, kappa = graded
+    t = inputs.random_box_points(500, 17, 1.8)
+    r = oracle.ifgf(p, a, kappa, levels=6, leaf_max=12, targets=t, grad=True)
+    assert rel(r["out"], oracle.direct(p, a, kappa, targets=t, skip=np.full(500, -1))) < 2e-3
+    assert rel(r["grad"], oracle.direct_grad(p, a, kappa, targets=t, skip=np.full(500, -1))) < 2e-2
+    g = oracle.ifgf(p, a, kappa, levels=6, leaf_max=12, grad=True)["grad"]
+    assert rel(g, oracle.direct_grad(p, a, kappa)) < 2e-2
+    r0 = oracle.ifgf(p, a, 0.0, levels=6, leaf_max=12)
+    assert rel(r0["out"], oracle.direct(p, a, 0.0)) < 1e-3
