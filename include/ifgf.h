@@ -100,6 +100,16 @@ typedef struct {
                                 used dropped.  Ignored while stage profiling
                                 is on.  0: launch eagerly                     */
     size_t workspace_limit;  /* device bytes the plan may allocate, 0: none  */
+    int32_t leaf_max;        /* adaptive octree (the remedy for uneven point
+                                counts per box named in Sec. 4 and Sec. 5):
+                                a box of level >= 2 holding at most leaf_max
+                                points (sources and distinct targets
+                                together) is a leaf and is not split; its
+                                sources reach the targets of its neighbour
+                                boxes directly on its own level and its
+                                relevant cones get their node values
+                                directly; boxes below it are no source boxes.
+                                0: every leaf on level D (Sec. 3.3.1)        */
 } ifgf_options;
 
 /* Per-level counts of a plan; entry d is level d (1-based). */
@@ -114,12 +124,13 @@ typedef struct {
     int32_t nc[IFGF_MAX_LEVELS + 1];         /* polar intervals n_{C,d}         */
     int64_t n_boxes[IFGF_MAX_LEVELS + 1];    /* relevant boxes |R_B^d|          */
     int64_t n_cones[IFGF_MAX_LEVELS + 1];    /* relevant cone segments |R_C^d|  */
-    int64_t n_cousin_boxes[IFGF_MAX_LEVELS + 1];  /* sum over boxes of |M B|    */
+    int64_t n_cousin_boxes[IFGF_MAX_LEVELS + 1];  /* sum over source boxes of |M B| */
     int64_t max_cousin_boxes[IFGF_MAX_LEVELS + 1];
     int64_t n_cousin_evals[IFGF_MAX_LEVELS + 1];  /* (target, cousin box) pairs */
     int64_t n_parent_evals[IFGF_MAX_LEVELS + 1];  /* (parent node, child) pairs
                                                      interpolated at level d   */
-    int64_t n_leaf_pairs;                    /* (cone node, source) pairs, d=D */
+    int64_t n_leaf_pairs;                    /* (cone node, source) pairs of the
+                                                leaf boxes of every level      */
     int64_t n_near_pairs;                    /* directly summed pairs           */
     int64_t n_dilated;                       /* cones marked only by dilation   */
     int64_t n_frames[IFGF_MAX_LEVELS + 1];   /* distinct child-to-parent frames
@@ -131,6 +142,9 @@ typedef struct {
     double t_plan_s;                         /* host seconds to build the plan  */
     int64_t n_sources;                       /* densities per right-hand side   */
     int64_t n_targets;                       /* outputs per right-hand side     */
+    int64_t n_src_boxes[IFGF_MAX_LEVELS + 1];  /* boxes of the source tree (all
+                                                relevant boxes unless adaptive) */
+    int64_t n_leaf_boxes[IFGF_MAX_LEVELS + 1]; /* its leaves on level d        */
 } ifgf_stats;
 
 /* Create a plan for the points (Sec. 3.3.2: box octree, relevant boxes,

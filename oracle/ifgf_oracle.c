@@ -23,8 +23,9 @@
  *       eq. factor_r's extra 1/(4 pi) is not used.
  *   R5  Cone refinement multiplies the interval counts going up the tree:
  *       n_{.,d-1} = a_d n_{.,d} with a_d = 2 iff 2 kappa H_d > 1 (Sec. 3.3.1).
- *   R6  Root box: centre = bounding-box midpoint, side = largest extent; box
- *       indices are clamped to the last box on the upper faces.
+ *   R6  Root box: centre = bounding-box midpoint, side = largest extent, the
+ *       box bounding the sources and any distinct targets; box indices are
+ *       clamped to the last box on the upper faces.
  *   R7  Cone index = the half-open interval of eq. (defconedomain) holding
  *       the coordinate: floor(coordinate / interval length), where a value
  *       within 1e-10 (in interval units) below a boundary counts as on it
@@ -550,7 +551,9 @@ int oracle_ifgf_ex(const double* pts, int64_t n, const double* dens, int32_t nrh
     const int P = ps * pang * pang;
     const double t_start = omp_get_wtime();   /* T_pre: the hierarchy below */
 
-    /* Root box B_1^1 containing Gamma_N (eq. deffirstbox; reading R6). */
+    /* Root box B_1^1 containing Gamma_N (eq. deffirstbox; reading R6): every
+     * point the operator involves, i.e. the sources and, when they are given
+     * apart, the targets as well. */
     double lo[3], hi[3];
     for (int c = 0; c < 3; ++c) lo[c] = hi[c] = pts[c];
     for (int64_t i = 1; i < n; ++i)
@@ -558,6 +561,12 @@ int oracle_ifgf_ex(const double* pts, int64_t n, const double* dens, int32_t nrh
             if (pts[3 * i + c] < lo[c]) lo[c] = pts[3 * i + c];
             if (pts[3 * i + c] > hi[c]) hi[c] = pts[3 * i + c];
         }
+    if (distinct_targets)
+        for (int64_t i = 0; i < m; ++i)
+            for (int c = 0; c < 3; ++c) {
+                if (tpos[3 * i + c] < lo[c]) lo[c] = tpos[3 * i + c];
+                if (tpos[3 * i + c] > hi[c]) hi[c] = tpos[3 * i + c];
+            }
     double x1[3], H1 = 0.0;
     for (int c = 0; c < 3; ++c) {
         x1[c] = 0.5 * (lo[c] + hi[c]);
@@ -1057,10 +1066,13 @@ int oracle_ifgf_ex(const double* pts, int64_t n, const double* dens, int32_t nrh
             stats->nc[d] = L[d].nc;
             stats->n_boxes[d] = L[d].nbox;
             stats->n_cones[d] = L[d].cone_off[L[d].nbox];
-            stats->n_cousin_boxes[d] = L[d].cou_off[L[d].nbox];
+            /* cousins of the source boxes (every box unless adaptive) */
             int64_t mx = 0;
-            for (int64_t b = 0; b < L[d].nbox; ++b)
+            for (int64_t b = 0; b < L[d].nbox; ++b) {
+                if (!L[d].active[b]) continue;
+                stats->n_cousin_boxes[d] += L[d].cou_off[b + 1] - L[d].cou_off[b];
                 if (L[d].cou_off[b + 1] - L[d].cou_off[b] > mx) mx = L[d].cou_off[b + 1] - L[d].cou_off[b];
+            }
             stats->max_cousin_boxes[d] = mx;
             stats->n_cousin_evals[d] = cousin_evals[d];
             stats->n_parent_evals[d] = parent_evals[d];

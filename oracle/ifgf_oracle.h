@@ -36,7 +36,8 @@ typedef struct {
     int32_t nc[ORACLE_MAX_LEVELS + 1];        /* polar intervals n_{C,d}     */
     int64_t n_boxes[ORACLE_MAX_LEVELS + 1];   /* relevant boxes |R_B^d|      */
     int64_t n_cones[ORACLE_MAX_LEVELS + 1];   /* relevant cones |R_C^d|      */
-    int64_t n_cousin_boxes[ORACLE_MAX_LEVELS + 1];  /* sum_k |M B_k|         */
+    int64_t n_cousin_boxes[ORACLE_MAX_LEVELS + 1];  /* sum_k |M B_k| over the
+                                                       source boxes          */
     int64_t max_cousin_boxes[ORACLE_MAX_LEVELS + 1];/* max_k |M B_k|         */
     int64_t n_cousin_evals[ORACLE_MAX_LEVELS + 1];  /* sum_k |V B_k ∩ targets|*/
     int64_t n_parent_evals[ORACLE_MAX_LEVELS + 1];  /* child->parent node evals*/

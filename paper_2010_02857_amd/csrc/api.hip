@@ -119,6 +119,17 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
         if (d == hp.D)
             if ((e = upload(p, H.nbr_start, &L.nbr_start)) != hipSuccess || (e = upload(p, H.nbr, &L.nbr)) != hipSuccess)
                 return e;
+        // adaptive octree: direct evaluations as point ranges (level D) and
+        // the slots of the leaf boxes above level D
+        if (hp.adaptive && d == hp.D) {
+            if ((e = upload(p, hp.near_start, &L.near_start)) != hipSuccess) return e;
+            if ((e = upload(p, hp.near_lo, &L.near_lo)) != hipSuccess) return e;
+            if ((e = upload(p, hp.near_hi, &L.near_hi)) != hipSuccess) return e;
+        }
+        if (hp.adaptive && d >= 3 && d < hp.D) {
+            L.nleaf_slots = (int)H.leaf_slots.size();
+            if ((e = upload(p, H.leaf_slots, &L.leaf_slots)) != hipSuccess) return e;
+        }
         if (interp_level) {
             if ((e = upload(p, H.box_oct, &L.box_oct)) != hipSuccess) return e;
             if ((e = upload(p, H.cou_start, &L.cou_start)) != hipSuccess) return e;
@@ -322,7 +333,7 @@ static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt,
         const bool on_gpu = !p.host_only && !(hv && std::atoi(hv) != 0);
         if (on_gpu) marker = ifgf::make_gpu_cone_marker();
         msg = ifgf::build_host_plan(points, n, k, levels, ps, pa, leaf_ns, leaf_nc, o.no_dilate == 0, pair_bytes,
-                                    ord_bytes, budget, p.hp, code, marker.get(), on_gpu);
+                                    ord_bytes, budget, p.hp, code, marker.get(), on_gpu, o.leaf_max);
     } catch (const std::bad_alloc&) {
         delete pl;
         return fail(IFGF_E_OUT_OF_MEMORY, "host allocation failed while building the plan");

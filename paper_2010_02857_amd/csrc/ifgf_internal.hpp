@@ -126,7 +126,14 @@ struct HostLevel {
     std::vector<int32_t> parent;              // [nbox] index at level d-1
     std::vector<int32_t> chl_start, chl;      // children (level d+1)
     std::vector<int32_t> nbr_start, nbr;      // neighbours incl. self
-    std::vector<int32_t> cou_start, cou;      // cousins
+    std::vector<int32_t> cou_start, cou;      // cousins that are source boxes (all of
+                                              // them unless the tree is adaptive)
+    // adaptive octree: the source tree (active boxes) and its leaves; the
+    // cousins of every active box, source boxes or not, for relevance rule
+    // (i) (empty when the tree is not adaptive: cou serves)
+    std::vector<uint8_t> active, leaf;        // [nbox]
+    std::vector<int32_t> mcou_start, mcou;
+    std::vector<int32_t> leaf_slots;          // slots of the leaf boxes (levels 3..D-1)
     // relevant cones
     std::vector<int32_t> cell_base;           // [nbox][ncell] first slot
     std::vector<uint64_t> cell_mask;          // [nbox][ncell][W]
@@ -196,6 +203,12 @@ struct HostPlan {
     std::vector<int32_t> perm;                // Morton position -> input index
     std::vector<double> pts;                  // [n][3] Morton order
     std::vector<HostLevel> L;                 // levels 0..D (0 unused)
+    // adaptive octree (leaf_max > 0): the direct evaluations of every level-D
+    // box as point ranges [near_lo, near_hi) of the leaves whose neighbourhood
+    // holds it, on their own levels
+    int leaf_max = 0;
+    bool adaptive = false;
+    std::vector<int32_t> near_start, near_lo, near_hi;
     ifgf_stats stats{};
 };
 
@@ -219,10 +232,12 @@ std::unique_ptr<ConeMarker> make_gpu_cone_marker();
 // marker: numbers the relevant cones (null: on the host).
 // pairs_device: the pair tables are left to build_pairs_device (only their
 // offsets pair_base are built here).
+// leaf_max: adaptive octree, boxes of level >= 2 with at most leaf_max points
+// are not split (0: every leaf on level D).
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
                             int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
                             double pair_budget, HostPlan& hp, ifgf_status& code, ConeMarker* marker = nullptr,
-                            bool pairs_device = false);
+                            bool pairs_device = false, int leaf_max = 0);
 
 // ---------------------------------------------------------- device mirror
 
@@ -239,6 +254,13 @@ struct LevelDev {
     const int32_t* nbr;
     const int32_t* cou_start;
     const int32_t* cou;
+    // adaptive octree: slots of this level's leaf boxes (levels 3..D-1), and
+    // on level D the direct evaluations as point ranges per box
+    int nleaf_slots;
+    const int32_t* leaf_slots;
+    const int32_t* near_start;
+    const int32_t* near_lo;
+    const int32_t* near_hi;
     const int32_t* cell_base;
     const unsigned long long* cell_mask;
     const int32_t* slot_box;

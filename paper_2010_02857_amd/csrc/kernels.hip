@@ -236,9 +236,26 @@ __global__ void __launch_bounds__(kBlock) k_permute_out(const cpx<T>* __restrict
     }
 }
 
-// Near field at the leaf level (Algorithm 1, direct evaluations onto the
-// neighbourhood U B): I(x_i) = sum over the neighbour boxes of x_i's leaf box
-// of a_j G(x_i, x_j), j != i.  Writes (initialises) the output.
+// The sources summed directly at the targets of level-D box b, as Morton
+// point ranges e in [near_first, near_end): the box's neighbours, or with an
+// adaptive octree the leaves (of any level) whose neighbourhood holds it.
+__device__ inline int near_first(const LevelDev& L, int b) { return L.near_start ? L.near_start[b] : L.nbr_start[b]; }
+__device__ inline int near_end(const LevelDev& L, int b) { return L.near_start ? L.near_start[b + 1] : L.nbr_start[b + 1]; }
+__device__ inline void near_range(const LevelDev& L, int e, int& lo, int& hi)
+{
+    if (L.near_start) {
+        lo = L.near_lo[e];
+        hi = L.near_hi[e];
+    } else {
+        const int q = L.nbr[e];
+        lo = L.box_start[q];
+        hi = L.box_start[q + 1];
+    }
+}
+
+// Near field (Algorithm 1, direct evaluations onto the neighbourhood U B):
+// I(x_i) = sum over the neighbour boxes of x_i's leaf box of a_j G(x_i, x_j),
+// j != i.  Writes (initialises) the output.
 template <typename T, int RB>
 __global__ void __launch_bounds__(kBlock) k_nearfield(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
                                                       const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ out)
@@ -250,9 +267,11 @@ __global__ void __launch_bounds__(kBlock) k_nearfield(KernelConsts kc, LevelDev 
     cpx<T> acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
-    for (int qi = L.nbr_start[b]; qi < L.nbr_start[b + 1]; ++qi) {
-        const int q = L.nbr[qi];
-        for (int j = L.box_start[q]; j < L.box_start[q + 1]; ++j) {
+    const int e1 = near_end(L, b);
+    for (int e = near_first(L, b); e < e1; ++e) {
+        int lo, hi;
+        near_range(L, e, lo, hi);
+        for (int j = lo; j < hi; ++j) {
             if (j == i) continue;
             double dx = x0 - pts[3 * j], dy = x1 - pts[3 * j + 1], dz = x2 - pts[3 * j + 2];
             double rr = sqrt(dx * dx + dy * dy + dz * dz);
@@ -272,19 +291,22 @@ __global__ void __launch_bounds__(kBlock) k_nearfield(KernelConsts kc, LevelDev 
     for (int r = 0; r < RB; ++r) out[(size_t)i * RB + r] = acc[r];
 }
 
-// Leaf level: F_k^D at every interpolation point of every relevant leaf cone
-// (eq. I_k): F(x) = sum_{m in B_k} a_m |x - c| / |x - x_m| e^{i k (|x - x_m| - |x - c|)},
+// Leaf boxes: F_k at every interpolation point of every relevant cone of a
+// leaf box (eq. I_k): F(x) = sum_{m in B_k} a_m |x - c| / |x - x_m| e^{i k (|x - x_m| - |x - c|)},
 // the difference of radii formed as (|w|^2 - 2 y.w) / (|y - w| + |y|) with
-// y = x - c, w = x_m - c.
+// y = x - c, w = x_m - c.  Every slot of level D (list null), or the slots
+// list[0..nlist) of the leaf boxes of a coarser level (adaptive octree).
 template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_leaf_nodes(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
-                                                       const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ F)
+                                                       const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ F,
+                                                       const int32_t* __restrict__ list, int nlist)
 {
     constexpr int P = PS * PA * PA;
     size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     int slot = (int)(gid / P);
     int nu = (int)(gid - (size_t)slot * P);
-    if (slot >= L.nslots) return;
+    if (slot >= (list ? nlist : L.nslots)) return;
+    if (list) slot = list[slot];
     const int b = L.slot_box[slot];
     const int cone = L.slot_cone[slot];
     const int cell = cone / L.ns, is = cone - cell * L.ns;
@@ -713,6 +735,7 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, Lev
     for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = (T)0;
     for (int k = Lp.chl_start[j]; k < Lp.chl_start[j + 1]; ++k) {
         const int oct = Lc.box_oct[k];
+        if (Lc.child_of[(size_t)j * 8 + oct] != k) continue;   // below a leaf (adaptive octree)
         double o[3] = {(oct & 1) ? half : -half, (oct & 2) ? half : -half, (oct & 4) ? half : -half};
         double v[3];
         node_minus(rr, dir, o, v);
@@ -2294,9 +2317,11 @@ __global__ void __launch_bounds__(kBlock) k_near_grad(KernelConsts kc, LevelDev 
 #pragma unroll
     for (int r = 0; r < RB; ++r) g[r] = gout[(size_t)i * RB + r];
     double acc0 = 0, acc1 = 0, acc2 = 0;
-    for (int qi = L.nbr_start[b]; qi < L.nbr_start[b + 1]; ++qi) {
-        const int q = L.nbr[qi];
-        for (int j = L.box_start[q]; j < L.box_start[q + 1]; ++j) {
+    const int e1 = near_end(L, b);
+    for (int e = near_first(L, b); e < e1; ++e) {
+        int lo, hi;
+        near_range(L, e, lo, hi);
+        for (int j = lo; j < hi; ++j) {
             if (j == i) continue;
             double dx = x0 - pts[3 * j], dy = x1 - pts[3 * j + 1], dz = x2 - pts[3 * j + 2];
             double rr = sqrt(dx * dx + dy * dy + dz * dz);
@@ -2757,6 +2782,10 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
     const HostPlan& hp = p.hp;
     const int n = (int)hp.n;
     using C = cpx<T>;
+    // nothing to interpolate: no source box of this level has cones, or no
+    // target has a cousin that is a source box (an adaptive octree can leave
+    // whole levels without source boxes)
+    if (hp.L[d].nslots == 0 || p.npairs_all[d] == 0) return;
     if (grad) {
         StageTimer tm_(p, IFGF_STAGE_COUSIN_GRAD, st, d);
         k_cousin_grad<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
@@ -2831,7 +2860,7 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
         {
             StageTimer tm_(p, IFGF_STAGE_LEAF_NODES, st, D);
             k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
-                kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
+                kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D], nullptr, 0);
         }
     hipError_t e;
     if (two && (e = hipEventRecord(ev_ready(p, D), st)) != hipSuccess) return e;
@@ -2849,8 +2878,19 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
                             if ((e = hipStreamWaitEvent(st, ev_read(p, dd), 0)) != hipSuccess) return e;
                             break;
                         }
-                StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st, d);
-                c2p_launch<T, PS, PA, RB>(p, kc, d, c2p_variant<T, PS, PA, RB>(p, d), st);
+                {
+                    StageTimer tm_(p, IFGF_STAGE_CHILD_TO_PARENT, st, d);
+                    c2p_launch<T, PS, PA, RB>(p, kc, d, c2p_variant<T, PS, PA, RB>(p, d), st);
+                }
+                // adaptive octree: the leaf boxes of level d - 1 have no
+                // children; their cone values come from their own sources
+                // (over the zeros the step above left in their slots)
+                const LevelDev& Lq = p.L[d - 1];
+                if (Lq.nleaf_slots > 0) {
+                    StageTimer tm_(p, IFGF_STAGE_LEAF_NODES, st, d - 1);
+                    k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)Lq.nleaf_slots * P), kBlock, 0, st>>>(
+                        kc, Lq, p.pts, (const C*)p.dens_m, (C*)p.F[d - 1], Lq.leaf_slots, Lq.nleaf_slots);
+                }
             }
         if (two && d > 3 && (e = hipEventRecord(ev_ready(p, d - 1), st)) != hipSuccess) return e;
     }
@@ -3090,7 +3130,7 @@ hipError_t autotune_t(DevicePlan& p, hipStream_t st)
     if ((e = hipMemsetAsync(p.dens_m, 0, (size_t)hp.n * RB * sizeof(C), st)) != hipSuccess) return e;
     if (hp.L[D].nslots > 0)
         k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
-            kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D]);
+            kc, p.L[D], p.pts, (const C*)p.dens_m, (C*)p.F[D], nullptr, 0);
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&e1)) != hipSuccess) {

@@ -284,7 +284,8 @@ void build_frames(HostPlan& hp, int d)
     const HostLevel& Lp = hp.L[d - 1];
     const int P = hp.P, ps = hp.ps, pang = hp.pang;
     L.child_of.assign((size_t)Lp.nbox * 8, -1);
-    for (int64_t k = 0; k < L.nbox; ++k) L.child_of[(size_t)L.parent[k] * 8 + L.box_oct[k]] = (int32_t)k;
+    for (int64_t k = 0; k < L.nbox; ++k)
+        if (L.active[k]) L.child_of[(size_t)L.parent[k] * 8 + L.box_oct[k]] = (int32_t)k;
     std::vector<uint64_t> keys;
     keys.reserve((size_t)Lp.nslots * 4);
     for (int64_t sl = 0; sl < Lp.nslots; ++sl) {
@@ -593,7 +594,7 @@ void build_tile_entries(HostPlan& hp, int d)
 std::string build_host_plan(const double* points, int64_t n, double kappa, int levels, int ps, int pang,
                             int leaf_ns, int leaf_nc, bool dilate, double tab_elem_bytes, double ord_elem_bytes,
                             double pair_budget, HostPlan& hp, ifgf_status& code, ConeMarker* marker,
-                            bool pairs_device)
+                            bool pairs_device, int leaf_max)
 {
     auto t0 = std::chrono::steady_clock::now();
     g_clock.start();
@@ -606,6 +607,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
     if (levels < 0 || levels > 22) return "levels must be 0 (auto) or 2..22";
     if (levels == 1) return "levels must be 0 (auto) or 2..22";
     if (leaf_ns < 1 || leaf_nc < 1 || leaf_ns > 64 || leaf_nc > 64) return "leaf cone counts out of range";
+    if (leaf_max < 0) return "leaf_max must be >= 0";
     for (int64_t i = 0; i < 3 * n; ++i)
         if (!std::isfinite(points[i])) return "points must be finite";
 
@@ -754,6 +756,29 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         }
     }
 
+    // The source tree (adaptive octree): the root is split; below it a box is
+    // active when its parent is active and not a leaf, and an active box is a
+    // leaf on level D or when it holds at most leaf_max points.
+    hp.leaf_max = leaf_max;
+    hp.adaptive = false;
+    for (int d = 1; d <= D; ++d) {
+        HostLevel& L = hp.L[d];
+        L.active.assign(L.nbox, 0);
+        L.leaf.assign(L.nbox, 0);
+        for (int64_t b = 0; b < L.nbox; ++b) {
+            if (d == 1) {
+                L.active[b] = 1;
+                continue;
+            }
+            const HostLevel& Lp = hp.L[d - 1];
+            const int32_t p = L.parent[b];
+            L.active[b] = Lp.active[p] && !Lp.leaf[p];
+            const int64_t cnt = L.box_start[b + 1] - L.box_start[b];
+            L.leaf[b] = L.active[b] && (d == D || (leaf_max > 0 && cnt <= leaf_max));
+            if (L.leaf[b] && d < D) hp.adaptive = true;
+        }
+    }
+
     phase("parents and children");
     // Neighbours (|a - k|_inf <= 1, self included) on every level.
     for (int d = 1; d <= D; ++d) {
@@ -806,6 +831,20 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                 }
             }
         }, 64);
+        if (hp.adaptive) {
+            // rule (i) of an active box reads all its cousins; the evaluation
+            // at the targets of a box reads its cousins that are source boxes
+            L.mcou_start.assign(L.nbox + 1, 0);
+            for (int64_t b = 0; b < L.nbox; ++b)
+                L.mcou_start[b + 1] = L.mcou_start[b] + (L.active[b] ? (int32_t)lists[b].size() : 0);
+            L.mcou.resize(L.mcou_start[L.nbox]);
+            for (int64_t b = 0; b < L.nbox; ++b)
+                if (L.active[b]) std::copy(lists[b].begin(), lists[b].end(), &L.mcou[L.mcou_start[b]]);
+            for (int64_t b = 0; b < L.nbox; ++b) {
+                auto& v = lists[b];
+                v.erase(std::remove_if(v.begin(), v.end(), [&](int32_t c) { return !L.active[c]; }), v.end());
+            }
+        }
         for (int64_t b = 0; b < L.nbox; ++b) L.cou_start[b + 1] = L.cou_start[b] + (int32_t)lists[b].size();
         L.cou.resize(L.cou_start[L.nbox]);
         for (int64_t b = 0; b < L.nbox; ++b) std::copy(lists[b].begin(), lists[b].end(), &L.cou[L.cou_start[b]]);
@@ -899,10 +938,13 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
             phase("  relevant cones on the GPU (level)");
             continue;
         }
+        const std::vector<int32_t>& mst = hp.adaptive ? L.mcou_start : L.cou_start;
+        const std::vector<int32_t>& mco = hp.adaptive ? L.mcou : L.cou;
         parallel_for(L.nbox, [&](int64_t b) {
+            if (!L.active[b]) return;   // not a source box: no cones
             const double* ctr = &L.box_ctr[3 * b];
-            for (int32_t ci = L.cou_start[b]; ci < L.cou_start[b + 1]; ++ci) {
-                int32_t c = L.cou[ci];
+            for (int32_t ci = mst[b]; ci < mst[b + 1]; ++ci) {
+                int32_t c = mco[ci];
                 for (int32_t j = L.box_start[c]; j < L.box_start[c + 1]; ++j) {
                     ConeLoc cl;
                     cone_locate(hp.pts[3 * j] - ctr[0], hp.pts[3 * j + 1] - ctr[1], hp.pts[3 * j + 2] - ctr[2], L.h,
@@ -1002,6 +1044,51 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         HostLevel& L = hp.L[d];
         L.slot_start.assign(L.nbox + 1, 0);
     }
+    // adaptive octree: the slots of the leaf boxes above level D, and the
+    // direct evaluations of every level-D box: the points of each leaf q (on
+    // its own level d) that neighbours the box's level-d ancestor
+    if (hp.adaptive) {
+        for (int d = 3; d < D; ++d) {
+            HostLevel& L = hp.L[d];
+            for (int64_t b = 0; b < L.nbox; ++b)
+                if (L.leaf[b])
+                    for (int32_t sl = L.slot_start[b]; sl < L.slot_start[b + 1]; ++sl) L.leaf_slots.push_back(sl);
+        }
+        const HostLevel& LD = hp.L[D];
+        std::vector<std::vector<int32_t>> rng(LD.nbox);
+        parallel_for(LD.nbox, [&](int64_t T) {
+            int32_t a = (int32_t)T;
+            std::vector<int32_t> anc(D + 1, -1);
+            for (int d = D; d >= 2; --d) {
+                anc[d] = a;
+                a = hp.L[d].parent[a];
+            }
+            for (int d = 2; d <= D; ++d) {
+                const HostLevel& L = hp.L[d];
+                for (int32_t qi = L.nbr_start[anc[d]]; qi < L.nbr_start[anc[d] + 1]; ++qi) {
+                    const int32_t q = L.nbr[qi];
+                    if (!L.leaf[q]) continue;
+                    rng[T].push_back(L.box_start[q]);
+                    rng[T].push_back(L.box_start[q + 1]);
+                }
+            }
+        }, 256);
+        hp.near_start.assign(LD.nbox + 1, 0);
+        for (int64_t T = 0; T < LD.nbox; ++T) {
+            if ((int64_t)hp.near_start[T] + (int64_t)rng[T].size() / 2 > INT32_MAX) {
+                code = IFGF_E_UNSUPPORTED;
+                return "too many direct-evaluation ranges";
+            }
+            hp.near_start[T + 1] = hp.near_start[T] + (int32_t)(rng[T].size() / 2);
+        }
+        hp.near_lo.resize(hp.near_start[LD.nbox]);
+        hp.near_hi.resize(hp.near_start[LD.nbox]);
+        for (int64_t T = 0; T < LD.nbox; ++T)
+            for (size_t e = 0; e < rng[T].size() / 2; ++e) {
+                hp.near_lo[hp.near_start[T] + e] = rng[T][2 * e];
+                hp.near_hi[hp.near_start[T] + e] = rng[T][2 * e + 1];
+            }
+    }
     for (int d = 4; d <= D; ++d)
         if (hp.L[d].use_frames && hp.L[d].frame_groups_ok && hp.L[d].ntiles > 0) build_tile_entries(hp, d);
     phase("box tile entries");
@@ -1050,12 +1137,18 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         st.nc[d] = L.nc;
         st.n_boxes[d] = L.nbox;
         st.n_cones[d] = L.nslots;
-        st.n_cousin_boxes[d] = L.cou_start[L.nbox];
-        int64_t mx = 0, ce = 0, pe = 0;
+        // cousins of the source boxes and the targets in them
+        const std::vector<int32_t>& mst = hp.adaptive ? L.mcou_start : L.cou_start;
+        const std::vector<int32_t>& mco = hp.adaptive ? L.mcou : L.cou;
+        int64_t mx = 0, ce = 0, pe = 0, nc = 0;
         for (int64_t b = 0; b < L.nbox; ++b) {
-            mx = std::max<int64_t>(mx, L.cou_start[b + 1] - L.cou_start[b]);
-            for (int32_t ci = L.cou_start[b]; ci < L.cou_start[b + 1]; ++ci) {
-                int32_t c = L.cou[ci];
+            st.n_src_boxes[d] += L.active[b];
+            st.n_leaf_boxes[d] += L.leaf[b];
+            if (!L.active[b] || mst.empty()) continue;
+            nc += mst[b + 1] - mst[b];
+            mx = std::max<int64_t>(mx, mst[b + 1] - mst[b]);
+            for (int32_t ci = mst[b]; ci < mst[b + 1]; ++ci) {
+                int32_t c = mco[ci];
                 ce += L.box_start[c + 1] - L.box_start[c];
             }
             if (d >= 4) {
@@ -1063,6 +1156,7 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                 pe += (int64_t)(hp.L[d - 1].slot_start[p + 1] - hp.L[d - 1].slot_start[p]) * hp.P;
             }
         }
+        st.n_cousin_boxes[d] = nc;
         st.max_cousin_boxes[d] = mx;
         st.n_cousin_evals[d] = ce;
         st.n_parent_evals[d] = pe;
@@ -1070,11 +1164,20 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         st.pairs_tabulated[d] = L.use_pairs ? 1 : 0;
     }
     {
-        const HostLevel& L = hp.L[D];
         int64_t leaf = 0, nearp = 0;
+        for (int d = 3; d <= D; ++d) {
+            const HostLevel& L = hp.L[d];
+            for (int64_t b = 0; b < L.nbox; ++b)
+                if (L.leaf[b])
+                    leaf += (int64_t)(L.slot_start[b + 1] - L.slot_start[b]) * hp.P * (L.box_start[b + 1] - L.box_start[b]);
+        }
+        const HostLevel& L = hp.L[D];
         for (int64_t b = 0; b < L.nbox; ++b) {
             int64_t nb = L.box_start[b + 1] - L.box_start[b];
-            leaf += (int64_t)(L.slot_start[b + 1] - L.slot_start[b]) * hp.P * nb;
+            if (hp.adaptive) {
+                for (int32_t e = hp.near_start[b]; e < hp.near_start[b + 1]; ++e) nearp += nb * (hp.near_hi[e] - hp.near_lo[e]);
+                continue;
+            }
             for (int32_t qi = L.nbr_start[b]; qi < L.nbr_start[b + 1]; ++qi) {
                 int32_t q = L.nbr[qi];
                 nearp += nb * (L.box_start[q + 1] - L.box_start[q]);

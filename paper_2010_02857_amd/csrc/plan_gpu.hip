@@ -300,9 +300,12 @@ class GpuConeMarker : public ConeMarker {
         // rule (i)
         IFGF_TRY(box_start_.put(L.box_start));
         IFGF_TRY(box_ctr_.put(L.box_ctr));
-        IFGF_TRY(cou_start_.put(L.cou_start));
-        IFGF_TRY(cou_.put(L.cou));
-        const int64_t ncou = L.cou_start[L.nbox];
+        // every cousin of the source boxes (adaptive octree: cou holds only
+        // the cousins that are source boxes themselves)
+        const std::vector<int32_t>& mst = hp.adaptive ? L.mcou_start : L.cou_start;
+        IFGF_TRY(cou_start_.put(mst));
+        IFGF_TRY(cou_.put(hp.adaptive ? L.mcou : L.cou));
+        const int64_t ncou = mst[L.nbox];
         if (ncou > 0)
             k_mark_cousin_points<<<blocks_for(ncou), kPB>>>(M, (int)L.nbox, ncou, cou_start_.as<int32_t>(),
                                                             cou_.as<int32_t>(), box_start_.as<int32_t>(),
@@ -314,7 +317,7 @@ class GpuConeMarker : public ConeMarker {
             std::vector<int64_t> off(L.nbox + 1, 0);
             for (int64_t b = 0; b < L.nbox; ++b) {
                 const int32_t p = L.parent[b];
-                off[b + 1] = off[b] + (Lp.slot_start[p + 1] - Lp.slot_start[p]);
+                off[b + 1] = off[b] + (L.active[b] ? Lp.slot_start[p + 1] - Lp.slot_start[p] : 0);
             }
             const int64_t total = off[L.nbox] * hp.P;
             IFGF_TRY(off_.put(off));

@@ -42,6 +42,7 @@ class Options(ctypes.Structure):
         ("no_dilate", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("workspace_limit", ctypes.c_size_t),
+        ("leaf_max", ctypes.c_int32),
     ]
 
 
@@ -74,6 +75,8 @@ class Stats(ctypes.Structure):
         ("t_plan_s", ctypes.c_double),
         ("n_sources", ctypes.c_int64),
         ("n_targets", ctypes.c_int64),
+        ("n_src_boxes", ctypes.c_int64 * _L),
+        ("n_leaf_boxes", ctypes.c_int64 * _L),
     ]
 
 
@@ -145,12 +148,14 @@ class Plan:
     degrees    (P_s, P_ang) Chebyshev nodes per cone direction.
     precision  "fp64" (complex128 I/O) or "mixed" (complex64 I/O).
     use_graph  capture apply calls into HIP graphs and replay them.
+    leaf_max   adaptive octree: boxes holding at most leaf_max points are not
+               split (0: every leaf on level D).
     """
 
     def __init__(self, points, k: float, levels: int = 0, degrees=(3, 5), precision: str = "fp64",
                  leaf=(1, 2), max_nrhs: int = 16, store_levels: int = -1, host_only: bool = False,
                  dilate: bool = True, workspace_limit: int = 0, use_graph: bool = False, targets=None,
-                 device=None):
+                 device=None, leaf_max: int = 0):
         def host(x):
             if hasattr(x, "detach"):
                 x = x.detach().cpu().numpy()
@@ -166,7 +171,7 @@ class Plan:
             raise ValueError("precision must be 'fp64' or 'mixed'")
         opt = Options(int(leaf[0]), int(leaf[1]), FP64 if precision == "fp64" else MIXED, int(max_nrhs),
                       int(store_levels), 1 if host_only else 0, 0 if dilate else 1, 1 if use_graph else 0,
-                      int(workspace_limit))
+                      int(workspace_limit), int(leaf_max))
         deg = (ctypes.c_int32 * 2)(int(degrees[0]), int(degrees[1]))
         h = ctypes.c_void_p()
         self._h = None
@@ -214,7 +219,7 @@ class Plan:
                "n_dilated": st.n_dilated, "device_bytes": st.device_bytes, "t_plan_s": st.t_plan_s,
                "n_sources": st.n_sources, "n_targets": st.n_targets}
         for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
-                    "n_parent_evals", "n_frames", "pairs_tabulated"):
+                    "n_parent_evals", "n_frames", "pairs_tabulated", "n_src_boxes", "n_leaf_boxes"):
             arr = getattr(st, key)
             out[key] = [int(arr[d]) for d in range(D + 1)]
         return out

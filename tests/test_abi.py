@@ -25,7 +25,8 @@ def test_status_strings():
         assert lib.ifgf_status_string(code).decode() == name
 
 
-@pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46", "lattice"])
+@pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46", "lattice", "adaptive6",
+                                  "adaptive60"])
 def test_host_plan_matches_oracle_counts(case):
     """Relevant boxes, cousins, relevant cones, child-to-parent and near-field
     work per level equal those of the CPU oracle (Sec. 3.3.2)."""
@@ -43,6 +44,12 @@ def test_host_plan_matches_oracle_counts(case):
         # points on box faces and cone faces and on the polar axes of box centres
         p, k = inputs.lattice(17), 8.0
         kw = okw = {"levels": 4}
+    elif case.startswith("adaptive"):
+        # graded mesh, adaptive octree: leaves on several levels
+        p, k = inputs.graded_sphere(18), 10.0
+        lm = 60 if case == "adaptive60" else 6
+        kw = {"levels": 6, "leaf_max": lm}
+        okw = {"levels": 6, "leaf_max": lm}
     elif case == "leaf23":
         p, k = inputs.cube_sphere(20, 0.25), 15.0
         kw = {"leaf": (2, 3)}
@@ -56,10 +63,26 @@ def test_host_plan_matches_oracle_counts(case):
     so = oracle.ifgf(p, inputs.densities(1, 1, p.shape[0]), k, **okw)["stats"]
     assert st["D"] == so["D"]
     for key in ("ns", "nc", "n_boxes", "n_cones", "n_cousin_boxes", "max_cousin_boxes", "n_cousin_evals",
-                "n_parent_evals"):
+                "n_parent_evals", "n_src_boxes", "n_leaf_boxes"):
         assert st[key] == so[key], key
     assert st["n_near_pairs"] == so["n_near_pairs"]
     assert abs(st["H1"] - so["H1"]) == 0.0
+
+
+def test_adaptive_tree_counts_sources_and_targets():
+    """With distinct targets the adaptive octree's splitting rule counts
+    sources and targets together, as the oracle does; leaf_max < 0 is
+    rejected."""
+    src = inputs.graded_sphere(12)
+    tgt = inputs.random_box_points(400, 3, 1.9)
+    st = ifgf.Plan(src, 8.0, levels=5, host_only=True, targets=tgt, leaf_max=10).stats()
+    so = oracle.ifgf(src, inputs.densities(1, 1, src.shape[0]), 8.0, levels=5, targets=tgt,
+                     leaf_max=10)["stats"]
+    assert st["n_leaf_boxes"] == so["n_leaf_boxes"] and st["n_src_boxes"] == so["n_src_boxes"]
+    assert sum(st["n_leaf_boxes"][:5]) > 0
+    with pytest.raises(ifgf.IFGFError) as e:
+        ifgf.Plan(src, 8.0, host_only=True, leaf_max=-1)
+    assert e.value.status == 1
 
 
 def test_auto_levels_quarter_wavelength():
