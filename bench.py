@@ -555,6 +555,7 @@ def main() -> int:
         del pm, xm
         torch.cuda.empty_cache()
         result["sphere393216"] = sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log)
+        result["graded_adaptive"] = graded_adaptive_extras(torch, ifgf, inputs, oracle, time_fn, log)
 
     # ---- the oracle on the host cores: the O1 direct sum above, on M of the
     # N targets, extrapolated to one full matvec of all right-hand sides
@@ -613,6 +614,16 @@ def sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log) -> dict:
     res["mixed_16rhs_matvecs_per_s"] = round(16 * 1000.0 / ms16, 3)
     res["roofline_16rhs"] = roofline_of(st, s16, l16, plan.kernel_choice(16), 16, 4, 75, 8, False, None)
     res["stage_ms_16rhs"] = {k: round(v[0] / 4, 3) for k, v in s16.items() if v[1]}
+    # the same stages with every kernel on one stream: the times above overlap
+    # (the cousin stage shares the GPU with the child-to-parent chain)
+    os.environ["IFGF_SIDE_STREAM"] = "0"
+    plan.profile(True)
+    ms16s = time_fn(lambda: plan.apply(x16), 3)
+    s16s = plan.stage_times()
+    plan.profile(False)
+    del os.environ["IFGF_SIDE_STREAM"]
+    res["mixed_16rhs_one_stream_matvecs_per_s"] = round(16 * 1000.0 / ms16s, 3)
+    res["stage_ms_16rhs_one_stream"] = {k: round(v[0] / 4, 3) for k, v in s16s.items() if v[1]}
     del plan
     torch.cuda.empty_cache()
     gplan = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=1, store_levels=0, use_graph=True)
@@ -632,6 +643,41 @@ def sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log) -> dict:
     del p64
     torch.cuda.empty_cache()
     log(f"sphere393216: {res}")
+    return res
+
+
+def graded_adaptive_extras(torch, ifgf, inputs, oracle, time_fn, log) -> dict:
+    """The adaptive octree on a locally refined mesh: the graded sphere (N =
+    393216, point density 16x the mean near one pole and 1/16 of it at the
+    other), kappa = 32 pi, mixed, 1 RHS.  Uniform trees of 8 levels (leaf
+    boxes about a quarter wavelength) and 9 levels against adaptive trees of
+    at most 9 levels; rate, eps on 1000 targets, plan time and bytes."""
+    kappa = 32.0 * math.pi
+    p = inputs.graded_sphere(256)
+    n = p.shape[0]
+    a = inputs.densities(6, 1, n)
+    x = torch.from_numpy(a).to(torch.complex64).cuda()
+    idx = inputs.error_subset(6, n, 1000)
+    d = oracle.direct(p, a, kappa, targets=p[idx], skip=idx)
+    res = {"points": "graded sphere c = 0.25", "n": n, "kappa": kappa, "precision": "mixed", "nrhs": 1}
+    for name, levels, lm in (("uniform_D8", 8, 0), ("adaptive_D8_leaf8", 8, 8), ("adaptive_D8_leaf24", 8, 24),
+                             ("uniform_D9", 9, 0), ("adaptive_D9_leaf16", 9, 16)):
+        t0 = time.time()
+        plan = ifgf.Plan(p, kappa, levels=levels, precision="mixed", max_nrhs=1, store_levels=0, leaf_max=lm)
+        t_plan = time.time() - t0
+        st = plan.stats()
+        plan.autotune(1)
+        ms = time_fn(lambda: plan.apply(x), 10)
+        out = plan.apply(x).cpu().numpy()
+        res[name] = {"levels": levels, "leaf_max": lm, "matvecs_per_s": round(1000.0 / ms, 3),
+                     "ms_per_matvec": round(ms, 3), "t_plan_s": round(t_plan, 2),
+                     "eps_vs_direct": float(np.linalg.norm(out[:, idx] - d) / np.linalg.norm(d)),
+                     "plan_device_bytes": st["device_bytes"], "cones": sum(st["n_cones"]),
+                     "leaf_boxes": st["n_leaf_boxes"][2:], "near_pairs": st["n_near_pairs"],
+                     "misses": plan.misses()}
+        del plan
+        torch.cuda.empty_cache()
+    log(f"graded adaptive: {res}")
     return res
 
 

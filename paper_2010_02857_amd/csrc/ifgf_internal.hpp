@@ -19,7 +19,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxNodes = 8;       // Chebyshev nodes per direction, upper bound
 constexpr int kMaxRhsPass = 16;    // right-hand sides handled by one kernel pass
 constexpr double kDilateTol = 1e-9;
-constexpr int kMaxFrameGroups = 32;  // distinct child cones one frame may touch
+constexpr int kMaxFrameGroups = 40;  // distinct child cones one frame may touch
 constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone per box tile
 constexpr int kPairQuad = 4;        // cone-ordered cousin pairs share a cone in runs of this length
 // child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)

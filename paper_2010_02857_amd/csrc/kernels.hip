@@ -1669,7 +1669,7 @@ k_child_to_parent_quads(KernelConsts kc, LevelDev Lc, LevelDev Lp,
 // entries is read in one step; the B operands of the next entry and the
 // points of the next octant are loaded while the current tiles run.  Each
 // parent slot is written by exactly one wavefront.
-constexpr int kBoxMaxEnt = 32;    // (octant, group) entries read at once
+constexpr int kBoxMaxEnt = 40;    // (octant, group) entries read at once
 
 template <int PS, int PA, int RB>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
@@ -1952,10 +1952,13 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
 // registers, and the epilogue multiplies every raw result by its point's
 // ratio and adds it to the pass's values in LDS (each (point, column)
 // belongs to one lane of one tile in an octant, so there are no races).
-// Without the raw-result and weight staging, FP64 fits in registers and
-// LDS at two waves per SIMD, FP32 at three.
+// Without the raw-result and weight staging, FP64 fits in registers at two
+// waves per SIMD (its LDS allows six waves per CU), FP32 at three.  The next
+// live octant's frame is loaded while the current one runs, and an entry's
+// B operands are loaded when the entry starts (a second operand set, loaded
+// one entry ahead, measured slower for both types).
 template <typename T, int PS, int PA, int RB>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* __restrict__ Fc,
                          cpx<T>* __restrict__ Fp, const cpx<T>* __restrict__ zero_cone)
 {
@@ -2066,18 +2069,45 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
                 ecs[i] = cs;
             }
             wave_lds_fence();
-            for (int o = o0; o < o1; ++o) {
-                if (!live(o)) continue;
-                // the octant's frame: coordinates and ratio of every point
+            // the frames of the chunk's live octants, one ahead in registers
+            constexpr int RPL = (P + 63) / 64;
+            T fq[RPL][5];
+            auto load_frame = [&](int o) {
                 const int f = sfr[o];
-                for (int nu = lane; nu < P; nu += 64) {
-                    const size_t e = (size_t)f * P + nu;
-                    rt[0][nu] = frt[3 * e];
-                    rt[1][nu] = frt[3 * e + 1];
-                    rt[2][nu] = frt[3 * e + 2];
-                    rg[0][nu] = frr[2 * e];
-                    rg[1][nu] = conj_sign * frr[2 * e + 1];
+#pragma unroll
+                for (int h = 0; h < RPL; ++h) {
+                    const int nu = lane + 64 * h;
+                    const size_t e = (size_t)f * P + (nu < P ? nu : 0);
+                    fq[h][0] = frt[3 * e];
+                    fq[h][1] = frt[3 * e + 1];
+                    fq[h][2] = frt[3 * e + 2];
+                    fq[h][3] = frr[2 * e];
+                    fq[h][4] = conj_sign * frr[2 * e + 1];
                 }
+            };
+            auto next_live = [&](int o) {
+                while (o < o1 && !live(o)) ++o;
+                return o;
+            };
+            int on = next_live(o0);
+            if (on < o1) load_frame(on);
+            while (on < o1) {
+                const int o = on;
+                // the octant's frame (loaded one octant ahead): coordinates and
+                // ratio of every point
+#pragma unroll
+                for (int h = 0; h < RPL; ++h) {
+                    const int nu = lane + 64 * h;
+                    if (nu < P) {
+                        rt[0][nu] = fq[h][0];
+                        rt[1][nu] = fq[h][1];
+                        rt[2][nu] = fq[h][2];
+                        rg[0][nu] = fq[h][3];
+                        rg[1][nu] = fq[h][4];
+                    }
+                }
+                on = next_live(o + 1);
+                if (on < o1) load_frame(on);
                 const int e_lo = sgo[o] - e0, e_hi = sgo[o + 1] - e0;
                 if (e_lo < e_hi) fetch_b(e_lo);
                 wave_lds_fence();
@@ -2085,17 +2115,9 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
                 for (int ei = e_lo; ei < e_hi; ++ei) {
                     const int info = einfo[ei];
                     const int g0 = info & 255, cnt = (info >> 8) & 255;
-                    // the entry's operands, taken over from the prefetch, then
-                    // the next entry's loads (this entry's again after the last)
-                    T b[NT][NK];
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-#pragma unroll
-                        for (int kk = 0; kk < NK; ++kk) {
-                            b[t][kk] = bn[t][kk];
-                            asm volatile("" : "+v"(b[t][kk]));
-                        }
-                    fetch_b(ei + 1 < e_hi ? ei + 1 : ei);
+                    // the first entry's operands were loaded with the frame
+                    if (ei > e_lo) fetch_b(ei);
+                    const T(&b)[NT][NK] = bn;
                     for (int t0 = 0; t0 < cnt; t0 += 16) {
                         const int rr = t0 + row;
                         const int nu_r = ord[g0 + (rr < cnt ? rr : 0)];
@@ -2631,6 +2653,7 @@ int c2p_default(const DevicePlan& p, int d)
 }
 
 inline int rb_index(int rb) { return rb == 1 ? 0 : (rb == 4 ? 1 : 2); }
+
 
 template <typename T, int PS, int PA, int RB>
 int c2p_variant(const DevicePlan& p, int d)
