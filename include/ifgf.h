@@ -159,7 +159,11 @@ typedef struct {
  *            wide (Sec. 4); for k = 0 the smallest D with at most 8 points
  *            per relevant leaf box.
  *   degrees  {P_s, P_ang}: Chebyshev nodes per cone in s and in each angle
- *            (Sec. 3.2); NULL: {3, 5}.  Supported: {3,5}, {4,6}, {2,3}.
+ *            (Sec. 3.2, eq. interp_pts); NULL: {3, 5}.  Each in 1..8 (below
+ *            1: IFGF_E_INVALID_ARG, above 8: IFGF_E_UNSUPPORTED).  {3,5},
+ *            {4,6} and {2,3} run kernels compiled for those counts (matrix
+ *            cores, pair tables); other counts run kernels that read them at
+ *            run time, with the geometry computed per evaluation.
  *   opt      NULL for defaults.
  *   plan     receives the new plan.                                        */
 ifgf_status ifgf_plan_create(const double* points, int64_t n, double k, int32_t levels,

@@ -295,8 +295,13 @@ static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt,
     ifgf_options o{};
     if (opt) o = *opt;
     int ps = degrees ? degrees[0] : 3, pa = degrees ? degrees[1] : 5;
-    if (!((ps == 3 && pa == 5) || (ps == 4 && pa == 6) || (ps == 2 && pa == 3)))
-        return fail(IFGF_E_UNSUPPORTED, "degrees must be {3,5}, {4,6} or {2,3}");
+    if (ps < 1 || pa < 1) return fail(IFGF_E_INVALID_ARG, "degrees (node counts) must be >= 1");
+    if (ps > ifgf::kMaxNodes || pa > ifgf::kMaxNodes)
+        return fail(IFGF_E_UNSUPPORTED, "degrees (node counts) above 8 are not supported");
+    // {3,5}, {4,6} and {2,3} have kernels compiled for their node counts;
+    // other counts run the kernels that read them at run time, which compute
+    // the cousin geometry per evaluation (no pair tables)
+    const bool compiled = (ps == 3 && pa == 5) || (ps == 4 && pa == 6) || (ps == 2 && pa == 3);
     int leaf_ns = o.leaf_ns ? o.leaf_ns : 1, leaf_nc = o.leaf_nc ? o.leaf_nc : 2;
     if (o.precision != IFGF_FP64 && o.precision != IFGF_MIXED) return fail(IFGF_E_INVALID_ARG, "unknown precision");
     int max_nrhs = o.max_nrhs ? o.max_nrhs : 16;
@@ -316,8 +321,8 @@ static ifgf_status create_common(const double* points, int64_t n, int64_t n_tgt,
     std::string msg;
     try {
         // a tabulated cousin-target pair: slot, 3 local coordinates, complex G
-        double pair_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 24.0 : 44.0);
-        double ord_bytes = p.host_only ? 0.0 : (o.precision == IFGF_MIXED ? 28.0 : 48.0);
+        double pair_bytes = p.host_only || !compiled ? 0.0 : (o.precision == IFGF_MIXED ? 24.0 : 44.0);
+        double ord_bytes = p.host_only || !compiled ? 0.0 : (o.precision == IFGF_MIXED ? 28.0 : 48.0);
         // pair tables: IFGF_PAIR_BUDGET_MB, else a quarter of the free device
         // memory, at most 64 GiB
         double budget = 0.0;

@@ -325,6 +325,8 @@ struct KernelConsts {
     int adj;                 // 1: the adjoint (conjugated centred factors and
                              // ratios); never inferred from the sign of kappa,
                              // which is -0.0 for the adjoint at k = 0
+    int ps = 0, pa = 0;      // node counts P_s, P_ang (read by the kernels
+                             // instantiated for run-time node counts)
 };
 
 // A plan: the host hierarchy, its device copy and the workspaces.

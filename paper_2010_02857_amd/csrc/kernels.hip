@@ -191,6 +191,129 @@ __device__ inline void interp(const cpx<T>* __restrict__ F, const T* Ls, const T
     }
 }
 
+// ------------------------------------- node counts known only at run time
+//
+// Kernels instantiated with PS = PA = 0 serve plans whose node counts were
+// not compiled in: P_s = kc.ps and P_ang = kc.pa (each 1..kMaxNodes) are read
+// at run time, the basis arrays are kMaxNodes long, and every loop runs to
+// kMaxNodes with a guard so that the arrays stay in registers.
+
+// Lagrange basis through the first n of the nodes cn at t (zeros beyond n).
+template <typename T>
+__device__ inline void lagrange_any(double t, const ChebNodes& cn, int n, T* L)
+{
+    const T tt = (T)t;
+    T d[kMaxNodes], suf[kMaxNodes];
+#pragma unroll
+    for (int k = 0; k < kMaxNodes; ++k) d[k] = tt - (T)cn.t[k];
+    suf[kMaxNodes - 1] = (T)1;
+#pragma unroll
+    for (int k = kMaxNodes - 2; k >= 0; --k) suf[k] = k + 1 < n ? suf[k + 1] * d[k + 1] : (T)1;
+    T pre = (T)1;
+#pragma unroll
+    for (int k = 0; k < kMaxNodes; ++k) {
+        L[k] = k < n ? pre * suf[k] * (T)cn.inv[k] : (T)0;
+        pre *= d[k];
+    }
+}
+
+// The basis and its derivative d/dt (zeros beyond n).
+template <typename T>
+__device__ inline void lagrange_d_any(double t, const ChebNodes& cn, int n, T* L, T* dL)
+{
+    const T tt = (T)t;
+    T d[kMaxNodes];
+#pragma unroll
+    for (int k = 0; k < kMaxNodes; ++k) d[k] = tt - (T)cn.t[k];
+#pragma unroll
+    for (int k = 0; k < kMaxNodes; ++k) {
+        T p = (T)1, dp = (T)0;
+#pragma unroll
+        for (int j = 0; j < kMaxNodes; ++j) {
+            if (j == k || j >= n) continue;
+            dp = dp * d[j] + p;
+            p *= d[j];
+        }
+        L[k] = k < n ? p * (T)cn.inv[k] : (T)0;
+        dL[k] = k < n ? dp * (T)cn.inv[k] : (T)0;
+    }
+}
+
+// Element i < kMaxNodes of a register array, by a chain of selects.
+template <typename T>
+__device__ inline T sel_any(const T* a, int i)
+{
+    T v = a[0];
+#pragma unroll
+    for (int k = 1; k < kMaxNodes; ++k) v = i == k ? a[k] : v;
+    return v;
+}
+
+// interp for run-time node counts ps x pa x pa: phi contracted first (in
+// registers), then theta and s.
+template <typename T, int RB>
+__device__ inline void interp_any(const cpx<T>* __restrict__ F, const T* Ls, const T* Lt, const T* Lp, int ps,
+                                  int pa, cpx<T>* v)
+{
+#pragma unroll
+    for (int r = 0; r < RB; ++r) v[r].x = v[r].y = (T)0;
+    for (int a = 0; a < ps; ++a) {
+        const T la = sel_any(Ls, a);
+        cpx<T> w[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) w[r].x = w[r].y = (T)0;
+        for (int b = 0; b < pa; ++b) {
+            const T lb = sel_any(Lt, b);
+            const cpx<T>* f = F + (size_t)(a * pa + b) * pa * RB;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                T ux = (T)0, uy = (T)0;
+#pragma unroll
+                for (int c = 0; c < kMaxNodes; ++c) {
+                    if (c < pa) {
+                        const cpx<T> q = f[c * RB + r];
+                        ux += Lp[c] * q.x;
+                        uy += Lp[c] * q.y;
+                    }
+                }
+                w[r].x += lb * ux;
+                w[r].y += lb * uy;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            v[r].x += la * w[r].x;
+            v[r].y += la * w[r].y;
+        }
+    }
+}
+
+// Dispatch between the compiled node counts (N > 0) and run-time ones (N = 0).
+template <int N>
+constexpr int basis_len()
+{
+    return N > 0 ? N : kMaxNodes;
+}
+template <typename T, int N>
+__device__ inline void basis(double t, const ChebNodes& cn, int n, T* L)
+{
+    if constexpr (N > 0) lagrange<T, N>(t, cn, L);
+    else lagrange_any<T>(t, cn, n, L);
+}
+template <typename T, int N>
+__device__ inline void basis_d(double t, const ChebNodes& cn, int n, T* L, T* dL)
+{
+    if constexpr (N > 0) lagrange_d<T, N>(t, cn, L, dL);
+    else lagrange_d_any<T>(t, cn, n, L, dL);
+}
+template <typename T, int PS, int PA, int RB>
+__device__ inline void interp_n(const cpx<T>* __restrict__ F, const T* Ls, const T* Lt, const T* Lp,
+                                const KernelConsts& kc, cpx<T>* v)
+{
+    if constexpr (PS > 0) interp<T, PS, PA, RB>(F, Ls, Lt, Lp, v);
+    else interp_any<T, RB>(F, Ls, Lt, Lp, kc.ps, kc.pa, v);
+}
+
 // ------------------------------------------------------------------ kernels
 
 // A window [w0, w0 + wn) of the plan's point indices (input order): all
@@ -301,7 +424,8 @@ __global__ void __launch_bounds__(kBlock) k_leaf_nodes(KernelConsts kc, LevelDev
                                                        const cpx<T>* __restrict__ dens, cpx<T>* __restrict__ F,
                                                        const int32_t* __restrict__ list, int nlist)
 {
-    constexpr int P = PS * PA * PA;
+    const int ps = PS > 0 ? PS : kc.ps, pa = PA > 0 ? PA : kc.pa;
+    const int P = ps * pa * pa;
     size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     int slot = (int)(gid / P);
     int nu = (int)(gid - (size_t)slot * P);
@@ -310,9 +434,9 @@ __global__ void __launch_bounds__(kBlock) k_leaf_nodes(KernelConsts kc, LevelDev
     const int b = L.slot_box[slot];
     const int cone = L.slot_cone[slot];
     const int cell = cone / L.ns, is = cone - cell * L.ns;
-    const int a = nu / (PA * PA), bc = nu - a * PA * PA;
-    const double rr = L.node_r[is * PS + a];
-    const double* dir = &L.node_dir[((size_t)cell * PA * PA + bc) * 3];
+    const int a = nu / (pa * pa), bc = nu - a * pa * pa;
+    const double rr = L.node_r[is * ps + a];
+    const double* dir = &L.node_dir[((size_t)cell * pa * pa + bc) * 3];
     const double y0 = rr * dir[0], y1 = rr * dir[1], y2 = rr * dir[2];
     const double ry = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
     const double c0 = L.box_ctr[3 * b], c1 = L.box_ctr[3 * b + 1], c2 = L.box_ctr[3 * b + 2];
@@ -347,7 +471,7 @@ template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_cousin_eval(KernelConsts kc, LevelDev L, const double* __restrict__ pts,
                                                         const cpx<T>* __restrict__ F, cpx<T>* __restrict__ out)
 {
-    constexpr int P = PS * PA * PA;
+    const int P = PS > 0 ? PS * PA * PA : kc.ps * kc.pa * kc.pa;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int t = L.pt_box[i];
@@ -365,12 +489,12 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval(KernelConsts kc, LevelDe
             atomicAdd(kc.miss, 1ull);
             continue;
         }
-        T Ls[PS], Lt[PA], Lp[PA];
-        lagrange<T, PS>(cl.ts, kc.cs, Ls);
-        lagrange<T, PA>(cl.tt, kc.ca, Lt);
-        lagrange<T, PA>(cl.tp, kc.ca, Lp);
+        T Ls[basis_len<PS>()], Lt[basis_len<PA>()], Lp[basis_len<PA>()];
+        basis<T, PS>(cl.ts, kc.cs, kc.ps, Ls);
+        basis<T, PA>(cl.tt, kc.ca, kc.pa, Lt);
+        basis<T, PA>(cl.tp, kc.ca, kc.pa, Lp);
         cpx<T> v[RB];
-        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
+        interp_n<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, kc, v);
         T c, s;
         expi<T>(kc.kappa * cl.r, c, s);
         T inv = (T)(kInv4Pi / cl.r);
@@ -716,7 +840,8 @@ template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                             const cpx<T>* __restrict__ Fc, cpx<T>* __restrict__ Fp)
 {
-    constexpr int P = PS * PA * PA;
+    const int ps = PS > 0 ? PS : kc.ps, pa = PA > 0 ? PA : kc.pa;
+    const int P = ps * pa * pa;
     size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     int pslot = (int)(gid / P);
     int nu = (int)(gid - (size_t)pslot * P);
@@ -724,9 +849,9 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, Lev
     const int j = Lp.slot_box[pslot];
     const int pcone = Lp.slot_cone[pslot];
     const int pcell = pcone / Lp.ns, pis = pcone - pcell * Lp.ns;
-    const int a = nu / (PA * PA), bc = nu - a * PA * PA;
-    const double rr = Lp.node_r[pis * PS + a];
-    const double* dir = &Lp.node_dir[((size_t)pcell * PA * PA + bc) * 3];
+    const int a = nu / (pa * pa), bc = nu - a * pa * pa;
+    const double rr = Lp.node_r[pis * ps + a];
+    const double* dir = &Lp.node_dir[((size_t)pcell * pa * pa + bc) * 3];
     const double y0 = rr * dir[0], y1 = rr * dir[1], y2 = rr * dir[2];
     const double ry = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
     const double half = 0.5 * Lc.H;
@@ -746,12 +871,12 @@ __global__ void __launch_bounds__(kBlock) k_child_to_parent(KernelConsts kc, Lev
             atomicAdd(kc.miss, 1ull);
             continue;
         }
-        T Ls[PS], Lt[PA], Lpp[PA];
-        lagrange<T, PS>(cl.ts, kc.cs, Ls);
-        lagrange<T, PA>(cl.tt, kc.ca, Lt);
-        lagrange<T, PA>(cl.tp, kc.ca, Lpp);
+        T Ls[basis_len<PS>()], Lt[basis_len<PA>()], Lpp[basis_len<PA>()];
+        basis<T, PS>(cl.ts, kc.cs, kc.ps, Ls);
+        basis<T, PA>(cl.tt, kc.ca, kc.pa, Lt);
+        basis<T, PA>(cl.tp, kc.ca, kc.pa, Lpp);
         cpx<T> val[RB];
-        interp<T, PS, PA, RB>(Fc + (size_t)slot * P * RB, Ls, Lt, Lpp, val);
+        interp_n<T, PS, PA, RB>(Fc + (size_t)slot * P * RB, Ls, Lt, Lpp, kc, val);
         double num = (o[0] * o[0] + o[1] * o[1] + o[2] * o[2]) - 2.0 * (y0 * o[0] + y1 * o[1] + y2 * o[2]);
         double diff = num / (cl.r + ry);
         T c, s;
@@ -2382,7 +2507,7 @@ __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDe
                                                         const cpx<T>* __restrict__ F, const cpx<T>* __restrict__ gout,
                                                         double* __restrict__ grad)
 {
-    constexpr int P = PS * PA * PA;
+    const int P = PS > 0 ? PS * PA * PA : kc.ps * kc.pa * kc.pa;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int t = L.pt_box[i];
@@ -2401,15 +2526,16 @@ __global__ void __launch_bounds__(kBlock) k_cousin_grad(KernelConsts kc, LevelDe
             atomicAdd(kc.miss, 1ull);
             continue;
         }
-        T Ls[PS], Lt[PA], Lp[PA], dLs[PS], dLt[PA], dLp[PA];
-        lagrange_d<T, PS>(cl.ts, kc.cs, Ls, dLs);
-        lagrange_d<T, PA>(cl.tt, kc.ca, Lt, dLt);
-        lagrange_d<T, PA>(cl.tp, kc.ca, Lp, dLp);
+        constexpr int NS = basis_len<PS>(), NA = basis_len<PA>();
+        T Ls[NS], Lt[NA], Lp[NA], dLs[NS], dLt[NA], dLp[NA];
+        basis_d<T, PS>(cl.ts, kc.cs, kc.ps, Ls, dLs);
+        basis_d<T, PA>(cl.tt, kc.ca, kc.pa, Lt, dLt);
+        basis_d<T, PA>(cl.tp, kc.ca, kc.pa, Lp, dLp);
         cpx<T> v[RB], vs[RB], vt[RB], vp[RB];
-        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, v);
-        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, dLs, Lt, Lp, vs);
-        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, dLt, Lp, vt);
-        interp<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, dLp, vp);
+        interp_n<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, Lp, kc, v);
+        interp_n<T, PS, PA, RB>(F + (size_t)slot * P * RB, dLs, Lt, Lp, kc, vs);
+        interp_n<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, dLt, Lp, kc, vt);
+        interp_n<T, PS, PA, RB>(F + (size_t)slot * P * RB, Ls, Lt, dLp, kc, vp);
         const double r = cl.r, r2 = r * r;
         const double rho2 = v0 * v0 + v1 * v1, rho = sqrt(rho2);
         const double cs_ = 2.0 / L.ds, ca_ = 2.0 / L.dang;
@@ -2510,8 +2636,12 @@ inline int rb_for(int nrhs) { return nrhs >= 5 ? 16 : (nrhs >= 2 ? 4 : 1); }
 // Pairs the per-pair value buffer holds: those of the largest tabulated level,
 // and of the largest untabulated one when that fits the budget
 // (IFGF_PVAL_BUDGET_MB, default 32768) at rb right-hand sides.
+inline bool compiled_degrees(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6) || (ps == 2 && pa == 3); }
+
 inline int64_t pval_pairs_for(const DevicePlan& p, int rb, size_t ce)
 {
+    // the kernels for run-time node counts evaluate cousins in one pass
+    if (!compiled_degrees(p.hp.ps, p.hp.pang)) return 0;
     int64_t geo = 0;
     for (int d = 3; d <= p.hp.D; ++d)
         if (!p.hp.L[d].use_pairs) geo = std::max<int64_t>(geo, p.npairs_all[d]);
@@ -2602,31 +2732,39 @@ inline double box_fill_min(int rb)
 template <typename T, int PS, int PA, int RB>
 int c2p_candidates(const DevicePlan& p, int d, int* v)
 {
-    constexpr int P = PS * PA * PA;
-    constexpr int S = lds_slots<P, RB>();
-    constexpr int GCAP = lds_gcap<T, P, RB, S>();
-    const LevelDev& L = p.L[d];
-    const bool groups = L.use_frames && L.frame_groups_ok;
-    int n = 0;
-    v[n++] = kC2PGeometry;
-    if (L.use_frames) v[n++] = kC2PFrames;
-    if constexpr (GCAP >= S) {
-        if (groups) v[n++] = kC2PLds;
-        if (groups && L.slot_order) v[n++] = kC2PLdsTiled;
+    if constexpr (PS == 0) {
+        // run-time node counts: the geometry kernel only
+        (void)p;
+        (void)d;
+        v[0] = kC2PGeometry;
+        return 1;
+    } else {
+        constexpr int P = PS * PA * PA;
+        constexpr int S = lds_slots<P, RB>();
+        constexpr int GCAP = lds_gcap<T, P, RB, S>();
+        const LevelDev& L = p.L[d];
+        const bool groups = L.use_frames && L.frame_groups_ok;
+        int n = 0;
+        v[n++] = kC2PGeometry;
+        if (L.use_frames) v[n++] = kC2PFrames;
+        if constexpr (GCAP >= S) {
+            if (groups) v[n++] = kC2PLds;
+            if (groups && L.slot_order) v[n++] = kC2PLdsTiled;
+        }
+        if constexpr (RB >= 4 && PA >= 4 && P <= 128) {
+            v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
+        }
+        if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
+            if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxes;
+        }
+        if constexpr (PA >= 4 && P <= 128) {
+            if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAcc;
+        }
+        if constexpr (RB == 1 && P <= 255) {
+            if (groups) v[n++] = kC2PQuads;
+        }
+        return n;
     }
-    if constexpr (RB >= 4 && PA >= 4 && P <= 128) {
-        v[n++] = groups ? kC2PMfma : kC2PMfmaGeometry;
-    }
-    if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
-        if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxes;
-    }
-    if constexpr (PA >= 4 && P <= 128) {
-        if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAcc;
-    }
-    if constexpr (RB == 1 && P <= 255) {
-        if (groups) v[n++] = kC2PQuads;
-    }
-    return n;
 }
 
 // The variant used when the plan has not been tuned: the box-batched kernel
@@ -2635,24 +2773,34 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
 template <typename T, int PS, int PA, int RB>
 int c2p_default(const DevicePlan& p, int d)
 {
-    int v[kC2PVariants];
-    const int n = c2p_candidates<T, PS, PA, RB>(p, d, v);
-    auto has = [&](int x) {
-        for (int i = 0; i < n; ++i)
-            if (v[i] == x) return true;
-        return false;
-    };
-    const bool full = (double)p.hp.L[d - 1].nslots >= box_fill_min(RB) * kBoxTile * (double)p.L[d].ntiles;
-    if (has(kC2PBoxes) && full) return kC2PBoxes;
-    if (std::is_same<T, double>::value && has(kC2PBoxAcc) && full) return kC2PBoxAcc;
-    if (has(kC2PMfma)) return kC2PMfma;
-    if (has(kC2PMfmaGeometry)) return kC2PMfmaGeometry;
-    if (has(kC2PLds)) return kC2PLds;
-    if (has(kC2PFrames)) return kC2PFrames;
-    return kC2PGeometry;
+    if constexpr (PS == 0) {
+        (void)p;
+        (void)d;
+        return kC2PGeometry;
+    } else {
+        int v[kC2PVariants];
+        const int n = c2p_candidates<T, PS, PA, RB>(p, d, v);
+        auto has = [&](int x) {
+            for (int i = 0; i < n; ++i)
+                if (v[i] == x) return true;
+            return false;
+        };
+        const bool full = (double)p.hp.L[d - 1].nslots >= box_fill_min(RB) * kBoxTile * (double)p.L[d].ntiles;
+        if (has(kC2PBoxes) && full) return kC2PBoxes;
+        if (std::is_same<T, double>::value && has(kC2PBoxAcc) && full) return kC2PBoxAcc;
+        if (has(kC2PMfma)) return kC2PMfma;
+        if (has(kC2PMfmaGeometry)) return kC2PMfmaGeometry;
+        if (has(kC2PLds)) return kC2PLds;
+        if (has(kC2PFrames)) return kC2PFrames;
+        return kC2PGeometry;
+    }
 }
 
 inline int rb_index(int rb) { return rb == 1 ? 0 : (rb == 4 ? 1 : 2); }
+
+// Node counts served by the kernels instantiated for run-time node counts
+// (PS = PA = 0): any other pair with 1 <= P_s, P_ang <= kMaxNodes.
+inline bool any_degrees(int ps, int pa) { return ps >= 1 && ps <= kMaxNodes && pa >= 1 && pa <= kMaxNodes; }
 
 
 template <typename T, int PS, int PA, int RB>
@@ -2665,75 +2813,83 @@ int c2p_variant(const DevicePlan& p, int d)
 template <typename T, int PS, int PA, int RB>
 void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipStream_t st)
 {
-    constexpr int P = PS * PA * PA;
-    constexpr int S = lds_slots<P, RB>();
-    constexpr int GCAP = lds_gcap<T, P, RB, S>();
-    constexpr int NT = lds_threads<P, RB>();
-    using C = cpx<T>;
-    const int64_t nps = p.hp.L[d - 1].nslots;
-    const C* Fc = (const C*)p.F[d];
-    C* Fp = (C*)p.F[d - 1];
-    switch (variant) {
-    case kC2PBoxes:
-        if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
-            k_child_to_parent_boxes<PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
-                kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+    if constexpr (PS == 0) {
+        // run-time node counts: geometry computed per evaluation
+        (void)variant;
+        const int64_t nps = p.hp.L[d - 1].nslots;
+        k_child_to_parent<T, 0, 0, RB><<<grid_for((size_t)nps * p.hp.P), kBlock, 0, st>>>(
+            kc, p.L[d], p.L[d - 1], (const cpx<T>*)p.F[d], (cpx<T>*)p.F[d - 1]);
+    } else {
+        constexpr int P = PS * PA * PA;
+        constexpr int S = lds_slots<P, RB>();
+        constexpr int GCAP = lds_gcap<T, P, RB, S>();
+        constexpr int NT = lds_threads<P, RB>();
+        using C = cpx<T>;
+        const int64_t nps = p.hp.L[d - 1].nslots;
+        const C* Fc = (const C*)p.F[d];
+        C* Fp = (C*)p.F[d - 1];
+        switch (variant) {
+        case kC2PBoxes:
+            if constexpr (std::is_same<T, float>::value && PA >= 4 && P <= 128) {
+                k_child_to_parent_boxes<PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                    kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+                return;
+            }
+            break;
+        case kC2PBoxAcc:
+            if constexpr (PA >= 4 && P <= 128) {
+                k_child_to_parent_boxacc<T, PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                    kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+                return;
+            }
+            break;
+        case kC2PMfma:
+        case kC2PMfmaGeometry:
+            if constexpr (RB >= 4 && PA >= 4 && P <= 128) {
+                // wavefronts per block: the slots' accumulators in LDS stay under
+                // about 40 KB per block
+                constexpr int W = mfma_waves<T, P, RB>();
+                const unsigned nb = (unsigned)((nps + W - 1) / W);
+                if (variant == kC2PMfma)
+                    k_child_to_parent_mfma<T, PS, PA, RB, W><<<nb, 64 * W, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                else
+                    k_child_to_parent_mfma_geo<T, PS, PA, RB, W><<<nb, 64 * W, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                return;
+            }
+            break;
+        case kC2PLds:
+            if constexpr (GCAP >= S) {
+                k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, false, NT>
+                    <<<(unsigned)((nps + S - 1) / S), NT, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                return;
+            }
+            break;
+        case kC2PLdsTiled:
+            if constexpr (GCAP >= S) {
+                k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, true, NT>
+                    <<<(unsigned)((nps + S - 1) / S), NT, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                return;
+            }
+            break;
+        case kC2PFrames:
+            k_child_to_parent_frames<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1],
+                                                                                                 Fc, Fp);
             return;
+        case kC2PQuads:
+            if constexpr (RB == 1 && P <= 255) {
+                constexpr int QS = kQuadSlots;
+                constexpr int QR = std::is_same<T, float>::value ? 4 : 2;
+                constexpr int QG = quad_gcap<T, P>();
+                k_child_to_parent_quads<T, PS, PA, QS, QR, QG>
+                    <<<(unsigned)((nps + QS - 1) / QS), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
+                return;
+            }
+            break;
+        default:
+            break;
         }
-        break;
-    case kC2PBoxAcc:
-        if constexpr (PA >= 4 && P <= 128) {
-            k_child_to_parent_boxacc<T, PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
-                kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
-            return;
-        }
-        break;
-    case kC2PMfma:
-    case kC2PMfmaGeometry:
-        if constexpr (RB >= 4 && PA >= 4 && P <= 128) {
-            // wavefronts per block: the slots' accumulators in LDS stay under
-            // about 40 KB per block
-            constexpr int W = mfma_waves<T, P, RB>();
-            const unsigned nb = (unsigned)((nps + W - 1) / W);
-            if (variant == kC2PMfma)
-                k_child_to_parent_mfma<T, PS, PA, RB, W><<<nb, 64 * W, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
-            else
-                k_child_to_parent_mfma_geo<T, PS, PA, RB, W><<<nb, 64 * W, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
-            return;
-        }
-        break;
-    case kC2PLds:
-        if constexpr (GCAP >= S) {
-            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, false, NT>
-                <<<(unsigned)((nps + S - 1) / S), NT, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
-            return;
-        }
-        break;
-    case kC2PLdsTiled:
-        if constexpr (GCAP >= S) {
-            k_child_to_parent_lds<T, PS, PA, RB, S, GCAP, true, NT>
-                <<<(unsigned)((nps + S - 1) / S), NT, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
-            return;
-        }
-        break;
-    case kC2PFrames:
-        k_child_to_parent_frames<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1],
-                                                                                             Fc, Fp);
-        return;
-    case kC2PQuads:
-        if constexpr (RB == 1 && P <= 255) {
-            constexpr int QS = kQuadSlots;
-            constexpr int QR = std::is_same<T, float>::value ? 4 : 2;
-            constexpr int QG = quad_gcap<T, P>();
-            k_child_to_parent_quads<T, PS, PA, QS, QR, QG>
-                <<<(unsigned)((nps + QS - 1) / QS), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
-            return;
-        }
-        break;
-    default:
-        break;
+        k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
     }
-    k_child_to_parent<T, PS, PA, RB><<<grid_for((size_t)nps * P), kBlock, 0, st>>>(kc, p.L[d], p.L[d - 1], Fc, Fp);
 }
 
 // The matrix-core cousin evaluation for batched right-hand sides runs only
@@ -2816,49 +2972,55 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
         return;
     }
     StageTimer tm_(p, IFGF_STAGE_COUSIN_EVAL, st, d);
-    bool done = false;
-    if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4) {
-        if (p.L[d].use_pairs && cousin_mfma_enabled()) {
-            k_cousin_eval_mfma<PS, PA, RB><<<(unsigned)((hp.L[d].nbox + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0,
-                                             st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.out_m);
-            done = true;
-        }
-    }
-    if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
-        if constexpr (RB == 1) {
-            k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord / kPairQuad), kBlock, 0, st>>>(
-                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
-            done = true;
-        } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
-            const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;
-            k_cousin_pairs_values_mfma<PS, PA, RB><<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock,
-                                                     0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
-            done = true;
-        }
-        if (done)
-            k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
-    }
-    if (done) {
-    } else if (p.L[d].use_pairs && p.pval && p.L[d].npairs_cou <= p.pval_pairs && cousin_geo_pairs_enabled() &&
-               hp.n < 64 * (int64_t)hp.L[d].nbox) {
-        // two phases through the pair table, where boxes hold few targets (in
-        // large boxes the threads of one target box already walk the same
-        // cousins together, and the one-kernel form measured faster)
-        k_cousin_pairs_tab<T, PS, PA, RB><<<grid_for((size_t)p.L[d].npairs_cou), kBlock, 0, st>>>(
-            kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
-        k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
-    } else if (p.L[d].use_pairs) {
-        k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
-                                                                           (C*)p.out_m);
-    } else if (p.pval && p.pair_off[d] && p.npairs_all[d] <= p.pval_pairs && cousin_geo_pairs_enabled()) {
-        // two phases with the geometry computed per pair
-        k_cousin_pairs_geo<T, PS, PA, RB><<<grid_for((size_t)p.npairs_all[d]), kBlock, 0, st>>>(
-            kc, p.L[d], p.pts, p.pair_off[d], p.npairs_all[d], (const C*)p.F[d], (C*)p.pval);
-        k_cousin_pairs_sum_geo<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pair_off[d], (const C*)p.pval,
-                                                                      (C*)p.out_m);
+    if constexpr (PS == 0) {
+        // run-time node counts: one kernel, geometry computed per evaluation
+        k_cousin_eval<T, 0, 0, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d], (C*)p.out_m);
+        return;
     } else {
-        k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
-                                                                     (C*)p.out_m);
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value && RB >= 4 && PA >= 4) {
+            if (p.L[d].use_pairs && cousin_mfma_enabled()) {
+                k_cousin_eval_mfma<PS, PA, RB><<<(unsigned)((hp.L[d].nbox + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0,
+                                                 st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.out_m);
+                done = true;
+            }
+        }
+        if (!done && p.L[d].use_pairs && p.L[d].npairs_ord > 0 && p.pval && cousin_two_phase_enabled()) {
+            if constexpr (RB == 1) {
+                k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord / kPairQuad), kBlock, 0, st>>>(
+                    kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+                done = true;
+            } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
+                const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;
+                k_cousin_pairs_values_mfma<PS, PA, RB><<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock,
+                                                         0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+                done = true;
+            }
+            if (done)
+                k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
+        }
+        if (done) {
+        } else if (p.L[d].use_pairs && p.pval && p.L[d].npairs_cou <= p.pval_pairs && cousin_geo_pairs_enabled() &&
+                   hp.n < 64 * (int64_t)hp.L[d].nbox) {
+            // two phases through the pair table, where boxes hold few targets (in
+            // large boxes the threads of one target box already walk the same
+            // cousins together, and the one-kernel form measured faster)
+            k_cousin_pairs_tab<T, PS, PA, RB><<<grid_for((size_t)p.L[d].npairs_cou), kBlock, 0, st>>>(
+                kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+            k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
+        } else if (p.L[d].use_pairs) {
+            k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
+                                                                               (C*)p.out_m);
+        } else if (p.pval && p.pair_off[d] && p.npairs_all[d] <= p.pval_pairs && cousin_geo_pairs_enabled()) {
+            // two phases with the geometry computed per pair
+            k_cousin_pairs_geo<T, PS, PA, RB><<<grid_for((size_t)p.npairs_all[d]), kBlock, 0, st>>>(
+                kc, p.L[d], p.pts, p.pair_off[d], p.npairs_all[d], (const C*)p.F[d], (C*)p.pval);
+            k_cousin_pairs_sum_geo<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pair_off[d], (const C*)p.pval,
+                                                                          (C*)p.out_m);
+        } else {
+            k_cousin_eval<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pts, (const C*)p.F[d],
+                                                                         (C*)p.out_m);
+        }
     }
 }
 
@@ -2874,7 +3036,7 @@ hipError_t upward_and_eval(DevicePlan& p, const KernelConsts& kc, hipStream_t st
 {
     const HostPlan& hp = p.hp;
     const int D = hp.D;
-    constexpr int P = PS * PA * PA;
+    const int P = hp.P;
     using C = cpx<T>;
     const bool two = sd && sd != st;
     if (!sd) sd = st;
@@ -2927,7 +3089,8 @@ hipError_t apply_pass(DevicePlan& p, const void* dens, int nrhs, int r0, void* o
     using C = cpx<T>;
     // the adjoint conjugates every factor e^{i k .}: the phases use -k, and
     // the tabulated centred factors and ratios are conjugated (kc.adj)
-    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), adj ? -p.hp.kappa : p.hp.kappa, n, p.miss, adj ? 1 : 0};
+    KernelConsts kc{make_cheb_nodes(p.hp.ps), make_cheb_nodes(p.hp.pang), adj ? -p.hp.kappa : p.hp.kappa, n, p.miss,
+                    adj ? 1 : 0, p.hp.ps, p.hp.pang};
     hipError_t e;
     // (a capture records the side stream's work too: it joins the capture
     // through the first event wait and leaves it through the last; the side
@@ -2970,7 +3133,8 @@ hipError_t grad_pass(DevicePlan& p, const void* dens, const void* gout, int nrhs
 {
     const int n = (int)p.hp.n;
     using C = cpx<T>;
-    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), p.hp.kappa, n, p.miss, 0};
+    KernelConsts kc{make_cheb_nodes(p.hp.ps), make_cheb_nodes(p.hp.pang), p.hp.kappa, n, p.miss, 0, p.hp.ps,
+                    p.hp.pang};
     if (!reuse)
         {
             StageTimer tm_(p, IFGF_STAGE_PERMUTE_IN, st);
@@ -3141,7 +3305,7 @@ hipError_t autotune_t(DevicePlan& p, hipStream_t st)
 {
     const HostPlan& hp = p.hp;
     const int D = hp.D;
-    constexpr int P = PS * PA * PA;
+    const int P = hp.P;
     using C = cpx<T>;
     hipError_t e = ensure_workspace<T>(p, RB, p.ws_store_pref, nullptr);
     if (e != hipSuccess) return e;
@@ -3149,7 +3313,8 @@ hipError_t autotune_t(DevicePlan& p, hipStream_t st)
     if (D < 4) return hipSuccess;
     const bool prof = p.profiling;
     p.profiling = false;
-    KernelConsts kc{make_cheb_nodes(PS), make_cheb_nodes(PA), hp.kappa, (int)hp.n, p.miss, 0};
+    KernelConsts kc{make_cheb_nodes(hp.ps), make_cheb_nodes(hp.pang), hp.kappa, (int)hp.n, p.miss, 0, hp.ps,
+                    hp.pang};
     if ((e = hipMemsetAsync(p.dens_m, 0, (size_t)hp.n * RB * sizeof(C), st)) != hipSuccess) return e;
     if (hp.L[D].nslots > 0)
         k_leaf_nodes<T, PS, PA, RB><<<grid_for((size_t)hp.L[D].nslots * P), kBlock, 0, st>>>(
@@ -3250,6 +3415,7 @@ hipError_t run_autotune(DevicePlan& p, int nrhs, hipStream_t st)
     if (ps == 3 && pa == 5) return mixed ? autotune_rb<float, 3, 5>(p, rb, st) : autotune_rb<double, 3, 5>(p, rb, st);
     if (ps == 4 && pa == 6) return mixed ? autotune_rb<float, 4, 6>(p, rb, st) : autotune_rb<double, 4, 6>(p, rb, st);
     if (ps == 2 && pa == 3) return mixed ? autotune_rb<float, 2, 3>(p, rb, st) : autotune_rb<double, 2, 3>(p, rb, st);
+    if (any_degrees(ps, pa)) return mixed ? autotune_rb<float, 0, 0>(p, rb, st) : autotune_rb<double, 0, 0>(p, rb, st);
     return hipErrorInvalidValue;
 }
 
@@ -3262,6 +3428,7 @@ int kernel_candidates(const DevicePlan& p, int nrhs, int d, int* v)
     if (ps == 3 && pa == 5) return mixed ? candidates_t<float, 3, 5>(p, rb, d, v) : candidates_t<double, 3, 5>(p, rb, d, v);
     if (ps == 4 && pa == 6) return mixed ? candidates_t<float, 4, 6>(p, rb, d, v) : candidates_t<double, 4, 6>(p, rb, d, v);
     if (ps == 2 && pa == 3) return mixed ? candidates_t<float, 2, 3>(p, rb, d, v) : candidates_t<double, 2, 3>(p, rb, d, v);
+    if (any_degrees(ps, pa)) return mixed ? candidates_t<float, 0, 0>(p, rb, d, v) : candidates_t<double, 0, 0>(p, rb, d, v);
     return 0;
 }
 
@@ -3291,6 +3458,7 @@ int kernel_choice(const DevicePlan& p, int nrhs, int d)
     if (ps == 3 && pa == 5) return mixed ? choice_t<float, 3, 5>(p, rb, d) : choice_t<double, 3, 5>(p, rb, d);
     if (ps == 4 && pa == 6) return mixed ? choice_t<float, 4, 6>(p, rb, d) : choice_t<double, 4, 6>(p, rb, d);
     if (ps == 2 && pa == 3) return mixed ? choice_t<float, 2, 3>(p, rb, d) : choice_t<double, 2, 3>(p, rb, d);
+    if (any_degrees(ps, pa)) return mixed ? choice_t<float, 0, 0>(p, rb, d) : choice_t<double, 0, 0>(p, rb, d);
     return -1;
 }
 
@@ -3305,6 +3473,8 @@ hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, bool 
         e = mixed ? apply_t<float, 4, 6>(p, dens, nrhs, out, adj, st) : apply_t<double, 4, 6>(p, dens, nrhs, out, adj, st);
     else if (ps == 2 && pa == 3)
         e = mixed ? apply_t<float, 2, 3>(p, dens, nrhs, out, adj, st) : apply_t<double, 2, 3>(p, dens, nrhs, out, adj, st);
+    else if (any_degrees(ps, pa))
+        e = mixed ? apply_t<float, 0, 0>(p, dens, nrhs, out, adj, st) : apply_t<double, 0, 0>(p, dens, nrhs, out, adj, st);
     else
         return hipErrorInvalidValue;
     if (e == hipSuccess) note_apply(p, dens, nrhs, adj);
@@ -3340,6 +3510,9 @@ hipError_t run_apply_noalloc(DevicePlan& p, const void* dens, int nrhs, void* ou
     if (ps == 2 && pa == 3)
         return mixed ? apply_noalloc_t<float, 2, 3>(p, dens, nrhs, out, adj, st, base)
                      : apply_noalloc_t<double, 2, 3>(p, dens, nrhs, out, adj, st, base);
+    if (any_degrees(ps, pa))
+        return mixed ? apply_noalloc_t<float, 0, 0>(p, dens, nrhs, out, adj, st, base)
+                     : apply_noalloc_t<double, 0, 0>(p, dens, nrhs, out, adj, st, base);
     return hipErrorInvalidValue;
 }
 
@@ -3357,6 +3530,8 @@ hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs,
         e = mixed ? grad_t<float, 4, 6>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 4, 6>(p, dens, gout, nrhs, grad, reuse, st);
     else if (ps == 2 && pa == 3)
         e = mixed ? grad_t<float, 2, 3>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 2, 3>(p, dens, gout, nrhs, grad, reuse, st);
+    else if (any_degrees(ps, pa))
+        e = mixed ? grad_t<float, 0, 0>(p, dens, gout, nrhs, grad, reuse, st) : grad_t<double, 0, 0>(p, dens, gout, nrhs, grad, reuse, st);
     else
         return hipErrorInvalidValue;
     if (e == hipSuccess && p.ws_store && nrhs <= kMaxRhsPass) {

@@ -26,7 +26,7 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("case", ["cfg1", "cloud", "laplace", "leaf23", "deg46", "lattice", "adaptive6",
-                                  "adaptive60"])
+                                  "adaptive60", "deg17", "deg52", "deg88"])
 def test_host_plan_matches_oracle_counts(case):
     """Relevant boxes, cousins, relevant cones, child-to-parent and near-field
     work per level equal those of the CPU oracle (Sec. 3.3.2)."""
@@ -50,6 +50,11 @@ def test_host_plan_matches_oracle_counts(case):
         lm = 60 if case == "adaptive60" else 6
         kw = {"levels": 6, "leaf_max": lm}
         okw = {"levels": 6, "leaf_max": lm}
+    elif case in ("deg17", "deg52", "deg88"):
+        # node counts with no compiled kernels (run-time node counts)
+        p, k = inputs.cube_sphere(14), 9.0
+        kw = {"degrees": (int(case[3]), int(case[4]))}
+        okw = dict(kw)
     elif case == "leaf23":
         p, k = inputs.cube_sphere(20, 0.25), 15.0
         kw = {"leaf": (2, 3)}
@@ -127,7 +132,9 @@ def test_invalid_arguments_are_rejected():
     assert _create(p, 50, k=float("nan"))[0] == 1
     assert _create(p, 50, levels=1)[0] == 1
     assert _create(p, 50, levels=30)[0] == 1
-    assert _create(p, 50, degrees=(7, 7))[0] == 4
+    assert _create(p, 50, degrees=(7, 7))[0] == 0      # run-time node counts
+    assert _create(p, 50, degrees=(9, 5))[0] == 4      # above kMaxNodes
+    assert _create(p, 50, degrees=(3, 0))[0] == 1
     q = p.copy()
     q[7] = q[3]
     rc, msg = _create(q, 50)

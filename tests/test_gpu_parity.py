@@ -297,6 +297,41 @@ def test_small_and_degenerate(torch, case):
     assert plan.misses() == 0
 
 
+@pytest.mark.parametrize("deg,prec,nrhs", [((1, 1), "fp64", 1), ((1, 4), "fp64", 4), ((2, 2), "mixed", 1),
+                                            ((3, 4), "fp64", 16), ((5, 5), "mixed", 4), ((4, 7), "fp64", 2),
+                                            ((8, 8), "fp64", 1), ((6, 3), "mixed", 16)])
+def test_run_time_node_counts(torch, deg, prec, nrhs):
+    """Node counts without compiled kernels (read at run time, any 1..8 per
+    direction): forward, adjoint, target gradient and the no-allocation
+    apply against the oracle; the error against the direct sum falls with
+    the order (Thm. errorestimatenested)."""
+    p = inputs.cube_sphere(14)
+    k = 9.0
+    a = inputs.densities(61, nrhs, p.shape[0])
+    g = inputs.densities(62, nrhs, p.shape[0])
+    ac, gc = (a, g) if prec == "fp64" else (as_c64(a), as_c64(g))
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    r = oracle.ifgf(p, ac, k, degrees=deg, grad=True)
+    ref_adj = np.conj(oracle.ifgf(p, np.conj(ac), k, degrees=deg)["out"])
+    plan = make_plan(p, k, prec, degrees=deg, max_nrhs=16, store_levels=0)
+    assert plan.kernel_candidates(nrhs) == {d: ["geometry"] for d in plan.kernel_candidates(nrhs)}
+    x = dev(torch, a, prec)
+    out = plan.apply(x).cpu().numpy()
+    assert par(out, r["out"]) < tol
+    assert par(plan.adjoint(x).cpu().numpy(), ref_adj) < tol
+    got = plan.grad_targets(x, dev(torch, g, prec)).cpu().numpy()
+    want = np.einsum("rn,rnc->nc", np.conj(gc), r["grad"]).real
+    assert par(got, want) < (1e-10 if prec == "fp64" else 1e-4)
+    y = torch.empty_like(x)
+    plan.apply_noalloc(x, y)
+    assert par(y.cpu().numpy(), out) < (1e-14 if prec == "fp64" else 1e-6)
+    assert plan.misses() == 0
+    if deg == (8, 8):
+        d = oracle.direct(p, ac, k)
+        e88, e46 = rel(out, d), rel(oracle.ifgf(p, ac, k, degrees=(4, 6))["out"], d)
+        assert e88 < 1e-5 and e88 < e46 / 10
+
+
 @pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp64", 4), ("fp64", 16), ("mixed", 1), ("mixed", 4),
                                        ("mixed", 16)])
 def test_without_frame_tables(torch, monkeypatch, prec, nrhs):
