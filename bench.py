@@ -556,6 +556,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         result["sphere393216"] = sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log)
         result["graded_adaptive"] = graded_adaptive_extras(torch, ifgf, inputs, oracle, time_fn, log)
+        result["laplace393216"] = laplace_extras(torch, ifgf, inputs, oracle, time_fn, log)
 
     # ---- the oracle on the host cores: the O1 direct sum above, on M of the
     # N targets, extrapolated to one full matvec of all right-hand sides
@@ -643,6 +644,41 @@ def sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log) -> dict:
     del p64
     torch.cuda.empty_cache()
     log(f"sphere393216: {res}")
+    return res
+
+
+def laplace_extras(torch, ifgf, inputs, oracle, time_fn, log) -> dict:
+    """The Laplace kernel (k = 0) on the N = 393216 sphere, the third row of
+    the paper's Table timingsLaplace: constant cone counts per box (reading
+    R5 with a_d = 1), levels chosen for at most 8 points per leaf box; node
+    counts and leaf cones (3,5) 1x2x4 (the Helmholtz default), (4,6) 2x4x8
+    (eps below the paper's) and (5,7) 1x2x4 (eps at the paper's level, node
+    counts read at run time); FP64 and mixed at 1 RHS, eps on 1000 targets,
+    plan time."""
+    w = inputs.WORKLOADS[2]
+    p = w.points()
+    n = p.shape[0]
+    a = w.densities()
+    idx = inputs.error_subset(2, n, 1000)
+    d = oracle.direct(p, a, 0.0, targets=p[idx], skip=idx)
+    res = {"n": n, "kappa": 0.0, "nrhs": 1, "paper_T_acc_s": 16.9, "paper_eps": 1.27e-5}
+    for deg, leaf in (((3, 5), (1, 2)), ((4, 6), (2, 4)), ((5, 7), (1, 2))):
+        for prec in ("fp64", "mixed"):
+            t0 = time.time()
+            plan = ifgf.Plan(p, 0.0, precision=prec, max_nrhs=1, store_levels=0, degrees=deg, leaf=leaf)
+            t_plan = time.time() - t0
+            st = plan.stats()
+            x = torch.from_numpy(a).to(torch.complex128 if prec == "fp64" else torch.complex64).cuda()
+            ms = time_fn(lambda: plan.apply(x), 5)
+            out = plan.apply(x).cpu().numpy()
+            res[f"{prec}_deg{deg[0]}{deg[1]}_leaf{leaf[0]}x{leaf[1]}"] = {
+                "matvecs_per_s": round(1000.0 / ms, 3), "ms_per_matvec": round(ms, 3), "t_plan_s": round(t_plan, 2),
+                "levels": st["D"], "cones": sum(st["n_cones"]), "plan_device_bytes": st["device_bytes"],
+                "eps_vs_direct": float(np.linalg.norm(out[:, idx] - d) / np.linalg.norm(d)),
+                "misses": plan.misses()}
+            del plan, x
+            torch.cuda.empty_cache()
+    log(f"laplace: {res}")
     return res
 
 

@@ -50,7 +50,8 @@ void release(ifgf::DevicePlan& p)
         int cur = -1;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(p.device);
-        (void)hipDeviceSynchronize();
+        // the plan's work on every stream that used it (not the whole device)
+        (void)ifgf::wait_plan_streams(p);
         for (void* q : p.ws_allocs) (void)hipFree(q);
         for (void* q : p.allocs) (void)hipFree(q);
         for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
@@ -477,7 +478,7 @@ static ifgf_status apply_common(ifgf_plan_t plan, const void* a, int32_t nrhs, v
     if (s != IFGF_OK) return s;
     ifgf::DevicePlan& p = plan->p;
     DeviceGuard g(p.device);
-    p.last_stream = (hipStream_t)stream;
+    p.use_stream((hipStream_t)stream);
     hipError_t e = p.use_graph && !p.profiling ? apply_graph(p, a, nrhs, out, adj, (hipStream_t)stream)
                                                : ifgf::run_apply(p, a, nrhs, out, adj, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, adj ? "ifgf_apply_adjoint" : "ifgf_apply");
@@ -491,6 +492,7 @@ ifgf_status ifgf_plan_autotune(ifgf_plan_t plan, int32_t nrhs, void* stream)
     if (nrhs < 1 || nrhs > plan->p.max_nrhs) return fail(IFGF_E_INVALID_ARG, "nrhs out of range");
     ifgf::DevicePlan& p = plan->p;
     DeviceGuard g(p.device);
+    p.use_stream((hipStream_t)stream);
     hipError_t e = ifgf::run_autotune(p, nrhs, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "ifgf_plan_autotune");
     return IFGF_OK;
@@ -564,7 +566,7 @@ ifgf_status ifgf_apply_noalloc(ifgf_plan_t plan, const void* densities, int32_t 
                                             std::to_string(need) + " bytes, more than the " + std::to_string(have) +
                                             "-byte device scratch array; use ifgf_apply");
     DeviceGuard g(p.device);
-    p.last_stream = (hipStream_t)stream;
+    p.use_stream((hipStream_t)stream);
     hipError_t e = ifgf::run_apply_noalloc(p, densities, nrhs, out, false, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "ifgf_apply_noalloc");
     return IFGF_OK;
@@ -578,7 +580,7 @@ static ifgf_status grad_common(ifgf_plan_t plan, const void* densities, const vo
     if (!grad_out) return fail(IFGF_E_INVALID_ARG, "grad_out is NULL");
     ifgf::DevicePlan& p = plan->p;
     DeviceGuard g(p.device);
-    p.last_stream = (hipStream_t)stream;
+    p.use_stream((hipStream_t)stream);
     hipError_t e = ifgf::run_grad(p, densities, grad_out, nrhs, grad_xyz, reuse, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, reuse ? "ifgf_grad_targets_stored" : "ifgf_grad_targets");
     return IFGF_OK;

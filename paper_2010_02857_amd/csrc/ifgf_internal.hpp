@@ -408,6 +408,16 @@ struct DevicePlan {
     uint64_t graph_clock = 0;
     // stream of the last apply or gradient call (synchronised by ifgf_plan_check)
     hipStream_t last_stream = nullptr;
+    // every stream that ran work on the plan's workspaces since they were last
+    // (re)allocated: the work a reallocation or the plan's release waits for
+    std::vector<hipStream_t> used_streams;
+    void use_stream(hipStream_t st)
+    {
+        last_stream = st;
+        for (hipStream_t u : used_streams)
+            if (u == st) return;
+        used_streams.push_back(st);
+    }
     // what the stored cone values hold (for gradient reuse)
     const void* stored_dens = nullptr;
     int stored_nrhs = 0;
@@ -478,6 +488,9 @@ hipError_t run_grad(DevicePlan& p, const void* dens, const void* gout, int nrhs,
 hipError_t run_apply_noalloc(DevicePlan& p, const void* dens, int nrhs, void* out, bool adj, hipStream_t stream);
 // Takes the current device's scratch address (once per device).
 hipError_t scratch_init(int device);
+// Waits for the plan's work on every stream that ran it since its workspaces
+// were last (re)allocated, and on its own streams (not the whole device).
+hipError_t wait_plan_streams(DevicePlan& p);
 size_t scratch_bytes();
 // Scratch bytes an apply of nrhs right-hand sides needs in that mode.
 size_t noalloc_bytes(const DevicePlan& p, int nrhs);

@@ -34,14 +34,26 @@ struct alignas(2 * sizeof(T)) cpx {
 // followed by FP32 sincos.
 template <typename T>
 __device__ inline void expi(double ph, T& c, T& s);
+// A zero phase (every phase of the Laplace kernel, k = 0) skips the sine
+// and cosine: e^0 = 1 exactly, as they would return.
 template <>
 __device__ inline void expi<double>(double ph, double& c, double& s)
 {
+    if (ph == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        return;
+    }
     sincos(ph, &s, &c);
 }
 template <>
 __device__ inline void expi<float>(double ph, float& c, float& s)
 {
+    if (ph == 0.0) {
+        c = 1.0f;
+        s = 0.0f;
+        return;
+    }
     double q = rint(ph * kInv2Pi);
     float red = (float)(ph - q * k2Pi);
     sincosf(red, &s, &c);
@@ -2636,6 +2648,27 @@ inline int rb_for(int nrhs) { return nrhs >= 5 ? 16 : (nrhs >= 2 ? 4 : 1); }
 // Pairs the per-pair value buffer holds: those of the largest tabulated level,
 // and of the largest untabulated one when that fits the budget
 // (IFGF_PVAL_BUDGET_MB, default 32768) at rb right-hand sides.
+}  // namespace
+
+// Waits for the plan's work on every stream that ran it (its callers'
+// streams, its side and capture streams), not for the whole device.
+hipError_t wait_plan_streams(DevicePlan& p)
+{
+    hipError_t e = hipSuccess;
+    for (hipStream_t u : p.used_streams)
+        if (e == hipSuccess) e = hipStreamSynchronize(u);
+    if (e == hipSuccess && p.side) e = hipStreamSynchronize(p.side);
+    if (e == hipSuccess && p.cap_stream) e = hipStreamSynchronize(p.cap_stream);
+    if (e == hipSuccess) {
+        // keep only the latest caller stream: the others have drained
+        p.used_streams.clear();
+        p.used_streams.push_back(p.last_stream);
+    }
+    return e;
+}
+
+namespace {
+
 inline bool compiled_degrees(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6) || (ps == 2 && pa == 3); }
 
 inline int64_t pval_pairs_for(const DevicePlan& p, int rb, size_t ce)
@@ -2662,7 +2695,8 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     if (fresh) *fresh = false;
     if (p.ws_rb >= rb && p.ws_store == store) return hipSuccess;
     if (fresh) *fresh = true;
-    hipError_t e = hipDeviceSynchronize();
+    // the old buffers may still be read by earlier calls' kernels
+    hipError_t e = wait_plan_streams(p);
     if (e != hipSuccess) return e;
     for (void* q : p.ws_allocs) (void)hipFree(q);
     p.ws_allocs.clear();

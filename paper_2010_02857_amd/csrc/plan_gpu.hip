@@ -532,10 +532,10 @@ hipError_t pairs_t(DevicePlan& p, int d, bool ordered)
     L.npairs_ord = 0;
     if (np > 0) k_pair_table<T><<<blocks_for(np), kPB>>>(L, p.pts, p.hp.kappa, np, pr_slot, pr_t, pr_g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!ordered || np == 0) return hipDeviceSynchronize();
+    if (!ordered || np == 0) return hipStreamSynchronize(nullptr);
     // the cone-ordered copy: stable sort of the pairs by slot
     const int64_t ns = H.nslots;
-    if (ns == 0) return hipDeviceSynchronize();
+    if (ns == 0) return hipStreamSynchronize(nullptr);
     DevBuf key, idx, skey, sidx, cnt, ucnt, pcnt, ustart, start, tmp;
     if ((e = key.alloc(np * 4)) != hipSuccess || (e = idx.alloc(np * 4)) != hipSuccess ||
         (e = skey.alloc(np * 4)) != hipSuccess || (e = sidx.alloc(np * 4)) != hipSuccess ||
@@ -595,7 +595,7 @@ hipError_t pairs_t(DevicePlan& p, int d, bool ordered)
     L.pro_slot = pro_slot;
     L.pro_t = pro_t;
     L.pro_g = pro_g;
-    return hipDeviceSynchronize();
+    return hipStreamSynchronize(nullptr);
 }
 
 }  // namespace

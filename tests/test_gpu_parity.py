@@ -756,3 +756,32 @@ def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs, tables):
         assert plan.misses() == 0
     assert par(outs["1"], outs["0"]) < (1e-13 if prec == "fp64" else 1e-6)
     monkeypatch.delenv("IFGF_COUSIN_GEO_PAIRS")
+
+
+def test_streams_and_workspace_reallocation(torch):
+    """Calls on different streams, the second one growing the workspaces:
+    the reallocation waits for the plan's work on the first stream (not for
+    the whole device), and every result equals a fresh plan's."""
+    p = inputs.cube_sphere(16)
+    k = 4.0 * math.pi
+    a1 = inputs.densities(71, 1, p.shape[0])
+    a16 = inputs.densities(72, 16, p.shape[0])
+    ref1 = make_plan(p, k, "fp64", max_nrhs=16).apply(dev(torch, a1, "fp64")).cpu().numpy()
+    ref16 = make_plan(p, k, "fp64", max_nrhs=16).apply(dev(torch, a16, "fp64")).cpu().numpy()
+    plan = make_plan(p, k, "fp64", max_nrhs=16, store_levels=0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    x1, x16 = dev(torch, a1, "fp64"), dev(torch, a16, "fp64")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        y1 = plan.apply(x1)
+    with torch.cuda.stream(s2):
+        s2.wait_stream(s1)      # the caller orders its own buffers; the plan orders its workspaces
+        y16 = plan.apply(x16)
+    torch.cuda.synchronize()
+    assert np.array_equal(y1.cpu().numpy(), ref1)
+    assert np.array_equal(y16.cpu().numpy(), ref16)
+    with torch.cuda.stream(s1):
+        y1b = plan.apply(x1)
+    del plan                     # release waits for the plan's streams
+    torch.cuda.synchronize()
+    assert np.array_equal(y1b.cpu().numpy(), ref1)
