@@ -2391,19 +2391,23 @@ __global__ void __launch_bounds__(kBlock) k_cousin_eval_mfma(KernelConsts kc, Le
     }
 }
 
-// Phase 1 for batched right-hand sides on the matrix cores (FP32): a
-// wavefront takes 16 consecutive pairs in cone order as the rows of 16 x 16
-// x 4 MFMA tiles; the rows that share a cone (usually all) form one tile
-// group with that cone's values as the B operand (K = its nodes, columns the
-// real and imaginary parts of the RB right-hand sides).  Each row is
-// multiplied by its centred factor and stored once, at the pair's place.
-template <int PS, int PA, int RB>
+// Phase 1 for batched right-hand sides on the matrix cores: a wavefront
+// takes 16 consecutive pairs in cone order as the rows of MFMA tiles; the
+// rows that share a cone (usually all) form one tile group with that cone's
+// values as the B operand (K = its nodes, columns the real and imaginary
+// parts of the RB right-hand sides).  Each row is multiplied by its centred
+// factor and stored once, at the pair's place.  FP32 uses 16 x 16 x 4 tiles;
+// FP64 the 16 x 16 x 4 or, with at most 8 real columns, the four-block
+// 4 x 4 x 4 instruction (the tiles of mfma_tile with CW columns).
+template <typename T, int PS, int PA, int RB>
 __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConsts kc, LevelDev L,
-                                                                     const cpx<float>* __restrict__ F,
-                                                                     cpx<float>* __restrict__ pval)
+                                                                     const cpx<T>* __restrict__ F,
+                                                                     cpx<T>* __restrict__ pval)
 {
     constexpr int NC = 2 * RB;
-    constexpr int NT = (NC + 15) / 16;
+    constexpr int CW = (sizeof(T) == 8 && NC <= 8) ? 4 : 16;
+    constexpr int NT = (NC + CW - 1) / CW;
+    constexpr int NO = CW == 16 ? 4 : 1;       // output elements per lane and tile
     constexpr int W = kBlock / 64;
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
     constexpr int P = PS * PA * PA;
@@ -2413,45 +2417,47 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConst
     const long long no = L.npairs_ord;
     const long long i0 = ((long long)xcd_block(blockIdx.x, gridDim.x) * W + wv) * 16;
     if (i0 >= no) return;                      // whole wavefront leaves
-    const int row = lane & 15, q = lane >> 4, col = lane & 15;
+    const int row = lane & 15, q = lane >> 4, col = lane % CW;
     const long long i = i0 + row;
     const bool valid = i < no;
     const long long ic = valid ? i : i0;
     const int slot = valid ? L.pro_slot[ic] : -1;
-    const float* pt = (const float*)L.pro_t;
-    const float* pg = (const float*)L.pro_g;
-    float Ls[PS], Lt[PA], Lpv[PA];
-    lagrange<float, PS>((double)pt[ic], kc.cs, Ls);
-    lagrange<float, PA>((double)pt[no + ic], kc.ca, Lt);
-    lagrange<float, PA>((double)pt[2 * no + ic], kc.ca, Lpv);
-    const float gr = pg[ic], gi = (kc.adj ? -1.f : 1.f) * pg[no + ic];
+    const T* pt = (const T*)L.pro_t;
+    const T* pg = (const T*)L.pro_g;
+    T Ls[PS], Lt[PA], Lpv[PA];
+    lagrange<T, PS>((double)pt[ic], kc.cs, Ls);
+    lagrange<T, PA>((double)pt[no + ic], kc.ca, Lt);
+    lagrange<T, PA>((double)pt[2 * no + ic], kc.ca, Lpv);
+    const T gr = pg[ic], gi = (kc.adj ? (T)-1 : (T)1) * pg[no + ic];
     const long long e = L.pr_order[ic];       // -1: a placeholder, not stored
-    const float* Ff = (const float*)F;
-    float* pf = (float*)pval;
+    const T* Ff = (const T*)F;
+    T* pf = (T*)pval;
     unsigned long long todo = __ballot(lane < 16 && valid);
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const int key = __shfl(slot, leader, 64);
         const bool in = valid && slot == key;
         todo &= ~__ballot(lane < 16 && in);
-        float Lsm[PS];
+        T Lsm[PS];
 #pragma unroll
-        for (int a = 0; a < PS; ++a) Lsm[a] = in ? Ls[a] : 0.f;
-        float b[NT][NK];
-        mfma_load_b<PS, PA, NC, NT>(Ff + (size_t)key * P * NC, q, col, b);
-        mf4 cm[NT];
-        mfma_tile<PS, PA, NT>(b, Lsm, Lt, Lpv, q, cm);
+        for (int a = 0; a < PS; ++a) Lsm[a] = in ? Ls[a] : (T)0;
+        T b[NT][NK];
+        mfma_load_b<PS, PA, NC, NT, CW>(Ff + (size_t)key * P * NC, q, col, b);
+        macc<T, CW> cm[NT];
+        mfma_tile<PS, PA, NT, CW>(b, Lsm, Lt, Lpv, q, cm);
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-            const int r = 4 * q + ii;
-            const float rgr = __shfl(gr, r, 64), rgi = __shfl(gi, r, 64);
+        for (int ii = 0; ii < NO; ++ii) {
+            const int r = mfma_out_row<CW, T>(lane, ii);
+            const T rgr = __shfl(gr, r, 64), rgi = __shfl(gi, r, 64);
             const int rin = __shfl((int)in, r, 64);
             const long long re = __shfl(e, r, 64);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const float v = cm[t][ii];
-                const float pv = __shfl_xor(v, 1, 64);
-                const int cg = 16 * t + col;
+                T v;
+                if constexpr (CW == 16) v = cm[t][ii];
+                else v = cm[t];
+                const T pv = __shfl_xor(v, 1, 64);
+                const int cg = CW * t + col;
                 if (rin && re >= 0 && cg < NC)
                     pf[(size_t)re * NC + cg] = (col & 1) == 0 ? v * rgr - pv * rgi : pv * rgi + v * rgr;
             }
@@ -3024,10 +3030,10 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
                 k_cousin_pairs_values<T, PS, PA><<<grid_for((size_t)p.L[d].npairs_ord / kPairQuad), kBlock, 0, st>>>(
                     kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
                 done = true;
-            } else if constexpr (std::is_same<T, float>::value && PA >= 4) {
+            } else if constexpr (PA >= 4) {
                 const size_t waves = ((size_t)p.L[d].npairs_ord + 15) / 16;
-                k_cousin_pairs_values_mfma<PS, PA, RB><<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock,
-                                                         0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
+                k_cousin_pairs_values_mfma<T, PS, PA, RB><<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)),
+                                                            kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d], (C*)p.pval);
                 done = true;
             }
             if (done)
