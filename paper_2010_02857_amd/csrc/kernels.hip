@@ -2826,8 +2826,11 @@ int c2p_default(const DevicePlan& p, int d)
             return false;
         };
         const bool full = (double)p.hp.L[d - 1].nslots >= box_fill_min(RB) * kBoxTile * (double)p.L[d].ntiles;
+        // with batched right-hand sides (and always in FP64) the kernel with
+        // the accumulators in LDS measured faster; at 1 RHS in FP32 the one
+        // with register accumulators
+        if (has(kC2PBoxAcc) && full && (std::is_same<T, double>::value || RB >= 4)) return kC2PBoxAcc;
         if (has(kC2PBoxes) && full) return kC2PBoxes;
-        if (std::is_same<T, double>::value && has(kC2PBoxAcc) && full) return kC2PBoxAcc;
         if (has(kC2PMfma)) return kC2PMfma;
         if (has(kC2PMfmaGeometry)) return kC2PMfmaGeometry;
         if (has(kC2PLds)) return kC2PLds;
