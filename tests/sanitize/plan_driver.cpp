@@ -1,6 +1,7 @@
 // Builds host-only IFGF plans (no GPU use) through the C ABI, for the
 // ThreadSanitizer run of the threaded host plan builder: an equiangular
-// cube-sphere at two wavenumbers and a random cloud, printing the counts.
+// cube-sphere at two wavenumbers, a random cloud, and both again on an
+// adaptive octree, printing the counts.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -28,10 +29,11 @@ static std::vector<double> cube_sphere(int n)
     return p;
 }
 
-static int run(const std::vector<double>& p, double k, int levels)
+static int run(const std::vector<double>& p, double k, int levels, int leaf_max = 0)
 {
     ifgf_options o{};
     o.host_only = 1;
+    o.leaf_max = leaf_max;
     ifgf_plan_t plan = nullptr;
     ifgf_status s = ifgf_plan_create(p.data(), (int64_t)(p.size() / 3), k, levels, nullptr, &o, &plan);
     if (s != IFGF_OK) {
@@ -57,5 +59,7 @@ int main()
     std::vector<double> c(3 * 8000);
     for (double& x : c) x = u(g);
     bad |= run(c, 40.0, 6);
+    bad |= run(cube_sphere(32), 8.0 * 3.14159265358979323846, 6, 12);
+    bad |= run(c, 40.0, 6, 20);
     return bad;
 }
