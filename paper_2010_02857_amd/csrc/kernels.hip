@@ -1227,21 +1227,39 @@ __device__ inline void mfma_tile(const T (*b)[PS * PA + (PS * PA * (PA - 4) + 3)
         if constexpr (CW == 16) c[t] = mvec<T>{(T)0, (T)0, (T)0, (T)0};
         else c[t] = (T)0;
     }
+    // the (s, theta) products, kept for the tail
+    T pab[NAB];
 #pragma unroll
     for (int ab = 0; ab < NAB; ++ab) {
         const int a = ab / PA, bb = ab - a * PA;
-        const T w = Ls[a] * Lt[bb] * lq;
+        pab[ab] = Ls[a] * Lt[bb];
+        const T w = pab[ab] * lq;
 #pragma unroll
         for (int t = 0; t < NT; ++t) c[t] = mfma_step<CW>(w, b[t][ab], c[t]);
     }
+    // tail step jt: lane quarter q takes node (ab, c) = (m / (PA - 4),
+    // 4 + m % (PA - 4)), m = 4 jt + q, so its product is one of at most four
+    // consecutive entries of pab (from index lo) and one of the PA - 4 last
+    // phi weights
 #pragma unroll
     for (int jt = 0; jt < KTAIL; ++jt) {
         const int m = 4 * jt + q;
+        constexpr int R = PA - 4;
+        const int lo = (4 * jt) / R;
+        const int abm = m / R, cc = m - abm * R;
         T w = (T)0;
         if (m < NREM) {
-            const int abm = m / (PA - 4), cc = 4 + (m - abm * (PA - 4));
-            const int a = abm / PA, bb = abm - a * PA;
-            w = pick<PS>(Ls, a) * pick<PA>(Lt, bb) * pick<PA>(Lpv, cc);
+            const int span = (4 * jt + 3) / R - lo + 1;
+            T pv = pab[lo];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                if (j < span && lo + j < NAB) {
+                    T y = pab[lo + j];
+                    asm("" : "+v"(y));
+                    pv = abm - lo == j ? y : pv;
+                }
+            }
+            w = pv * pick<R>(Lpv + 4, cc);
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) c[t] = mfma_step<CW>(w, b[t][NAB + jt], c[t]);
@@ -1279,8 +1297,8 @@ __device__ inline void mfma_load_b(const T* __restrict__ Fcs, int q, int col,
 // Epilogue of a tile: rows mfma_row(q, i), column col of each tile; multiply by the
 // row's ratio (complex: columns 2r, 2r+1 are re, im of right-hand side r) and
 // accumulate into the wavefront's LDS values of the parent slot.
-template <int NC, int NT, int CW = 16, typename T>
-__device__ inline void mfma_epilogue(const macc<T, CW>* c, int lane, int t0, int cnt, const int* rownode,
+template <int NC, int NT, int CW = 16, typename T, typename I>
+__device__ inline void mfma_epilogue(const macc<T, CW>* c, int lane, int t0, int cnt, const I* rownode,
                                      const T* ratio_re, const T* ratio_im, T* acc)
 {
     const int col = lane % CW;
@@ -1454,12 +1472,17 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
 }
 
 // The same on levels without tabulated frames: every lane computes the
-// child-frame geometry of its interpolation points in FP64 (as
-// k_child_to_parent does); the wavefront then sorts the octant's points by
-// child cone with ballots ("groups"), looks the groups' cones up in
-// parallel (one lane per group), and runs the groups' MFMA tiles.  (Also
-// loading the next group's operands during the current group's tiles was
-// measured 20% slower in FP64 at 4 RHS: its registers cost a wave per SIMD.)
+// child-frame geometry of interpolation points in FP64 (as k_child_to_parent
+// does).  The (octant, point) pairs of the slot's children are taken in
+// chunks of CH consecutive pairs, so the lanes stay busy when a frame's P
+// points do not fill whole passes of 64; the wavefront sorts a chunk's
+// points by (octant, child cone) with ballots ("groups"), looks the groups'
+// cones up in parallel (one lane per group), and runs the groups' MFMA
+// tiles.  Every point of an octant is in one group, and the groups come in
+// octant order, so each parent point receives its octants' terms in octant
+// order.  (Loading the next group's operands during the current group's
+// tiles was measured no faster in FP32 at 4 RHS, and in FP64 its registers
+// cost a wave per SIMD.)
 template <typename T, int PS, int PA, int RB, int W>
 __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                       const cpx<T>* __restrict__ Fc,
@@ -1470,16 +1493,20 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
     constexpr int CW = (sizeof(T) == 8 && NC <= 8) ? 4 : 16;   // columns per tile
     constexpr int NT = (NC + CW - 1) / CW;
     constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
+    // lane passes per chunk (one with 16 right-hand sides, whose
+    // accumulators leave less LDS)
+    constexpr int NH = RB >= 16 ? 1 : 3;
+    constexpr int CH = 64 * NH;                // (octant, point) pairs per chunk
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
-    static_assert(P <= 128, "two passes of 64 points");
+    static_assert(P <= 128, "point indices");
     __shared__ T accs[W][P * NC];
-    __shared__ T nt[W][P][3];                  // local coordinates of every point
-    __shared__ T nrr[W][P], nri[W][P];         // ratio of every point
-    __shared__ int rown[W][P];                 // points in group order
-    __shared__ T rre[W][P], rim[W][P];         // their ratios
-    __shared__ unsigned gkey[W][P];            // child cone of each group
-    __shared__ int goff[W][P + 1];             // first row of each group
-    __shared__ int gcs[W][P];                  // child slot of each group, -1 missing
+    __shared__ T rts[W][CH][3];                // local coordinates, in group order
+    __shared__ T rre[W][CH], rim[W][CH];       // ratios, in group order
+    __shared__ uint8_t rown[W][CH];            // parent point of each row
+    __shared__ unsigned gkey[W][CH];           // child cone of each group
+    __shared__ uint8_t goct[W][CH];            // octant of each group
+    __shared__ int16_t goff[W][CH + 1];        // first row of each group
+    __shared__ int gcs[W][CH];                 // child slot of each group, -1 missing
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1495,17 +1522,28 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
     const int pcell = pcone / Lp.ns, pis = pcone - pcell * Lp.ns;
     const double half = 0.5 * Lc.H;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    // the octants with a child, in order, packed 4 bits each
+    unsigned olist = 0;
+    int m = 0;
+    for (int o = 0; o < 8; ++o)
+        if (Lc.child_of[(size_t)j * 8 + o] >= 0) olist |= (unsigned)o << (4 * m++);
+    const int E = m * P;
 
-    for (int o = 0; o < 8; ++o) {
-        const int k = Lc.child_of[(size_t)j * 8 + o];
-        if (k < 0) continue;
-        const double ov[3] = {(o & 1) ? half : -half, (o & 2) ? half : -half, (o & 4) ? half : -half};
-        // geometry of the points nu = lane and nu = lane + 64
-        unsigned key[2] = {0xffffffffu, 0xffffffffu};
+    for (int c0 = 0; c0 < E; c0 += CH) {
+        // geometry of the pairs c0 + lane + 64 h
+        unsigned key[NH];
+        int oi[NH];
+        T tl[NH][3], gr[NH], gi[NH];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int nu = lane + 64 * h;
-            if (nu < P) {
+        for (int h = 0; h < NH; ++h) {
+            const int e = c0 + lane + 64 * h;
+            key[h] = 0xffffffffu;
+            oi[h] = -1;
+            if (e < E) {
+                const int ii = e / P, nu = e - ii * P;
+                const int o = (int)((olist >> (4 * ii)) & 15u);
+                oi[h] = ii;
+                const double ov[3] = {(o & 1) ? half : -half, (o & 2) ? half : -half, (o & 4) ? half : -half};
                 const int a = nu / (PA * PA), bc = nu - a * PA * PA;
                 const double rr = Lp.node_r[pis * PS + a];
                 const double* dir = &Lp.node_dir[((size_t)pcell * PA * PA + bc) * 3];
@@ -1516,59 +1554,75 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
                 ConeLoc cl;
                 cone_locate(v[0], v[1], v[2], Lc.h, Lc.ds, Lc.dang, Lc.ns, Lc.nc, cl);
                 key[h] = (unsigned)(cl.cell * Lc.ns + cl.is);
-                nt[wv][nu][0] = (T)cl.ts;
-                nt[wv][nu][1] = (T)cl.tt;
-                nt[wv][nu][2] = (T)cl.tp;
+                tl[h][0] = (T)cl.ts;
+                tl[h][1] = (T)cl.tt;
+                tl[h][2] = (T)cl.tp;
                 const double num = (ov[0] * ov[0] + ov[1] * ov[1] + ov[2] * ov[2]) -
                                    2.0 * (y0 * ov[0] + y1 * ov[1] + y2 * ov[2]);
                 const double diff = num / (cl.r + ry);
                 T cph, sph;
                 expi<T>(kc.kappa * diff, cph, sph);
                 const T mag = (T)(ry / cl.r);
-                nrr[wv][nu] = mag * cph;
-                nri[wv][nu] = mag * sph;
+                gr[h] = mag * cph;
+                gi[h] = mag * sph;
+            } else {
+                tl[h][0] = tl[h][1] = tl[h][2] = gr[h] = gi[h] = (T)0;
             }
         }
-        wave_lds_fence();
-        // the groups: points sorted by child cone, in order of first appearance
-        bool un0 = lane < P, un1 = lane + 64 < P;
+        // the groups: pairs sorted by (octant, child cone), in order of first
+        // appearance
+        bool un[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) un[h] = oi[h] >= 0;
         int ng = 0, base = 0;
         for (;;) {
-            const unsigned long long m0 = __ballot(un0), m1 = __ballot(un1);
-            if (!m0 && !m1) break;
-            const int leader = m0 ? (__ffsll((long long)m0) - 1) : 64 + (__ffsll((long long)m1) - 1);
-            const unsigned lkey = __shfl(leader < 64 ? key[0] : key[1], leader & 63, 64);
-            const bool in0 = un0 && key[0] == lkey, in1 = un1 && key[1] == lkey;
-            const unsigned long long g0 = __ballot(in0), g1 = __ballot(in1);
-            const int c0n = __popcll(g0);
-            if (in0) {
-                const int r = base + __popcll(g0 & lt_mask);
-                rown[wv][r] = lane;
-                rre[wv][r] = nrr[wv][lane];
-                rim[wv][r] = nri[wv][lane];
+            unsigned long long mk[NH];
+            int leader = -1;
+#pragma unroll
+            for (int h = NH - 1; h >= 0; --h) {
+                mk[h] = __ballot(un[h]);
+                if (mk[h]) leader = 64 * h + (__ffsll((long long)mk[h]) - 1);
             }
-            if (in1) {
-                const int r = base + c0n + __popcll(g1 & lt_mask);
-                rown[wv][r] = lane + 64;
-                rre[wv][r] = nrr[wv][lane + 64];
-                rim[wv][r] = nri[wv][lane + 64];
+            if (leader < 0) break;
+            unsigned lk = 0;
+            int lo = 0;
+#pragma unroll
+            for (int h = 0; h < NH; ++h)
+                if (leader / 64 == h) {
+                    lk = __shfl(key[h], leader & 63, 64);
+                    lo = __shfl(oi[h], leader & 63, 64);
+                }
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                const bool in = un[h] && key[h] == lk && oi[h] == lo;
+                const unsigned long long g = __ballot(in);
+                if (in) {
+                    const int r = base + __popcll(g & lt_mask);
+                    const int e = c0 + lane + 64 * h;
+                    rown[wv][r] = (uint8_t)(e - oi[h] * P);
+                    rts[wv][r][0] = tl[h][0];
+                    rts[wv][r][1] = tl[h][1];
+                    rts[wv][r][2] = tl[h][2];
+                    rre[wv][r] = gr[h];
+                    rim[wv][r] = gi[h];
+                }
+                un[h] = un[h] && !in;
+                if (lane == 0 && h == 0) {
+                    gkey[wv][ng] = lk;
+                    goct[wv][ng] = (uint8_t)((olist >> (4 * lo)) & 15u);
+                    goff[wv][ng] = (int16_t)base;
+                }
+                base += __popcll(g);
             }
-            if (lane == 0) {
-                gkey[wv][ng] = lkey;
-                goff[wv][ng] = base;
-            }
-            base += c0n + __popcll(g1);
             ++ng;
-            un0 = un0 && !in0;
-            un1 = un1 && !in1;
         }
-        if (lane == 0) goff[wv][ng] = base;
+        if (lane == 0) goff[wv][ng] = (int16_t)base;
         wave_lds_fence();
         // the groups' child slots, looked up together
         for (int g = lane; g < ng; g += 64) {
             const unsigned kk = gkey[wv][g];
             const int cell = (int)(kk / (unsigned)Lc.ns), is = (int)(kk - (unsigned)cell * Lc.ns);
-            const int cs = lookup(Lc, k, cell, is);
+            const int cs = lookup(Lc, Lc.child_of[(size_t)j * 8 + goct[wv][g]], cell, is);
             gcs[wv][g] = cs;
             if (cs < 0) atomicAdd(kc.miss, (unsigned long long)(goff[wv][g + 1] - goff[wv][g]));
         }
@@ -1584,10 +1638,10 @@ __global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConst
                 T Ls[PS], Lt[PA], Lpv[PA];
                 const int rr = t0 + row;
                 if (rr < cnt) {
-                    const int nu = rown[wv][g0 + rr];
-                    lagrange<T, PS>((double)nt[wv][nu][0], kc.cs, Ls);
-                    lagrange<T, PA>((double)nt[wv][nu][1], kc.ca, Lt);
-                    lagrange<T, PA>((double)nt[wv][nu][2], kc.ca, Lpv);
+                    const T* tr = rts[wv][g0 + rr];
+                    lagrange<T, PS>((double)tr[0], kc.cs, Ls);
+                    lagrange<T, PA>((double)tr[1], kc.ca, Lt);
+                    lagrange<T, PA>((double)tr[2], kc.ca, Lpv);
                 } else {
 #pragma unroll
                     for (int i = 0; i < PS; ++i) Ls[i] = (T)0;
