@@ -97,6 +97,10 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
     p.zero_cone = m;
     if ((e = hipMemset(m, 0, zb)) != hipSuccess) return e;
     p.L.assign(hp.D + 1, LevelDev{});
+    // device bytes the cone orders of the levels without pair tables may
+    // take (IFGF_GEO_ORDER_BUDGET_MB, default 16384; 0: none)
+    double geo_order_budget = 16384.0 * 1024.0 * 1024.0;
+    if (const char* v = std::getenv("IFGF_GEO_ORDER_BUDGET_MB")) geo_order_budget = std::atof(v) * 1024.0 * 1024.0;
     for (int d = 1; d <= hp.D; ++d) {
         HostLevel& H = hp.L[d];
         LevelDev& L = p.L[d];
@@ -157,6 +161,12 @@ hipError_t upload_plan(ifgf::DevicePlan& p)
             const long long* po = nullptr;
             if ((e = upload(p, off, &po)) != hipSuccess) return e;
             p.pair_off[d] = po;
+            // without a cone-ordered pair table: the pairs in cone order, for the
+            // matrix-core evaluation of batched right-hand sides
+            if (!(H.use_pairs && H.pairs_ordered) && p.max_nrhs >= 4 && geo_order_budget > 0) {
+                if ((e = build_pair_order_device(p, d, geo_order_budget)) != hipSuccess) return e;
+                geo_order_budget -= 4.0 * (double)p.ngo[d];
+            }
         }
         L.use_pairs = H.use_pairs ? 1 : 0;
         if (H.use_pairs && H.pairs_device) {

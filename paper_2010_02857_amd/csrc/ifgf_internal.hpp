@@ -355,6 +355,12 @@ struct DevicePlan {
     const long long* pair_off[IFGF_MAX_LEVELS + 1] = {};
     int64_t npairs_all[IFGF_MAX_LEVELS + 1] = {};
     int64_t pval_pairs = 0;     // pairs the pval workspace holds
+    // levels without a pair table: the pairs with a cone in cone order, each
+    // as its target point (low 24 bits) and its cousin's index in the target
+    // box's cousin list (high 8 bits), runs of one cone padded to kPairQuad
+    // entries with 0xffffffff (null: not built)
+    const uint32_t* go_ord[IFGF_MAX_LEVELS + 1] = {};
+    int64_t ngo[IFGF_MAX_LEVELS + 1] = {};
     std::vector<void*> allocs;
     size_t tree_bytes = 0;
     // workspaces, sized for `ws_rb` right-hand sides per pass
@@ -464,6 +470,11 @@ hipError_t run_apply(DevicePlan& p, const void* dens, int nrhs, void* out, bool 
 // Level d's cousin-target pair table (and with `ordered` its cone-ordered
 // copy) computed in device memory from the uploaded level (plan_gpu.hip).
 hipError_t build_pairs_device(DevicePlan& p, int d, bool ordered);
+// Level d's pairs (of a level without a pair table) in cone order, as
+// go_ord[d] / ngo[d] (plan_gpu.hip).  Leaves go_ord[d] null where a pair has
+// no cone, where the points or cousin lists do not fit the packing, or
+// where `budget` bytes would not hold the order.
+hipError_t build_pair_order_device(DevicePlan& p, int d, double budget);
 // Allocates the workspaces an apply with nrhs right-hand sides needs (so
 // that the apply itself allocates nothing and can be captured).
 hipError_t run_prepare(DevicePlan& p, int nrhs);

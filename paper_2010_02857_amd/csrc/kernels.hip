@@ -2519,6 +2519,124 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConst
     }
 }
 
+// Phase 1 for batched right-hand sides on levels without a pair table, on the
+// matrix cores: the pairs in cone order (go_ord), 64 per wavefront.  Every
+// lane takes one pair -- its target, its cousin, the pair's place in the
+// value buffer, the cone holding the target, the target's local coordinates
+// in it and G(x_t, x_c), all in FP64 as k_cousin_pairs_geo does -- and the
+// wavefront then runs the pairs as four tiles of 16 rows, those of one cone
+// (usually all) in one group with that cone's values as the B operand, as
+// k_cousin_pairs_values_mfma does.  Each row's value times its factor is
+// stored once, at the pair's place; phase 2 is k_cousin_pairs_sum_geo.
+template <typename T, int PS, int PA, int RB>
+__global__ void __launch_bounds__(kBlock) k_cousin_pairs_go_mfma(KernelConsts kc, LevelDev L,
+                                                                 const double* __restrict__ pts,
+                                                                 const long long* __restrict__ pair_off,
+                                                                 const uint32_t* __restrict__ ord, long long no,
+                                                                 const cpx<T>* __restrict__ F,
+                                                                 cpx<T>* __restrict__ pval)
+{
+    constexpr int NC = 2 * RB;
+    constexpr int CW = (sizeof(T) == 8 && NC <= 8) ? 4 : 16;
+    constexpr int NT = (NC + CW - 1) / CW;
+    constexpr int NO = CW == 16 ? 4 : 1;       // output elements per lane and tile
+    constexpr int W = kBlock / 64;
+    constexpr int NK = PS * PA + (PS * PA * (PA - 4) + 3) / 4;
+    constexpr int P = PS * PA * PA;
+    static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
+    __shared__ int sslot[W][64];               // cone of each pair, -1: none
+    __shared__ long long splace[W][64];        // its place in the value buffer
+    __shared__ T stc[W][3][64];                // local coordinates
+    __shared__ T sgr[W][64], sgi[W][64];       // G(x_t, x_c)
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long i0 = ((long long)xcd_block(blockIdx.x, gridDim.x) * W + wv) * 64;
+    if (i0 >= no) return;                      // whole wavefront leaves
+    T* pf = (T*)pval;
+    {
+        const long long i = i0 + lane;
+        const uint32_t v = i < no ? ord[i] : 0xffffffffu;
+        int slot = -1;
+        long long place = -1;
+        T t0 = (T)0, t1 = (T)0, t2 = (T)0, gr = (T)0, gi = (T)0;
+        if (v != 0xffffffffu) {
+            const int tp = (int)(v & 0xffffffu), ci = (int)(v >> 24);
+            const int tb = L.pt_box[tp];
+            const int b0 = L.box_start[tb];
+            const int nT = L.box_start[tb + 1] - b0;
+            const int c = L.cou[L.cou_start[tb] + ci];
+            place = pair_off[tb] + (long long)ci * nT + (tp - b0);
+            ConeLoc cl;
+            cone_locate(pts[3 * tp] - L.box_ctr[3 * c], pts[3 * tp + 1] - L.box_ctr[3 * c + 1],
+                        pts[3 * tp + 2] - L.box_ctr[3 * c + 2], L.h, L.ds, L.dang, L.ns, L.nc, cl);
+            slot = lookup(L, c, cl.cell, cl.is);
+            if (slot < 0) {
+                // (the order holds only pairs whose cone the plan found)
+                atomicAdd(kc.miss, 1ull);
+                for (int r = 0; r < NC; ++r) pf[(size_t)place * NC + r] = (T)0;
+                place = -1;
+            } else {
+                t0 = (T)cl.ts;
+                t1 = (T)cl.tt;
+                t2 = (T)cl.tp;
+                T cs, sn;
+                expi<T>(kc.kappa * cl.r, cs, sn);
+                const T inv = (T)(kInv4Pi / cl.r);
+                gr = cs * inv;
+                gi = sn * inv;
+            }
+        }
+        sslot[wv][lane] = slot;
+        splace[wv][lane] = place;
+        stc[wv][0][lane] = t0;
+        stc[wv][1][lane] = t1;
+        stc[wv][2][lane] = t2;
+        sgr[wv][lane] = gr;
+        sgi[wv][lane] = gi;
+    }
+    wave_lds_fence();
+    const int row = lane & 15, q = lane >> 4, col = lane % CW;
+    const T* Ff = (const T*)F;
+    for (int r0 = 0; r0 < 64; r0 += 16) {
+        const int rs = sslot[wv][r0 + row];
+        T Ls[PS], Lt[PA], Lpv[PA];
+        lagrange<T, PS>((double)stc[wv][0][r0 + row], kc.cs, Ls);
+        lagrange<T, PA>((double)stc[wv][1][r0 + row], kc.ca, Lt);
+        lagrange<T, PA>((double)stc[wv][2][r0 + row], kc.ca, Lpv);
+        unsigned long long todo = __ballot(lane < 16 && rs >= 0);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int key = __shfl(rs, leader, 64);
+            const bool in = rs >= 0 && rs == key;
+            todo &= ~__ballot(lane < 16 && in);
+            T Lsm[PS];
+#pragma unroll
+            for (int a = 0; a < PS; ++a) Lsm[a] = in ? Ls[a] : (T)0;
+            T b[NT][NK];
+            mfma_load_b<PS, PA, NC, NT, CW>(Ff + (size_t)key * P * NC, q, col, b);
+            macc<T, CW> cm[NT];
+            mfma_tile<PS, PA, NT, CW>(b, Lsm, Lt, Lpv, q, cm);
+#pragma unroll
+            for (int ii = 0; ii < NO; ++ii) {
+                const int r = r0 + mfma_out_row<CW, T>(lane, ii);
+                const bool rin = sslot[wv][r] == key;
+                const long long re = splace[wv][r];
+                const T rgr = sgr[wv][r], rgi = sgi[wv][r];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    T v;
+                    if constexpr (CW == 16) v = cm[t][ii];
+                    else v = cm[t];
+                    const T pv = __shfl_xor(v, 1, 64);
+                    const int cg = CW * t + col;
+                    if (rin && re >= 0 && cg < NC)
+                        pf[(size_t)re * NC + cg] = (col & 1) == 0 ? v * rgr - pv * rgi : pv * rgi + v * rgr;
+                }
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- gradients
 
 // d/dx of the near field: sum_j a_j G(x, x_j) (i k - 1/r) (x - x_j) / r,
@@ -3009,6 +3127,14 @@ inline bool cousin_geo_pairs_enabled()
     return !(v && *v && std::atoi(v) == 0);
 }
 
+// Cousin pairs of levels without a pair table in cone order on the matrix
+// cores (batched right-hand sides): on unless IFGF_COUSIN_GEO_ORDER=0.
+inline bool cousin_geo_order_enabled()
+{
+    const char* v = std::getenv("IFGF_COUSIN_GEO_ORDER");
+    return !(v && *v && std::atoi(v) == 0);
+}
+
 // Two-phase cousin evaluation for one right-hand side: on unless
 // IFGF_COUSIN_TWO_PHASE=0.
 inline bool cousin_two_phase_enabled()
@@ -3096,6 +3222,20 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
             if (done)
                 k_cousin_pairs_sum<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.pval, (C*)p.out_m);
         }
+        if constexpr (RB >= 4 && PA >= 4) {
+            // the pairs in cone order on the matrix cores, geometry per pair
+            // (levels without a cone-ordered pair table)
+            if (!done && p.go_ord[d] && p.pval && p.pair_off[d] && p.npairs_all[d] <= p.pval_pairs &&
+                cousin_geo_pairs_enabled() && cousin_geo_order_enabled()) {
+                const size_t waves = ((size_t)p.ngo[d] + 63) / 64;
+                k_cousin_pairs_go_mfma<T, PS, PA, RB><<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock,
+                                                        0, st>>>(kc, p.L[d], p.pts, p.pair_off[d], p.go_ord[d],
+                                                                 p.ngo[d], (const C*)p.F[d], (C*)p.pval);
+                k_cousin_pairs_sum_geo<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pair_off[d],
+                                                                              (const C*)p.pval, (C*)p.out_m);
+                done = true;
+            }
+        }
         if (done) {
         } else if (p.L[d].use_pairs && p.pval && p.L[d].npairs_cou <= p.pval_pairs && cousin_geo_pairs_enabled() &&
                    hp.n < 64 * (int64_t)hp.L[d].nbox) {
@@ -3109,7 +3249,7 @@ void cousin_stage(DevicePlan& p, const KernelConsts& kc, int d, bool grad, hipSt
             k_cousin_eval_pairs<T, PS, PA, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], (const C*)p.F[d],
                                                                                (C*)p.out_m);
         } else if (p.pval && p.pair_off[d] && p.npairs_all[d] <= p.pval_pairs && cousin_geo_pairs_enabled()) {
-            // two phases with the geometry computed per pair
+            // two phases with the geometry computed per pair, one thread per pair
             k_cousin_pairs_geo<T, PS, PA, RB><<<grid_for((size_t)p.npairs_all[d]), kBlock, 0, st>>>(
                 kc, p.L[d], p.pts, p.pair_off[d], p.npairs_all[d], (const C*)p.F[d], (C*)p.pval);
             k_cousin_pairs_sum_geo<T, RB><<<grid_for(n), kBlock, 0, st>>>(kc, p.L[d], p.pair_off[d], (const C*)p.pval,

@@ -598,7 +598,128 @@ hipError_t pairs_t(DevicePlan& p, int d, bool ordered)
     return hipStreamSynchronize(nullptr);
 }
 
+// One thread per (target box T, cousin c, target t) pair of a level without
+// a pair table, at entry pair_off[T] + c n_T + t: the slot of the cousin's
+// cone that holds the target (the sort key; pairs without one sort last and
+// are counted) and the pair packed as (target point, c).
+__global__ void __launch_bounds__(kPB) k_go_keys(LevelDev L, const double* __restrict__ pts,
+                                                 const long long* __restrict__ pair_off, int64_t np,
+                                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                 int32_t* __restrict__ cnt, unsigned long long* __restrict__ nmiss)
+{
+    GRID_LOOP(e, np) {
+        const int tb = owner(pair_off, L.nbox, e);
+        const int b0 = L.box_start[tb];
+        const int nT = L.box_start[tb + 1] - b0;
+        const int64_t rel = e - pair_off[tb];
+        const int ci = (int)(rel / nT), t = (int)(rel - (int64_t)ci * nT);
+        const int c = L.cou[L.cou_start[tb] + ci];
+        const int j = b0 + t;
+        ConeLoc cl;
+        cone_locate(pts[3 * j] - L.box_ctr[3 * c], pts[3 * j + 1] - L.box_ctr[3 * c + 1],
+                    pts[3 * j + 2] - L.box_ctr[3 * c + 2], L.h, L.ds, L.dang, L.ns, L.nc, cl);
+        const int s = lookup(L, c, cl.cell, cl.is);
+        key[e] = s >= 0 ? (uint32_t)s : 0xffffffffu;
+        val[e] = (uint32_t)j | ((uint32_t)ci << 24);
+        if (s >= 0) atomicAdd(&cnt[s], 1);
+        else atomicAdd(nmiss, 1ull);
+    }
+}
+
+// Entry i of the slot-sorted pairs goes to position start[s] + (i -
+// ustart[s]) of the order; the places after each slot's run are padding.
+__global__ void __launch_bounds__(kPB) k_go_scatter(const uint32_t* __restrict__ skey,
+                                                    const uint32_t* __restrict__ sval, int64_t nvalid,
+                                                    const int64_t* __restrict__ ustart,
+                                                    const int64_t* __restrict__ start, uint32_t* __restrict__ ord)
+{
+    GRID_LOOP(i, nvalid) {
+        const int64_t s = skey[i];
+        ord[start[s] + (i - ustart[s])] = sval[i];
+    }
+}
+
+__global__ void __launch_bounds__(kPB) k_go_padding(const int32_t* __restrict__ cnt,
+                                                    const int64_t* __restrict__ start, int64_t nslots, int64_t no,
+                                                    uint32_t* __restrict__ ord)
+{
+    GRID_LOOP(s, nslots) {
+        const int64_t end = s + 1 < nslots ? start[s + 1] : no;
+        for (int64_t pos = start[s] + cnt[s]; pos < end; ++pos) ord[pos] = 0xffffffffu;
+    }
+}
+
 }  // namespace
+
+hipError_t build_pair_order_device(DevicePlan& p, int d, double budget)
+{
+    const HostLevel& H = p.hp.L[d];
+    const LevelDev& L = p.L[d];
+    const int64_t np = p.npairs_all[d];
+    const int64_t ns = H.nslots;
+    p.go_ord[d] = nullptr;
+    p.ngo[d] = 0;
+    if (np <= 0 || np > INT32_MAX || ns <= 0 || !p.pair_off[d] || p.hp.n >= ((int64_t)1 << 24)) return hipSuccess;
+    for (int64_t T = 0; T < H.nbox; ++T)
+        if (H.cou_start[T + 1] - H.cou_start[T] > 255) return hipSuccess;
+    // padded size bound: every slot's run rounded up to kPairQuad
+    if ((double)(np + (int64_t)(kPairQuad - 1) * ns) * 4.0 > budget) return hipSuccess;
+    hipError_t e;
+    DevBuf key, val, skey, sval, cnt, ucnt, pcnt, ustart, start, tmp, miss;
+    if ((e = key.alloc(np * 4)) != hipSuccess || (e = val.alloc(np * 4)) != hipSuccess ||
+        (e = skey.alloc(np * 4)) != hipSuccess || (e = sval.alloc(np * 4)) != hipSuccess ||
+        (e = cnt.alloc(ns * 4)) != hipSuccess || (e = ucnt.alloc(ns * 8)) != hipSuccess ||
+        (e = pcnt.alloc(ns * 8)) != hipSuccess || (e = ustart.alloc(ns * 8)) != hipSuccess ||
+        (e = start.alloc(ns * 8)) != hipSuccess || (e = miss.alloc(8)) != hipSuccess)
+        return e;
+    if ((e = hipMemset(cnt.as<void>(), 0, ns * 4)) != hipSuccess) return e;
+    if ((e = hipMemset(miss.as<void>(), 0, 8)) != hipSuccess) return e;
+    k_go_keys<<<blocks_for(np), kPB>>>(L, p.pts, p.pair_off[d], np, key.as<uint32_t>(), val.as<uint32_t>(),
+                                       cnt.as<int32_t>(), miss.as<unsigned long long>());
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    unsigned long long nmiss = 0;
+    if ((e = hipMemcpy(&nmiss, miss.as<void>(), 8, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    if (nmiss > 0) return hipSuccess;          // keep the per-pair path, which counts the misses
+    size_t tb = 0, tb2 = 0;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key.as<uint32_t>(), skey.as<uint32_t>(),
+                                                val.as<uint32_t>(), sval.as<uint32_t>(), (int)np)) != hipSuccess)
+        return e;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, ucnt.as<int64_t>(), ustart.as<int64_t>(), (int)ns)) !=
+        hipSuccess)
+        return e;
+    if ((e = tmp.alloc(tb > tb2 ? tb : tb2)) != hipSuccess) return e;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp.as<void>(), tb, key.as<uint32_t>(), skey.as<uint32_t>(),
+                                                val.as<uint32_t>(), sval.as<uint32_t>(), (int)np)) != hipSuccess)
+        return e;
+    key.reset();
+    val.reset();
+    k_pad_counts<<<blocks_for(ns), kPB>>>(cnt.as<int32_t>(), ns, ucnt.as<int64_t>(), pcnt.as<int64_t>());
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(tmp.as<void>(), tb2, ucnt.as<int64_t>(), ustart.as<int64_t>(),
+                                              (int)ns)) != hipSuccess)
+        return e;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(tmp.as<void>(), tb2, pcnt.as<int64_t>(), start.as<int64_t>(),
+                                              (int)ns)) != hipSuccess)
+        return e;
+    int64_t tail[2];
+    if ((e = hipMemcpy(&tail[0], start.as<int64_t>() + (ns - 1), 8, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    if ((e = hipMemcpy(&tail[1], pcnt.as<int64_t>() + (ns - 1), 8, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    const int64_t no = tail[0] + tail[1];
+    void* q = nullptr;
+    if ((e = hipMalloc(&q, (size_t)no * 4)) != hipSuccess) return e;
+    p.allocs.push_back(q);
+    p.tree_bytes += (size_t)no * 4;
+    uint32_t* ord = (uint32_t*)q;
+    k_go_scatter<<<blocks_for(np), kPB>>>(skey.as<uint32_t>(), sval.as<uint32_t>(), np, ustart.as<int64_t>(),
+                                          start.as<int64_t>(), ord);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_go_padding<<<blocks_for(ns), kPB>>>(cnt.as<int32_t>(), start.as<int64_t>(), ns, no, ord);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return e;
+    p.go_ord[d] = ord;
+    p.ngo[d] = no;
+    return hipSuccess;
+}
 
 std::unique_ptr<ConeMarker> make_gpu_cone_marker() { return std::unique_ptr<ConeMarker>(new GpuConeMarker()); }
 

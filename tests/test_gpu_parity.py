@@ -758,6 +758,44 @@ def test_cousin_geo_pairs_on_off(torch, monkeypatch, prec, nrhs, tables):
     monkeypatch.delenv("IFGF_COUSIN_GEO_PAIRS")
 
 
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 4), ("fp64", 16), ("mixed", 4), ("mixed", 16)])
+def test_cousin_geo_order(torch, monkeypatch, prec, nrhs):
+    """On levels without cousin-pair tables the pairs kept in cone order (a
+    4-byte entry per pair) run on the matrix cores; with the order off
+    (IFGF_COUSIN_GEO_ORDER=0) one thread per pair.  Both match the oracle,
+    forward and adjoint, and the order takes device memory only when built
+    (IFGF_GEO_ORDER_BUDGET_MB=0: not built)."""
+    monkeypatch.setenv("IFGF_PAIR_BUDGET_MB", "0")
+    p = inputs.cube_sphere(20)
+    k = 5.0 * math.pi
+    a = inputs.densities(44, nrhs, p.shape[0])
+    ac = a if prec == "fp64" else as_c64(a)
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    ref = oracle.ifgf(p, ac, k)["out"]
+    ref_adj = np.conj(oracle.ifgf(p, np.conj(ac), k)["out"])
+    outs, nbytes = {}, {}
+    for flag, budget in (("1", None), ("0", None), ("1", "0")):
+        monkeypatch.setenv("IFGF_COUSIN_GEO_ORDER", flag)
+        if budget is None:
+            monkeypatch.delenv("IFGF_GEO_ORDER_BUDGET_MB", raising=False)
+        else:
+            monkeypatch.setenv("IFGF_GEO_ORDER_BUDGET_MB", budget)
+        print(f"geo order {flag} budget {budget}", flush=True)
+        plan = make_plan(p, k, prec, max_nrhs=16)
+        assert sum(plan.stats()["pairs_tabulated"]) == 0
+        nbytes[(flag, budget)] = plan.stats()["device_bytes"]
+        out = plan.apply(dev(torch, a, prec)).cpu().numpy()
+        adj = plan.adjoint(dev(torch, a, prec)).cpu().numpy()
+        assert par(out, ref) < tol
+        assert par(adj, ref_adj) < tol
+        assert plan.misses() == 0
+        outs[(flag, budget)] = out
+    assert nbytes[("1", None)] > nbytes[("1", "0")]
+    assert par(outs[("1", None)], outs[("0", None)]) < (1e-13 if prec == "fp64" else 1e-6)
+    monkeypatch.delenv("IFGF_COUSIN_GEO_ORDER")
+    monkeypatch.delenv("IFGF_GEO_ORDER_BUDGET_MB", raising=False)
+
+
 def test_streams_and_workspace_reallocation(torch):
     """Calls on different streams, the second one growing the workspaces:
     the reallocation waits for the plan's work on the first stream (not for
