@@ -376,7 +376,7 @@ def main() -> int:
     if args.summarize:
         return summarize(args.summarize)
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         return 2
 

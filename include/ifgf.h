@@ -54,7 +54,7 @@ typedef enum {
     IFGF_E_OUT_OF_MEMORY = 2, /* host or device allocation failed, or the
                                  workspace limit is too small                 */
     IFGF_E_HIP = 3,           /* a HIP runtime call or kernel launch failed   */
-    IFGF_E_UNSUPPORTED = 4,   /* valid request this build cannot serve        */
+    IFGF_E_UNSUPPORTED = 4,   /* valid request the library cannot serve       */
     IFGF_E_INTERNAL = 5
 } ifgf_status;
 
