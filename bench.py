@@ -83,7 +83,7 @@ SIMDS = 1024                   # 256 CUs x 4 SIMDs
 CLOCK_HZ = 2.4e9
 COPY_NUMEL = 64 << 20          # float32 elements read and written by the calibration copy
 # child-to-parent variants that run on the matrix cores
-MFMA_VARIANTS = ("mfma", "mfma_geometry", "boxes", "box_acc")
+MFMA_VARIANTS = ("mfma", "mfma_geometry", "boxes", "box_acc", "box_acc_half")
 
 
 def profile_commands(d: str) -> list[str]:

@@ -283,10 +283,13 @@ typedef enum {
                                    box-tile order (blocks of boxes, one parent
                                    cone after the other), which shares frames
                                    in cache                                   */
-    IFGF_C2P_BOX_ACC = 8        /* matrix cores (FP32 or FP64), boxes of one
+    IFGF_C2P_BOX_ACC = 8,       /* matrix cores (FP32 or FP64), boxes of one
                                    parent cone as matrix columns, parent values
                                    accumulated in LDS, weights formed in
                                    registers                                  */
+    IFGF_C2P_BOX_ACC_HALF = 9   /* IFGF_C2P_BOX_ACC with 8 complex columns per
+                                   pass in one tile, half its LDS (FP64, 1 or
+                                   4 RHS per pass)                           */
 } ifgf_c2p_variant;
 
 /* Times every applicable child-to-parent variant at every level for nrhs

@@ -24,7 +24,7 @@ constexpr int kBoxTile = 16;        // parent slots (boxes) of one parent cone p
 constexpr int kPairQuad = 4;        // cone-ordered cousin pairs share a cone in runs of this length
 // child-to-parent kernel variants (ifgf_plan_autotune, ifgf_plan_kernel_choice)
 enum { kC2PGeometry = 0, kC2PFrames = 1, kC2PLds = 2, kC2PMfma = 3, kC2PMfmaGeometry = 4, kC2PBoxes = 5,
-       kC2PQuads = 6, kC2PLdsTiled = 7, kC2PBoxAcc = 8, kC2PVariants = 9 };
+       kC2PQuads = 6, kC2PLdsTiled = 7, kC2PBoxAcc = 8, kC2PBoxAccHalf = 9, kC2PVariants = 10 };
 
 // Chebyshev nodes t_k = cos((2k+1) pi / (2n)) on [-1, 1] and the inverse
 // denominators of their Lagrange polynomials, 1 / prod_{j != k} (t_k - t_j).
@@ -174,6 +174,7 @@ struct HostLevel {
     // entries of the box tiles: (octant, group) pairs of the tile's frames in
     // octant order, with their child slot in each of the tile's boxes
     std::vector<int32_t> te_start;            // [ntiles + 1] first entry of the tile
+    double te_per_tile = 0;                   // entries per tile, on average
     std::vector<uint16_t> te_go;              // [ntiles][9] first entry of octant o, relative; [8] = count
     std::vector<int32_t> te_info;             // [entries] g0 | cnt << 8 | o << 16
     std::vector<int32_t> te_cs;               // [entries][kBoxTile] child slot, -1 no child, -2 cone missing

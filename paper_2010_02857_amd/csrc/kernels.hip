@@ -2148,16 +2148,21 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
 // live octant's frame is loaded while the current one runs, and an entry's
 // B operands are loaded when the entry starts (a second operand set, loaded
 // one entry ahead, measured slower for both types).
-template <typename T, int PS, int PA, int RB>
+template <typename T, int PS, int PA, int RB, bool HALF>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* __restrict__ Fc,
                          cpx<T>* __restrict__ Fp, const cpx<T>* __restrict__ zero_cone)
 {
     constexpr int P = PS * PA * PA;
-    constexpr int NT = 2;                      // tiles per pass: real and imaginary parts
-    static_assert(16 % RB == 0, "a pass holds whole boxes");
-    constexpr int BX = 16 / RB;                // boxes per pass (16 complex columns)
-    constexpr int AS = 33;                     // row stride of the accumulators (re 0..15, im 16..31)
+    // HALF: a pass holds 8 complex columns as the 16 columns of one tile (real
+    // and imaginary parts of a column side by side), so that the accumulators
+    // take half the LDS; else 16 complex columns in two tiles, real parts in
+    // tile 0 and imaginary parts in tile 1
+    constexpr int CP = HALF ? 8 : 16;          // complex columns per pass
+    constexpr int NT = HALF ? 1 : 2;           // tiles per pass
+    static_assert(CP % RB == 0, "a pass holds whole boxes");
+    constexpr int BX = CP / RB;                // boxes per pass
+    constexpr int AS = HALF ? 17 : 33;         // row stride of the accumulators
     constexpr int ME = kBoxMaxEnt;
     constexpr int NAB = PS * PA;
     constexpr int NREM = NAB * (PA - 4);
@@ -2207,22 +2212,38 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
     // missing child reads the zero cone.
     T bn[NT][NK];
     auto fetch_b = [&](int ei) {
-        const int cs = ecs[ei * BX + col / RB];
-        const cpx<T>* src = cs >= 0 ? Fc + (size_t)cs * P * RB + (col % RB) : zero_cone + (col % RB);
+        if constexpr (HALF) {
+            // column col: part col % 2 of complex column col / 2
+            const int cc = col >> 1, part = col & 1;
+            const int cs = ecs[ei * BX + cc / RB];
+            const T* src = (const T*)(cs >= 0 ? Fc + (size_t)cs * P * RB + (cc % RB) : zero_cone + (cc % RB)) + part;
 #pragma unroll
-        for (int ab = 0; ab < NAB; ++ab) {
-            const cpx<T> v = src[(size_t)(ab * PA + q) * RB];
-            bn[0][ab] = v.x;
-            bn[1][ab] = v.y;
-        }
+            for (int ab = 0; ab < NAB; ++ab) bn[0][ab] = src[(size_t)(ab * PA + q) * RB * 2];
 #pragma unroll
-        for (int jt = 0; jt < NK - NAB; ++jt) {
-            int m = 4 * jt + q;
-            m = m < NREM ? m : NREM - 1;
-            const int abm = m / (PA - 4), c4 = 4 + (m - abm * (PA - 4));
-            const cpx<T> v = src[(size_t)(abm * PA + c4) * RB];
-            bn[0][NAB + jt] = v.x;
-            bn[1][NAB + jt] = v.y;
+            for (int jt = 0; jt < NK - NAB; ++jt) {
+                int m = 4 * jt + q;
+                m = m < NREM ? m : NREM - 1;
+                const int abm = m / (PA - 4), c4 = 4 + (m - abm * (PA - 4));
+                bn[0][NAB + jt] = src[(size_t)(abm * PA + c4) * RB * 2];
+            }
+        } else {
+            const int cs = ecs[ei * BX + col / RB];
+            const cpx<T>* src = cs >= 0 ? Fc + (size_t)cs * P * RB + (col % RB) : zero_cone + (col % RB);
+#pragma unroll
+            for (int ab = 0; ab < NAB; ++ab) {
+                const cpx<T> v = src[(size_t)(ab * PA + q) * RB];
+                bn[0][ab] = v.x;
+                bn[NT - 1][ab] = v.y;
+            }
+#pragma unroll
+            for (int jt = 0; jt < NK - NAB; ++jt) {
+                int m = 4 * jt + q;
+                m = m < NREM ? m : NREM - 1;
+                const int abm = m / (PA - 4), c4 = 4 + (m - abm * (PA - 4));
+                const cpx<T> v = src[(size_t)(abm * PA + c4) * RB];
+                bn[0][NAB + jt] = v.x;
+                bn[NT - 1][NAB + jt] = v.y;
+            }
         }
     };
 
@@ -2326,12 +2347,23 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int ri = t0 + mfma_row<T>(q, i);
-                            if (ri < cnt) {
-                                const int nu = ord[g0 + ri];
-                                const T vr = c[0][i], vi = c[1][i];
-                                const T gr = rg[0][nu], gi = rg[1][nu];
-                                acc[nu * AS + col] += vr * gr - vi * gi;
-                                acc[nu * AS + 16 + col] += vr * gi + vi * gr;
+                            if constexpr (HALF) {
+                                // the other part of the lane's complex column is in lane ^ 1
+                                const T v = c[0][i];
+                                const T pv = __shfl_xor(v, 1, 64);
+                                if (ri < cnt) {
+                                    const int nu = ord[g0 + ri];
+                                    const T gr = rg[0][nu], gi = rg[1][nu];
+                                    acc[nu * AS + col] += (col & 1) == 0 ? v * gr - pv * gi : pv * gi + v * gr;
+                                }
+                            } else {
+                                if (ri < cnt) {
+                                    const int nu = ord[g0 + ri];
+                                    const T vr = c[0][i], vi = c[NT - 1][i];
+                                    const T gr = rg[0][nu], gi = rg[1][nu];
+                                    acc[nu * AS + col] += vr * gr - vi * gi;
+                                    acc[nu * AS + 16 + col] += vr * gi + vi * gr;
+                                }
                             }
                         }
                     }
@@ -2342,12 +2374,13 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
         }
         wave_lds_fence();
         // write the pass's slots: column cc is (box cc / RB, right-hand side cc % RB)
-        for (int i = lane; i < P * 16; i += 64) {
-            const int nu = i >> 4, cc = i & 15;
+        for (int i = lane; i < P * CP; i += 64) {
+            const int nu = i / CP, cc = i - nu * CP;
             const int bl = cc / RB, r = cc - bl * RB;
             const int bi = b0 + bl;
             const int s = bi < kBoxTile ? bslot[bi] : -1;
-            if (s >= 0) Fp[((size_t)s * P + nu) * RB + r] = cpx<T>{acc[nu * AS + cc], acc[nu * AS + 16 + cc]};
+            const int ir = HALF ? 2 * cc : cc, ii = HALF ? 2 * cc + 1 : 16 + cc;
+            if (s >= 0) Fp[((size_t)s * P + nu) * RB + r] = cpx<T>{acc[nu * AS + ir], acc[nu * AS + ii]};
         }
         wave_lds_fence();
     }
@@ -2928,6 +2961,10 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     return hipSuccess;
 }
 
+// Entries (octant, child-cone group) per box tile from which the FP64 default
+// takes the half-width box kernel.
+constexpr double kHalfEntries = 16.0;
+
 // Least average number of slots per box tile (as a fraction of kBoxTile) for
 // which the default rule picks the box-batched child-to-parent kernel (never
 // for 16 right-hand sides, where the autotuner decides); IFGF_BOX_FILL
@@ -2972,6 +3009,9 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
         if constexpr (PA >= 4 && P <= 128) {
             if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAcc;
         }
+        if constexpr (std::is_same<T, double>::value && RB <= 8 && PA >= 4 && P <= 128) {
+            if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAccHalf;
+        }
         if constexpr (RB == 1 && P <= 255) {
             if (groups) v[n++] = kC2PQuads;
         }
@@ -3001,6 +3041,9 @@ int c2p_default(const DevicePlan& p, int d)
         // with batched right-hand sides (and always in FP64) the kernel with
         // the accumulators in LDS measured faster; at 1 RHS in FP32 the one
         // with register accumulators
+        // in FP64, tiles with many entries (small child-cone groups) measured
+        // faster at half width (more wavefronts per CU hide the operand loads)
+        if (has(kC2PBoxAccHalf) && full && p.hp.L[d].te_per_tile >= kHalfEntries) return kC2PBoxAccHalf;
         if (has(kC2PBoxAcc) && full && (std::is_same<T, double>::value || RB >= 4)) return kC2PBoxAcc;
         if (has(kC2PBoxes) && full) return kC2PBoxes;
         if (has(kC2PMfma)) return kC2PMfma;
@@ -3053,7 +3096,14 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
             break;
         case kC2PBoxAcc:
             if constexpr (PA >= 4 && P <= 128) {
-                k_child_to_parent_boxacc<T, PS, PA, RB><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                k_child_to_parent_boxacc<T, PS, PA, RB, false><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                    kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+                return;
+            }
+            break;
+        case kC2PBoxAccHalf:
+            if constexpr (std::is_same<T, double>::value && RB <= 8 && PA >= 4 && P <= 128) {
+                k_child_to_parent_boxacc<T, PS, PA, RB, true><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
                     kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
                 return;
             }

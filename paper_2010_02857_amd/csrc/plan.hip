@@ -549,6 +549,7 @@ void build_tile_entries(HostPlan& hp, int d)
         L.te_start[t + 1] = L.te_start[t] + n;
     }
     const int64_t ne = L.te_start[nt];
+    L.te_per_tile = nt > 0 ? (double)ne / (double)nt : 0.0;
     L.te_go.assign((size_t)nt * 9, 0);
     L.te_mask.assign((size_t)nt * kBoxTile, 0);
     L.te_info.assign((size_t)ne, 0);

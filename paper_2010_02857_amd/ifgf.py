@@ -253,7 +253,8 @@ class Plan:
                                            cnt.ctypes.data_as(ctypes.c_void_p)))
         return {d: (float(ms[d]), int(cnt[d])) for d in range(MAX_LEVELS + 1) if cnt[d]}
 
-    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes", "quads", "lds_tiled", "box_acc")
+    C2P_VARIANTS = ("geometry", "frames", "lds", "mfma", "mfma_geometry", "boxes", "quads", "lds_tiled", "box_acc",
+                    "box_acc_half")
 
     def autotune(self, nrhs: int = 1):
         """Time the child-to-parent kernel variants of every level for nrhs
