@@ -288,8 +288,8 @@ typedef enum {
                                    accumulated in LDS, weights formed in
                                    registers                                  */
     IFGF_C2P_BOX_ACC_HALF = 9   /* IFGF_C2P_BOX_ACC with 8 complex columns per
-                                   pass in one tile, half its LDS (FP64, 1 or
-                                   4 RHS per pass)                           */
+                                   pass in one tile, half its LDS (1 or 4 RHS
+                                   per pass)                                  */
 } ifgf_c2p_variant;
 
 /* Times every applicable child-to-parent variant at every level for nrhs

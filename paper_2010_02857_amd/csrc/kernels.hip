@@ -2149,7 +2149,7 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
 // B operands are loaded when the entry starts (a second operand set, loaded
 // one entry ahead, measured slower for both types).
 template <typename T, int PS, int PA, int RB, bool HALF>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALF && sizeof(T) == 4 ? 4 : 3)))
 k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* __restrict__ Fc,
                          cpx<T>* __restrict__ Fp, const cpx<T>* __restrict__ zero_cone)
 {
@@ -2961,9 +2961,13 @@ hipError_t ensure_workspace(DevicePlan& p, int rb, bool store, bool* fresh)
     return hipSuccess;
 }
 
-// Entries (octant, child-cone group) per box tile from which the FP64 default
-// takes the half-width box kernel.
-constexpr double kHalfEntries = 16.0;
+// Entries (octant, child-cone group) per box tile from which the default
+// takes the half-width box kernel: 16 in FP64, 20 in FP32 (4 RHS).
+template <typename T>
+constexpr double half_entries()
+{
+    return std::is_same<T, double>::value ? 16.0 : 20.0;
+}
 
 // Least average number of slots per box tile (as a fraction of kBoxTile) for
 // which the default rule picks the box-batched child-to-parent kernel (never
@@ -3009,7 +3013,7 @@ int c2p_candidates(const DevicePlan& p, int d, int* v)
         if constexpr (PA >= 4 && P <= 128) {
             if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAcc;
         }
-        if constexpr (std::is_same<T, double>::value && RB <= 8 && PA >= 4 && P <= 128) {
+        if constexpr (RB <= 8 && PA >= 4 && P <= 128) {
             if (groups && L.ntiles > 0 && L.te_start) v[n++] = kC2PBoxAccHalf;
         }
         if constexpr (RB == 1 && P <= 255) {
@@ -3041,9 +3045,11 @@ int c2p_default(const DevicePlan& p, int d)
         // with batched right-hand sides (and always in FP64) the kernel with
         // the accumulators in LDS measured faster; at 1 RHS in FP32 the one
         // with register accumulators
-        // in FP64, tiles with many entries (small child-cone groups) measured
-        // faster at half width (more wavefronts per CU hide the operand loads)
-        if (has(kC2PBoxAccHalf) && full && p.hp.L[d].te_per_tile >= kHalfEntries) return kC2PBoxAccHalf;
+        // tiles with many entries (small child-cone groups) measured faster at
+        // half width (more wavefronts per CU hide the operand loads)
+        if (has(kC2PBoxAccHalf) && full && p.hp.L[d].te_per_tile >= half_entries<T>() &&
+            (std::is_same<T, double>::value || RB >= 4))
+            return kC2PBoxAccHalf;
         if (has(kC2PBoxAcc) && full && (std::is_same<T, double>::value || RB >= 4)) return kC2PBoxAcc;
         if (has(kC2PBoxes) && full) return kC2PBoxes;
         if (has(kC2PMfma)) return kC2PMfma;
@@ -3102,7 +3108,7 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
             }
             break;
         case kC2PBoxAccHalf:
-            if constexpr (std::is_same<T, double>::value && RB <= 8 && PA >= 4 && P <= 128) {
+            if constexpr (RB <= 8 && PA >= 4 && P <= 128) {
                 k_child_to_parent_boxacc<T, PS, PA, RB, true><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
                     kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
                 return;
