@@ -1480,11 +1480,15 @@ k_child_to_parent_mfma(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* 
 // cones up in parallel (one lane per group), and runs the groups' MFMA
 // tiles.  Every point of an octant is in one group, and the groups come in
 // octant order, so each parent point receives its octants' terms in octant
-// order.  (Loading the next group's operands during the current group's
-// tiles was measured no faster in FP32 at 4 RHS, and in FP64 its registers
-// cost a wave per SIMD.)
+// order.  In FP32 up to 4 right-hand sides the kernel is held to 128 VGPRs,
+// four wavefronts per SIMD instead of three: 15% faster.  (Loading the next
+// group's operands during the current group's tiles was measured no faster
+// in FP32 at 4 RHS, and in FP64 its registers cost a wave per SIMD; FP64 in
+// 16 x 16 x 4 tiles, half of each unused, fits three wavefronts per SIMD
+// but measured 5-6% slower.)
 template <typename T, int PS, int PA, int RB, int W>
-__global__ void __launch_bounds__(64 * W) k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && RB <= 4 ? 4 : 1)))
+k_child_to_parent_mfma_geo(KernelConsts kc, LevelDev Lc, LevelDev Lp,
                                                                       const cpx<T>* __restrict__ Fc,
                                                                       cpx<T>* __restrict__ Fp)
 {
