@@ -2566,7 +2566,8 @@ __global__ void __launch_bounds__(kBlock) k_cousin_pairs_values_mfma(KernelConst
 // k_cousin_pairs_values_mfma does.  Each row's value times its factor is
 // stored once, at the pair's place; phase 2 is k_cousin_pairs_sum_geo.
 template <typename T, int PS, int PA, int RB>
-__global__ void __launch_bounds__(kBlock) k_cousin_pairs_go_mfma(KernelConsts kc, LevelDev L,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1)))
+k_cousin_pairs_go_mfma(KernelConsts kc, LevelDev L,
                                                                  const double* __restrict__ pts,
                                                                  const long long* __restrict__ pair_off,
                                                                  const uint32_t* __restrict__ ord, long long no,
