@@ -792,8 +792,25 @@ def test_cousin_geo_order(torch, monkeypatch, prec, nrhs):
         outs[(flag, budget)] = out
     assert nbytes[("1", None)] > nbytes[("1", "0")]
     assert par(outs[("1", None)], outs[("0", None)]) < (1e-13 if prec == "fp64" else 1e-6)
-    monkeypatch.delenv("IFGF_COUSIN_GEO_ORDER")
+    # the ordered pairs inside a captured apply: every replay equals the eager
+    # result, with eager work in between
+    monkeypatch.setenv("IFGF_COUSIN_GEO_ORDER", "1")
     monkeypatch.delenv("IFGF_GEO_ORDER_BUDGET_MB", raising=False)
+    gplan = make_plan(p, k, prec, max_nrhs=16, use_graph=True)
+    eager = make_plan(p, k, prec, max_nrhs=16)
+    x = dev(torch, a, prec)
+    y = torch.empty_like(x)
+    for it in range(3):
+        x.copy_(dev(torch, inputs.densities(90 + it, nrhs, p.shape[0]), prec))
+        g = gplan.apply(x, out=y).clone()
+        torch.cuda.synchronize()
+        e = eager.apply(x)
+        scratch = (x.abs() ** 2).sum()
+        torch.cuda.synchronize()
+        assert float(scratch) > 0
+        assert torch.equal(g, e)
+    assert gplan.misses() == 0
+    monkeypatch.delenv("IFGF_COUSIN_GEO_ORDER")
 
 
 def test_streams_and_workspace_reallocation(torch):
