@@ -554,6 +554,18 @@ def main() -> int:
         log(f"mixed {nrhs} RHS: {msm:.1f} ms, eps {epsm}")
         del pm, xm
         torch.cuda.empty_cache()
+        # the same mixed matvec captured as one hipGraph and replayed
+        pg = ifgf.Plan(p, w.kappa, precision="mixed", max_nrhs=nrhs, store_levels=0, use_graph=True)
+        xg = torch.from_numpy(a).to(torch.complex64).cuda()
+        og = torch.empty_like(xg)
+        pg.apply(xg, out=og)
+        msg = time_fn(lambda: pg.apply(xg, out=og), 5)
+        outg = og.cpu().numpy()
+        result["mixed_graph_matvecs_per_s"] = round(nrhs * 1000.0 / msg, 4)
+        result["mixed_graph_equals_eager"] = bool(np.array_equal(outg, outm))
+        log(f"mixed {nrhs} RHS graph replay: {msg:.1f} ms, equal to eager: {result['mixed_graph_equals_eager']}")
+        del pg, xg, og
+        torch.cuda.empty_cache()
         result["sphere393216"] = sphere393216_extras(torch, ifgf, inputs, oracle, time_fn, log)
         result["graded_adaptive"] = graded_adaptive_extras(torch, ifgf, inputs, oracle, time_fn, log)
         result["laplace393216"] = laplace_extras(torch, ifgf, inputs, oracle, time_fn, log)
