@@ -651,7 +651,29 @@ __global__ void __launch_bounds__(kPB) k_go_padding(const int32_t* __restrict__ 
 
 }  // namespace
 
+namespace {
+
+hipError_t pair_order(DevicePlan& p, int d, double budget);
+
+}  // namespace
+
+// The order is an optimisation: where its buffers do not fit the device, the
+// level keeps the per-pair evaluation and the plan is built all the same.
 hipError_t build_pair_order_device(DevicePlan& p, int d, double budget)
+{
+    hipError_t e = pair_order(p, d, budget);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        p.go_ord[d] = nullptr;
+        p.ngo[d] = 0;
+        return hipSuccess;
+    }
+    return e;
+}
+
+namespace {
+
+hipError_t pair_order(DevicePlan& p, int d, double budget)
 {
     const HostLevel& H = p.hp.L[d];
     const LevelDev& L = p.L[d];
@@ -720,6 +742,8 @@ hipError_t build_pair_order_device(DevicePlan& p, int d, double budget)
     p.ngo[d] = no;
     return hipSuccess;
 }
+
+}  // namespace
 
 std::unique_ptr<ConeMarker> make_gpu_cone_marker() { return std::unique_ptr<ConeMarker>(new GpuConeMarker()); }
 
