@@ -159,6 +159,7 @@ struct HostLevel {
     // the distinct child cones of each frame ("groups") and the group of
     // every interpolation point, for staging child cones in LDS
     bool frame_groups_ok = false;             // every frame has <= kMaxFrameGroups
+    int fr_max_groups = 0;                    // the most groups of any frame
     std::vector<uint8_t> fr_ngrp;             // [nframes]
     std::vector<uint32_t> fr_gkey;            // [nframes][kMaxFrameGroups]
     std::vector<uint8_t> fr_grp;              // [nframes][P]

@@ -1865,6 +1865,8 @@ k_child_to_parent_quads(KernelConsts kc, LevelDev Lc, LevelDev Lp,
 // points of the next octant are loaded while the current tiles run.  Each
 // parent slot is written by exactly one wavefront.
 constexpr int kBoxMaxEnt = 40;    // (octant, group) entries read at once
+constexpr int kCompactEnt = 24;   // the same for the compact FP64 box kernel, whose frames
+                                  // may touch at most this many child cones
 
 template <int PS, int PA, int RB>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
@@ -2152,7 +2154,7 @@ k_child_to_parent_boxes(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<flo
 // live octant's frame is loaded while the current one runs, and an entry's
 // B operands are loaded when the entry starts (a second operand set, loaded
 // one entry ahead, measured slower for both types).
-template <typename T, int PS, int PA, int RB, bool HALF>
+template <typename T, int PS, int PA, int RB, bool HALF, bool CMP = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALF && sizeof(T) == 4 ? 4 : 3)))
 k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>* __restrict__ Fc,
                          cpx<T>* __restrict__ Fp, const cpx<T>* __restrict__ zero_cone)
@@ -2166,21 +2168,28 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
     constexpr int NT = HALF ? 1 : 2;           // tiles per pass
     static_assert(CP % RB == 0, "a pass holds whole boxes");
     constexpr int BX = CP / RB;                // boxes per pass
-    constexpr int AS = HALF ? 17 : 33;         // row stride of the accumulators
-    constexpr int ME = kBoxMaxEnt;
+    // CMP (FP64, full width, levels whose frames touch at most kCompactEnt
+    // child cones): the accumulators unpadded with their columns XOR-swizzled
+    // by the point against bank conflicts, only the current octant's point
+    // order in LDS (loaded one octant ahead with its frame), chunks of at most
+    // kCompactEnt entries and the tile's slots and child masks in registers,
+    // so that seven wavefronts fit per CU instead of six
+    static_assert(!CMP || (!HALF && sizeof(T) == 8), "the compact layout is FP64 full width");
+    constexpr int AS = CMP ? 32 : (HALF ? 17 : 33);   // row stride of the accumulators
+    constexpr int ME = CMP ? kCompactEnt : kBoxMaxEnt;
     constexpr int NAB = PS * PA;
     constexpr int NREM = NAB * (PA - 4);
     constexpr int NK = NAB + (NREM + 3) / 4;
     static_assert(PA >= 4, "the K ordering needs at least four phi nodes");
-    static_assert(P <= 255 && ME >= kMaxFrameGroups, "entry and point indices");
+    static_assert(P <= 255 && (CMP || ME >= kMaxFrameGroups), "entry and point indices");
     __shared__ T acc[P * AS];                  // the pass's parent values by point
     __shared__ T rt[3][P];                     // local coordinates of the octant's points
     __shared__ T rg[2][P];                     // their ratios
-    __shared__ uint8_t sord[8 * P];            // points of the 8 frames in group order
+    __shared__ uint8_t sord[CMP ? P : 8 * P];  // points of the frames in group order (CMP: the octant's)
     __shared__ int sfr[8];                     // frame of each octant, -1
     __shared__ int sgo[9];                     // first entry of each octant
-    __shared__ int bslot[kBoxTile];
-    __shared__ uint8_t smask[kBoxTile];        // children of each tile box (bit o)
+    __shared__ int bslot[CMP ? 1 : kBoxTile];
+    __shared__ uint8_t smask[CMP ? 1 : kBoxTile];   // children of each tile box (bit o)
     __shared__ int einfo[ME];                  // g0 | cnt << 8 | o << 16
     __shared__ int ecs[ME * BX];               // child slot of (entry, box of the pass), -1
 
@@ -2192,22 +2201,29 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
     const T conj_sign = kc.adj ? (T)-1 : (T)1;
     const int row = lane & 15, q = lane >> 4, col = lane & 15;
 
-    int my_slot = -1;
+    int my_slot = -1, my_mask = 0;
     if (lane < kBoxTile) {
         my_slot = Lc.bt_slot[(size_t)tile * kBoxTile + lane];
-        bslot[lane] = my_slot;
-        smask[lane] = Lc.te_mask[(size_t)tile * kBoxTile + lane];
+        my_mask = Lc.te_mask[(size_t)tile * kBoxTile + lane];
+        if constexpr (!CMP) {
+            bslot[lane] = my_slot;
+            smask[lane] = (uint8_t)my_mask;
+        }
     }
+    // accumulator of (point nu, column cc)
+    auto aix = [&](int nu, int cc) { return CMP ? nu * AS + ((cc & 16) | ((cc ^ nu) & 15)) : nu * AS + cc; };
     if (lane < 8) sfr[lane] = Lc.bt_frame[(size_t)tile * 8 + lane];
     if (lane < 9) sgo[lane] = Lc.te_go[(size_t)tile * 9 + lane];
     const int64_t ebase = Lc.te_start[tile];
     const int nbt = __popcll(__ballot(my_slot >= 0));
     wave_lds_fence();
-    for (int i = lane; i < 8 * P; i += 64) {
-        const int o = i / P, r = i - o * P;
-        const int f = sfr[o];
-        const uint8_t v = Lc.fr_order[(size_t)(f >= 0 ? f : 0) * P + r];
-        sord[i] = f >= 0 ? v : (uint8_t)0;
+    if constexpr (!CMP) {
+        for (int i = lane; i < 8 * P; i += 64) {
+            const int o = i / P, r = i - o * P;
+            const int f = sfr[o];
+            const uint8_t v = Lc.fr_order[(size_t)(f >= 0 ? f : 0) * P + r];
+            sord[i] = f >= 0 ? v : (uint8_t)0;
+        }
     }
     wave_lds_fence();
 
@@ -2259,7 +2275,10 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
             pm = 255;
         } else {
             const int bl = lane >> 3, o = lane & 7;
-            const bool has = lane < BX * 8 && b0 + bl < kBoxTile && ((smask[b0 + bl] >> o) & 1);
+            int mk = 0;
+            if constexpr (CMP) mk = __shfl(my_mask, (b0 + bl) & (kBoxTile - 1), 64);
+            else mk = lane < BX * 8 && b0 + bl < kBoxTile ? smask[b0 + bl] : 0;
+            const bool has = lane < BX * 8 && b0 + bl < kBoxTile && ((mk >> o) & 1);
             const unsigned long long bal = __ballot(has);
 #pragma unroll
             for (int k = 0; k < BX; ++k) pm |= (int)((bal >> (8 * k)) & 255ull);
@@ -2288,6 +2307,7 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
             // the frames of the chunk's live octants, one ahead in registers
             constexpr int RPL = (P + 63) / 64;
             T fq[RPL][5];
+            int fo_ord[CMP ? RPL : 1];
             auto load_frame = [&](int o) {
                 const int f = sfr[o];
 #pragma unroll
@@ -2299,6 +2319,7 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
                     fq[h][2] = frt[3 * e + 2];
                     fq[h][3] = frr[2 * e];
                     fq[h][4] = conj_sign * frr[2 * e + 1];
+                    if constexpr (CMP) fo_ord[h] = Lc.fr_order[e];
                 }
             };
             auto next_live = [&](int o) {
@@ -2320,6 +2341,7 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
                         rt[2][nu] = fq[h][2];
                         rg[0][nu] = fq[h][3];
                         rg[1][nu] = fq[h][4];
+                        if constexpr (CMP) sord[nu] = (uint8_t)fo_ord[h];
                     }
                 }
                 on = next_live(o + 1);
@@ -2327,7 +2349,7 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
                 const int e_lo = sgo[o] - e0, e_hi = sgo[o + 1] - e0;
                 if (e_lo < e_hi) fetch_b(e_lo);
                 wave_lds_fence();
-                const uint8_t* ord = &sord[o * P];
+                const uint8_t* ord = &sord[CMP ? 0 : o * P];
                 for (int ei = e_lo; ei < e_hi; ++ei) {
                     const int info = einfo[ei];
                     const int g0 = info & 255, cnt = (info >> 8) & 255;
@@ -2365,8 +2387,8 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
                                     const int nu = ord[g0 + ri];
                                     const T vr = c[0][i], vi = c[NT - 1][i];
                                     const T gr = rg[0][nu], gi = rg[1][nu];
-                                    acc[nu * AS + col] += vr * gr - vi * gi;
-                                    acc[nu * AS + 16 + col] += vr * gi + vi * gr;
+                                    acc[aix(nu, col)] += vr * gr - vi * gi;
+                                    acc[aix(nu, 16 + col)] += vr * gi + vi * gr;
                                 }
                             }
                         }
@@ -2382,9 +2404,12 @@ k_child_to_parent_boxacc(KernelConsts kc, LevelDev Lc, LevelDev Lp, const cpx<T>
             const int nu = i / CP, cc = i - nu * CP;
             const int bl = cc / RB, r = cc - bl * RB;
             const int bi = b0 + bl;
-            const int s = bi < kBoxTile ? bslot[bi] : -1;
+            int sv = -1;
+            if constexpr (CMP) sv = __shfl(my_slot, bi & (kBoxTile - 1), 64);
+            else sv = bi < kBoxTile ? bslot[bi] : -1;
+            const int s = bi < kBoxTile ? sv : -1;
             const int ir = HALF ? 2 * cc : cc, ii = HALF ? 2 * cc + 1 : 16 + cc;
-            if (s >= 0) Fp[((size_t)s * P + nu) * RB + r] = cpx<T>{acc[nu * AS + ir], acc[nu * AS + ii]};
+            if (s >= 0) Fp[((size_t)s * P + nu) * RB + r] = cpx<T>{acc[aix(nu, ir)], acc[aix(nu, ii)]};
         }
         wave_lds_fence();
     }
@@ -2974,6 +2999,14 @@ constexpr double half_entries()
     return std::is_same<T, double>::value ? 16.0 : 20.0;
 }
 
+// FP64 box kernel in its compact LDS layout (seven wavefronts per CU) on the
+// levels whose frames allow it (IFGF_BOXACC_COMPACT=0: never).
+inline bool boxacc_compact()
+{
+    const char* v = std::getenv("IFGF_BOXACC_COMPACT");
+    return !(v && *v && std::atoi(v) == 0);
+}
+
 // Least average number of slots per box tile (as a fraction of kBoxTile) for
 // which the default rule picks the box-batched child-to-parent kernel (never
 // for 16 right-hand sides, where the autotuner decides); IFGF_BOX_FILL
@@ -3107,6 +3140,13 @@ void c2p_launch(DevicePlan& p, const KernelConsts& kc, int d, int variant, hipSt
             break;
         case kC2PBoxAcc:
             if constexpr (PA >= 4 && P <= 128) {
+                if constexpr (std::is_same<T, double>::value) {
+                    if (p.hp.L[d].fr_max_groups <= kCompactEnt && boxacc_compact()) {
+                        k_child_to_parent_boxacc<T, PS, PA, RB, false, true><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
+                            kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
+                        return;
+                    }
+                }
                 k_child_to_parent_boxacc<T, PS, PA, RB, false><<<(unsigned)p.L[d].ntiles, 64, 0, st>>>(
                     kc, p.L[d], p.L[d - 1], Fc, Fp, (const C*)p.zero_cone);
                 return;

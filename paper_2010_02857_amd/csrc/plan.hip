@@ -381,6 +381,8 @@ void build_frames(HostPlan& hp, int d)
         L.fr_ngrp[f] = (uint8_t)ng;
     }, 256);
     L.frame_groups_ok = too_many.load() == 0 && P <= 255;
+    L.fr_max_groups = 0;
+    for (int64_t f = 0; f < L.nframes; ++f) L.fr_max_groups = std::max<int>(L.fr_max_groups, L.fr_ngrp[f]);
     if (!L.frame_groups_ok) return;
     // the points of each frame ordered by group (for tiles of one child cone)
     L.fr_order.assign((size_t)L.nframes * P, 0);

@@ -436,6 +436,36 @@ def test_every_child_to_parent_variant(torch, prec, nrhs):
         plan.set_kernel_choice(nrhs, {2: "geometry"})
 
 
+@pytest.mark.parametrize("nrhs", [1, 4, 16])
+def test_fp64_box_kernel_layouts(torch, monkeypatch, nrhs):
+    """The FP64 box kernel forced at every level where it applies, in its
+    compact LDS layout (seven wavefronts per CU, taken where frames touch at
+    most 24 child cones) and in the padded one (IFGF_BOXACC_COMPACT=0):
+    forward and adjoint match the oracle, and the two layouts agree."""
+    p = inputs.cube_sphere(20)
+    k = 5.0 * math.pi
+    a = inputs.densities(19, nrhs, p.shape[0])
+    ref = oracle.ifgf(p, a, k)["out"]
+    ref_adj = np.conj(oracle.ifgf(p, np.conj(a), k)["out"])
+    plan = make_plan(p, k, "fp64", max_nrhs=16)
+    cand = plan.kernel_candidates(nrhs)
+    levels = {d: "box_acc" for d, names in cand.items() if "box_acc" in names}
+    assert levels
+    plan.set_kernel_choice(nrhs, levels)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("IFGF_BOXACC_COMPACT", flag)
+        print(f"box kernel compact={flag} at levels {sorted(levels)}", flush=True)
+        out = plan.apply(dev(torch, a, "fp64")).cpu().numpy()
+        adj = plan.adjoint(dev(torch, a, "fp64")).cpu().numpy()
+        assert par(out, ref) < FP64_TOL
+        assert par(adj, ref_adj) < FP64_TOL
+        outs.append(out)
+    assert par(outs[0], outs[1]) < 1e-14
+    assert plan.misses() == 0
+    monkeypatch.delenv("IFGF_BOXACC_COMPACT")
+
+
 @pytest.mark.parametrize("prec,nrhs,store", [("mixed", 1, 0), ("mixed", 1, 1), ("fp64", 1, 0), ("mixed", 16, 0),
                                               ("fp64", 4, 1)])
 def test_side_stream_matches_one_stream(torch, prec, nrhs, store, monkeypatch):
