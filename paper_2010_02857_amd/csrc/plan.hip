@@ -286,16 +286,53 @@ void build_frames(HostPlan& hp, int d)
     L.child_of.assign((size_t)Lp.nbox * 8, -1);
     for (int64_t k = 0; k < L.nbox; ++k)
         if (L.active[k]) L.child_of[(size_t)L.parent[k] * 8 + L.box_oct[k]] = (int32_t)k;
+    // the distinct (parent cone, octant) keys in increasing order: marked in a
+    // bit set over the key space and read back in order (a sort where that
+    // space is too large for one)
+    const uint64_t kspace = (uint64_t)Lp.ncell * (uint64_t)Lp.ns * 8u;
+    const bool bitset = kspace <= ((uint64_t)1 << 33);
     std::vector<uint64_t> keys;
-    keys.reserve((size_t)Lp.nslots * 4);
-    for (int64_t sl = 0; sl < Lp.nslots; ++sl) {
-        int32_t j = Lp.slot_box[sl];
-        for (int o = 0; o < 8; ++o)
-            if (L.child_of[(size_t)j * 8 + o] >= 0) keys.push_back((uint64_t)Lp.slot_cone[sl] * 8 + o);
+    std::vector<uint64_t> kbits;
+    std::vector<int64_t> kbase;
+    if (bitset) {
+        const int64_t nw = (int64_t)((kspace + 63) / 64);
+        kbits.assign((size_t)nw, 0);
+        std::atomic<int64_t> np{0};
+        parallel_for(Lp.nslots, [&](int64_t sl) {
+            const int32_t j = Lp.slot_box[sl];
+            int c = 0;
+            for (int o = 0; o < 8; ++o)
+                if (L.child_of[(size_t)j * 8 + o] >= 0) {
+                    const uint64_t key = (uint64_t)Lp.slot_cone[sl] * 8 + o;
+                    __atomic_fetch_or(&kbits[key >> 6], 1ull << (key & 63), __ATOMIC_RELAXED);
+                    ++c;
+                }
+            if (c) np.fetch_add(c, std::memory_order_relaxed);
+        }, 1024);
+        L.npairs = np.load();
+        kbase.assign((size_t)nw + 1, 0);
+        for (int64_t w = 0; w < nw; ++w) kbase[w + 1] = kbase[w] + __builtin_popcountll(kbits[w]);
+        keys.resize((size_t)kbase[nw]);
+        parallel_for(nw, [&](int64_t w) {
+            uint64_t m = kbits[w];
+            int64_t i = kbase[w];
+            while (m) {
+                const int b = __builtin_ctzll(m);
+                keys[(size_t)i++] = (uint64_t)w * 64 + (uint64_t)b;
+                m &= m - 1;
+            }
+        }, 4096);
+    } else {
+        keys.reserve((size_t)Lp.nslots * 4);
+        for (int64_t sl = 0; sl < Lp.nslots; ++sl) {
+            int32_t j = Lp.slot_box[sl];
+            for (int o = 0; o < 8; ++o)
+                if (L.child_of[(size_t)j * 8 + o] >= 0) keys.push_back((uint64_t)Lp.slot_cone[sl] * 8 + o);
+        }
+        L.npairs = (int64_t)keys.size();
+        parallel_sort(keys);
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
     }
-    L.npairs = (int64_t)keys.size();
-    parallel_sort(keys);
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
     L.nframes = (int64_t)keys.size();
     g_clock.lap("    frame keys");
     // tabulate when frames are shared at least 4x, or when the table is small
@@ -315,7 +352,11 @@ void build_frames(HostPlan& hp, int d)
         for (int o = 0; o < 8; ++o)
             if (L.child_of[(size_t)j * 8 + o] >= 0) {
                 uint64_t key = (uint64_t)Lp.slot_cone[sl] * 8 + o;
-                L.pframe[(size_t)sl * 8 + o] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), key) - keys.begin());
+                // the key's rank among the distinct keys
+                L.pframe[(size_t)sl * 8 + o] =
+                    bitset ? (int32_t)(kbase[key >> 6] +
+                                       __builtin_popcountll(kbits[key >> 6] & ((1ull << (key & 63)) - 1ull)))
+                           : (int32_t)(std::lower_bound(keys.begin(), keys.end(), key) - keys.begin());
             }
     }, 1024);
     g_clock.lap("    frame of each slot");
