@@ -11,6 +11,9 @@
 #include <numeric>
 #include <thread>
 
+#include <sys/mman.h>
+
+#include "host_mem.hpp"
 #include "ifgf_internal.hpp"
 
 namespace ifgf {
@@ -68,6 +71,28 @@ void parallel_for(int64_t n, F&& f, int64_t grain = 1)
     work();
     for (auto& t : th) t.join();
 }
+
+}  // namespace
+
+void map_pages(void* p, size_t bytes)
+{
+    if (bytes < ((size_t)16 << 20)) return;
+    const uintptr_t pg = 4096, huge = (uintptr_t)2 << 20, chunk = (uintptr_t)32 << 20;
+    const uintptr_t a = ((uintptr_t)p + pg - 1) & ~(pg - 1);
+    const uintptr_t b = ((uintptr_t)p + bytes) & ~(pg - 1);
+    if (b <= a) return;
+    madvise((void*)a, b - a, MADV_HUGEPAGE);
+    // chunks aligned to the huge page, one thread each
+    const uintptr_t a0 = a & ~(huge - 1);
+    const int64_t nchunk = (int64_t)((b - a0 + chunk - 1) / chunk);
+    parallel_for(nchunk, [&](int64_t c) {
+        const uintptr_t s = std::max(a, a0 + (uintptr_t)c * chunk);
+        const uintptr_t e = std::min(b, a0 + (uintptr_t)(c + 1) * chunk);
+        if (s < e) madvise((void*)s, e - s, MADV_POPULATE_WRITE);
+    });
+}
+
+namespace {
 
 // Stable sort by `less`: chunks sorted on the thread pool, then merged
 // pairwise in rounds (each round's merges in parallel; merging keeps the
@@ -183,8 +208,11 @@ void build_pairs(HostPlan& hp, int d)
     HostLevel& L = hp.L[d];
     pair_offsets(L);
     const int64_t np = L.pair_base[L.nbox];
+    reserve_mapped(L.pr_slot, np);
     L.pr_slot.assign(np, -1);
+    reserve_mapped(L.pr_t, (size_t)3 * np);
     L.pr_t.assign((size_t)3 * np, 0.0);
+    reserve_mapped(L.pr_g, (size_t)2 * np);
     L.pr_g.assign((size_t)2 * np, 0.0);
     const double kappa = hp.kappa;
     const double inv4pi = 1.0 / (4.0 * kPi);
@@ -228,7 +256,9 @@ void build_pair_order(HostLevel& L)
     for (int64_t s = 0; s < L.nslots; ++s)
         start[(size_t)s + 1] = start[(size_t)s] + (cnt[(size_t)s] + kPairQuad - 1) / kPairQuad * kPairQuad;
     const int64_t no = start[(size_t)L.nslots];
+    reserve_mapped(L.pr_order, (size_t)no);
     L.pr_order.assign((size_t)no, -1);
+    reserve_mapped(L.pro_slot, (size_t)no);
     L.pro_slot.assign((size_t)no, 0);
     for (int64_t s = 0; s < L.nslots; ++s)
         for (int64_t i = start[(size_t)s]; i < start[(size_t)s + 1]; ++i) L.pro_slot[(size_t)i] = (int32_t)s;
@@ -237,7 +267,9 @@ void build_pair_order(HostLevel& L)
         for (int64_t e = 0; e < np; ++e)
             if (L.pr_slot[e] >= 0) L.pr_order[(size_t)pos[(size_t)L.pr_slot[e]]++] = (int32_t)e;
     }
+    reserve_mapped(L.pro_t, (size_t)3 * no);
     L.pro_t.assign((size_t)3 * no, 0.0);
+    reserve_mapped(L.pro_g, (size_t)2 * no);
     L.pro_g.assign((size_t)2 * no, 0.0);
     parallel_for(no, [&](int64_t i) {
         const int64_t e = L.pr_order[(size_t)i];
@@ -283,6 +315,7 @@ void build_frames(HostPlan& hp, int d)
     HostLevel& L = hp.L[d];
     const HostLevel& Lp = hp.L[d - 1];
     const int P = hp.P, ps = hp.ps, pang = hp.pang;
+    reserve_mapped(L.child_of, (size_t)Lp.nbox * 8);
     L.child_of.assign((size_t)Lp.nbox * 8, -1);
     for (int64_t k = 0; k < L.nbox; ++k)
         if (L.active[k]) L.child_of[(size_t)L.parent[k] * 8 + L.box_oct[k]] = (int32_t)k;
@@ -297,19 +330,26 @@ void build_frames(HostPlan& hp, int d)
     if (bitset) {
         const int64_t nw = (int64_t)((kspace + 63) / 64);
         kbits.assign((size_t)nw, 0);
-        std::atomic<int64_t> np{0};
         parallel_for(Lp.nslots, [&](int64_t sl) {
             const int32_t j = Lp.slot_box[sl];
-            int c = 0;
             for (int o = 0; o < 8; ++o)
                 if (L.child_of[(size_t)j * 8 + o] >= 0) {
                     const uint64_t key = (uint64_t)Lp.slot_cone[sl] * 8 + o;
-                    __atomic_fetch_or(&kbits[key >> 6], 1ull << (key & 63), __ATOMIC_RELAXED);
-                    ++c;
+                    uint64_t* w = &kbits[key >> 6];
+                    const uint64_t bit = 1ull << (key & 63);
+                    // most keys recur: set a bit only where it is still clear
+                    // (a read leaves the word shared between the threads)
+                    if (!(__atomic_load_n(w, __ATOMIC_RELAXED) & bit)) __atomic_fetch_or(w, bit, __ATOMIC_RELAXED);
                 }
-            if (c) np.fetch_add(c, std::memory_order_relaxed);
         }, 1024);
-        L.npairs = np.load();
+        // every slot of box j pairs with each of j's children
+        int64_t np = 0;
+        for (int64_t j = 0; j < Lp.nbox; ++j) {
+            int c = 0;
+            for (int o = 0; o < 8; ++o) c += L.child_of[(size_t)j * 8 + o] >= 0;
+            np += (int64_t)c * (Lp.slot_start[j + 1] - Lp.slot_start[j]);
+        }
+        L.npairs = np;
         kbase.assign((size_t)nw + 1, 0);
         for (int64_t w = 0; w < nw; ++w) kbase[w + 1] = kbase[w] + __builtin_popcountll(kbits[w]);
         keys.resize((size_t)kbase[nw]);
@@ -346,6 +386,7 @@ void build_frames(HostPlan& hp, int d)
         L.nframes = 0;
         return;
     }
+    reserve_mapped(L.pframe, (size_t)Lp.nslots * 8);
     L.pframe.assign((size_t)Lp.nslots * 8, -1);
     parallel_for(Lp.nslots, [&](int64_t sl) {
         int32_t j = Lp.slot_box[sl];
@@ -360,8 +401,11 @@ void build_frames(HostPlan& hp, int d)
             }
     }, 1024);
     g_clock.lap("    frame of each slot");
+    reserve_mapped(L.fr_key, (size_t)L.nframes * P);
     L.fr_key.resize((size_t)L.nframes * P);
+    reserve_mapped(L.fr_t, (size_t)L.nframes * P * 3);
     L.fr_t.resize((size_t)L.nframes * P * 3);
+    reserve_mapped(L.fr_ratio, (size_t)L.nframes * P * 2);
     L.fr_ratio.resize((size_t)L.nframes * P * 2);
     const double kappa = hp.kappa;
     parallel_for(L.nframes, [&](int64_t f) {
@@ -400,7 +444,9 @@ void build_frames(HostPlan& hp, int d)
     g_clock.lap("    frame geometry");
     // groups: distinct child cones per frame, in order of first appearance
     L.fr_ngrp.assign(L.nframes, 0);
+    reserve_mapped(L.fr_gkey, (size_t)L.nframes * kMaxFrameGroups);
     L.fr_gkey.assign((size_t)L.nframes * kMaxFrameGroups, 0);
+    reserve_mapped(L.fr_grp, (size_t)L.nframes * P);
     L.fr_grp.assign((size_t)L.nframes * P, 0);
     std::atomic<int> too_many{0};
     parallel_for(L.nframes, [&](int64_t f) {
@@ -426,6 +472,7 @@ void build_frames(HostPlan& hp, int d)
     for (int64_t f = 0; f < L.nframes; ++f) L.fr_max_groups = std::max<int>(L.fr_max_groups, L.fr_ngrp[f]);
     if (!L.frame_groups_ok) return;
     // the points of each frame ordered by group (for tiles of one child cone)
+    reserve_mapped(L.fr_order, (size_t)L.nframes * P);
     L.fr_order.assign((size_t)L.nframes * P, 0);
     L.fr_goff.assign((size_t)L.nframes * (kMaxFrameGroups + 1), 0);
     parallel_for(L.nframes, [&](int64_t f) {
@@ -455,10 +502,9 @@ void build_frames(HostPlan& hp, int d)
     const int mode = tile_sort();
     std::vector<std::vector<int32_t>> btiles(nblk);   // kBoxTile entries per tile, -1 padded
     std::vector<int64_t> bt(nblk + 1, 0);
-    auto mask = [&](int32_t sl) {
-        int m = 0;
-        for (int o = 0; o < 8; ++o) m |= (L.child_of[(size_t)Lp.slot_box[sl] * 8 + o] >= 0) << o;
-        return m;
+    struct SlotKey {
+        uint64_t k;   // parent cone << 8 | child mask (0 in mode 0)
+        int32_t s;    // slot, which breaks ties in the order of the slots
     };
     // a run's tiles as kBoxTile entries each (-1 padded); cost = the octant
     // passes they run
@@ -472,14 +518,30 @@ void build_frames(HostPlan& hp, int d)
     // blocks one after the other, each block's sort and runs on all threads
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t j0 = b * blk, j1 = std::min<int64_t>(Lp.nbox, j0 + blk);
-        std::vector<int32_t> v((size_t)(Lp.slot_start[j1] - Lp.slot_start[j0]));
-        std::iota(v.begin(), v.end(), Lp.slot_start[j0]);
-        parallel_stable_sort(v, [&](int32_t x, int32_t y) {
-            if (Lp.slot_cone[x] != Lp.slot_cone[y]) return Lp.slot_cone[x] < Lp.slot_cone[y];
-            return mode != 0 && mask(x) < mask(y);
-        });
-        std::vector<int> mk(v.size());
-        parallel_for((int64_t)v.size(), [&](int64_t k) { mk[k] = mask(v[k]); }, 4096);
+        const int32_t s0 = Lp.slot_start[j0];
+        const int64_t nsb = Lp.slot_start[j1] - s0;
+        // the children of each box of the block (bit o: a child in octant o)
+        std::vector<uint8_t> bm((size_t)(j1 - j0));
+        parallel_for(j1 - j0, [&](int64_t j) {
+            int m = 0;
+            for (int o = 0; o < 8; ++o) m |= (L.child_of[(size_t)(j0 + j) * 8 + o] >= 0) << o;
+            bm[j] = (uint8_t)m;
+        }, 1024);
+        auto mask = [&](int32_t sl) { return (int)bm[Lp.slot_box[sl] - j0]; };
+        // the block's slots by parent cone, then (unless mode 0) child mask,
+        // in slot order among equals
+        std::vector<SlotKey> sk((size_t)nsb);
+        parallel_for(nsb, [&](int64_t i) {
+            const int32_t sl = s0 + (int32_t)i;
+            sk[i] = SlotKey{((uint64_t)(uint32_t)Lp.slot_cone[sl] << 8) | (uint64_t)(mode != 0 ? mask(sl) : 0), sl};
+        }, 4096);
+        parallel_stable_sort(sk, [](const SlotKey& x, const SlotKey& y) { return x.k != y.k ? x.k < y.k : x.s < y.s; });
+        std::vector<int32_t> v((size_t)nsb);
+        std::vector<int> mk((size_t)nsb);
+        parallel_for(nsb, [&](int64_t k) {
+            v[k] = sk[k].s;
+            mk[k] = mask(sk[k].s);
+        }, 4096);
         // runs of one parent cone
         std::vector<size_t> run{0};
         for (size_t k = 1; k < v.size(); ++k)
@@ -553,6 +615,7 @@ void build_frames(HostPlan& hp, int d)
     }
     for (int64_t b = 0; b < nblk; ++b) bt[b + 1] += bt[b];
     L.ntiles = bt[nblk];
+    reserve_mapped(L.bt_slot, (size_t)L.ntiles * kBoxTile);
     L.bt_slot.assign((size_t)L.ntiles * kBoxTile, -1);
     L.bt_frame.assign((size_t)L.ntiles * 8, -1);
     parallel_for(nblk, [&](int64_t b) {
@@ -595,7 +658,9 @@ void build_tile_entries(HostPlan& hp, int d)
     L.te_per_tile = nt > 0 ? (double)ne / (double)nt : 0.0;
     L.te_go.assign((size_t)nt * 9, 0);
     L.te_mask.assign((size_t)nt * kBoxTile, 0);
+    reserve_mapped(L.te_info, (size_t)ne);
     L.te_info.assign((size_t)ne, 0);
+    reserve_mapped(L.te_cs, (size_t)ne * kBoxTile);
     L.te_cs.assign((size_t)ne * kBoxTile, -1);
     parallel_for(nt, [&](int64_t t) {
         int32_t kid[kBoxTile][8];
@@ -1060,9 +1125,13 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
             L.slot_start[b + 1] = L.slot_start[b] + cnt[b];
         }
         L.nslots = L.slot_start[L.nbox];
+        reserve_mapped(L.slot_box, L.nslots);
         L.slot_box.resize(L.nslots);
+        reserve_mapped(L.slot_cone, L.nslots);
         L.slot_cone.resize(L.nslots);
+        reserve_mapped(L.cell_base, (size_t)L.nbox * L.ncell);
         L.cell_base.assign((size_t)L.nbox * L.ncell, 0);
+        reserve_mapped(L.cell_mask, (size_t)L.nbox * L.ncell * L.W);
         L.cell_mask.assign((size_t)L.nbox * L.ncell * L.W, 0);
         parallel_for(L.nbox, [&](int64_t b) {
             const uint64_t* P = &prim[(size_t)b * wpb];

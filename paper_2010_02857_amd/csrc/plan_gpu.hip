@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "host_mem.hpp"
 #include "ifgf_internal.hpp"
 
 namespace ifgf {
@@ -264,6 +265,7 @@ class DevBuf {
 template <typename T>
 hipError_t get(std::vector<T>& v, const DevBuf& b, size_t n)
 {
+    reserve_mapped(v, n);
     v.resize(n);
     if (n == 0) return hipSuccess;
     return hipMemcpy(v.data(), b.as<T>(), n * sizeof(T), hipMemcpyDeviceToHost);
