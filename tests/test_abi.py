@@ -189,3 +189,23 @@ def test_distinct_targets_host_plan():
     assert lib.ifgf_plan_create_targets(buf.ctypes.data_as(ctypes.c_void_p), 4,
                                         buf.ctypes.data_as(ctypes.c_void_p), 0, 1.0, 0, None, None,
                                         ctypes.byref(h)) == 1
+
+
+@pytest.mark.parametrize("case", ["cfg1", "adaptive"])
+def test_host_plan_independent_of_thread_count(case, monkeypatch):
+    """The threaded host builder gives the same hierarchy, relevant cones and
+    frames on one thread as on eight (frame keys, tile sorts and page mapping
+    are split over the thread pool)."""
+    if case == "cfg1":
+        w = inputs.WORKLOADS[1]
+        p, k, kw = w.points(), w.kappa, {}
+    else:
+        p, k, kw = inputs.graded_sphere(18), 10.0, {"levels": 6, "leaf_max": 6}
+    got = []
+    for threads in ("1", "8"):
+        monkeypatch.setenv("IFGF_HOST_THREADS", threads)
+        st = ifgf.Plan(p, k, host_only=True, **kw).stats()
+        st.pop("t_plan_s")
+        got.append(st)
+    assert got[0] == got[1]
+    assert any(f > 0 for f in got[0]["n_frames"])
