@@ -50,9 +50,15 @@ struct Marks {
     double h, ds, dang;
 };
 
+// Marks only ever set bits, so a bit seen set is set for good: most marks
+// repeat one (every interpolation point of a box's parent cones falls into a
+// few of its cones) and end with that load, instead of queueing atomics on
+// the few words of one box.
 __device__ inline void set_bit(unsigned long long* w, int64_t bit)
 {
-    atomicOr(w + (bit >> 6), 1ull << (bit & 63));
+    unsigned long long* a = w + (bit >> 6);
+    const unsigned long long m = 1ull << (bit & 63);
+    if (!(__hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & m)) atomicOr(a, m);
 }
 
 // The cone of a query point, and with dilation the cones on the other side
