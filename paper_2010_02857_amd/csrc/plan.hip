@@ -781,14 +781,23 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         box_index(&points[3 * i], hp.corner, HD, nbD, &kD[3 * i]);
         mort[i] = interleave3(kD[3 * i], kD[3 * i + 1], kD[3 * i + 2], bits);
     }, 4096);
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        if (mort[a] != mort[b]) return mort[a] < mort[b];
+    // (code, point) pairs sorted on the thread pool; the order is total, so
+    // the permutation is the one any sort gives
+    struct MortonKey {
+        uint64_t code;
+        int32_t i;
+    };
+    std::vector<MortonKey> mo((size_t)n);
+    parallel_for(n, [&](int64_t i) { mo[i] = MortonKey{mort[i], (int32_t)i}; }, 4096);
+    parallel_stable_sort(mo, [&](const MortonKey& x, const MortonKey& y) {
+        if (x.code != y.code) return x.code < y.code;
         for (int c = 0; c < 3; ++c)
-            if (points[3 * a + c] != points[3 * b + c]) return points[3 * a + c] < points[3 * b + c];
-        return a < b;
+            if (points[3 * x.i + c] != points[3 * y.i + c]) return points[3 * x.i + c] < points[3 * y.i + c];
+        return x.i < y.i;
     });
+    std::vector<int32_t> order(n);
+    parallel_for(n, [&](int64_t i) { order[i] = mo[i].i; }, 4096);
+    std::vector<MortonKey>().swap(mo);
     for (int64_t i = 1; i < n; ++i) {
         int32_t a = order[i - 1], b = order[i];
         if (mort[a] == mort[b] && points[3 * a] == points[3 * b] && points[3 * a + 1] == points[3 * b + 1] &&
@@ -799,13 +808,13 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
     hp.pts.resize(3 * n);
     std::vector<uint64_t> mcode(n);
     std::vector<int64_t> mk(3 * n);
-    for (int64_t i = 0; i < n; ++i) {
+    parallel_for(n, [&](int64_t i) {
         for (int a = 0; a < 3; ++a) {
             hp.pts[3 * i + a] = points[3 * order[i] + a];
             mk[3 * i + a] = kD[3 * order[i] + a];
         }
         mcode[i] = mort[order[i]];
-    }
+    }, 4096);
 
     phase("Morton sort");
     // Relevant boxes of every level: unique Morton prefixes.
