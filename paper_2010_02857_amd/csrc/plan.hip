@@ -933,8 +933,8 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
         L.cou_start.assign(L.nbox + 1, 0);
         if (d < 3) continue;
         const HostLevel& Lp = hp.L[d - 1];
-        std::vector<std::vector<int32_t>> lists(L.nbox);
-        parallel_for(L.nbox, [&](int64_t b) {
+        // the cousins of box b, in order, to f
+        auto each_cousin = [&](int64_t b, auto&& f) {
             int64_t k[3];
             deinterleave3(L.prefix[b], d - 1, k);
             int32_t p = L.parent[b];
@@ -945,10 +945,28 @@ std::string build_host_plan(const double* points, int64_t n, double kappa, int l
                     deinterleave3(L.prefix[c], d - 1, kc);
                     if (std::llabs(kc[0] - k[0]) <= 1 && std::llabs(kc[1] - k[1]) <= 1 && std::llabs(kc[2] - k[2]) <= 1)
                         continue;
-                    lists[b].push_back(c);
+                    f((int32_t)c);
                 }
             }
-        }, 64);
+        };
+        if (!hp.adaptive) {
+            // counted, then written in place, both on the thread pool
+            parallel_for(L.nbox, [&](int64_t b) {
+                int32_t m = 0;
+                each_cousin(b, [&](int32_t) { ++m; });
+                L.cou_start[b + 1] = m;
+            }, 64);
+            for (int64_t b = 0; b < L.nbox; ++b) L.cou_start[b + 1] += L.cou_start[b];
+            reserve_mapped(L.cou, (size_t)L.cou_start[L.nbox]);
+            L.cou.resize(L.cou_start[L.nbox]);
+            parallel_for(L.nbox, [&](int64_t b) {
+                int32_t* o = L.cou.data() + L.cou_start[b];
+                each_cousin(b, [&](int32_t c) { *o++ = c; });
+            }, 64);
+            continue;
+        }
+        std::vector<std::vector<int32_t>> lists(L.nbox);
+        parallel_for(L.nbox, [&](int64_t b) { each_cousin(b, [&](int32_t c) { lists[b].push_back(c); }); }, 64);
         if (hp.adaptive) {
             // rule (i) of an active box reads all its cousins; the evaluation
             // at the targets of a box reads its cousins that are source boxes
