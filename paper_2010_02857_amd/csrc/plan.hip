@@ -530,18 +530,49 @@ void build_frames(HostPlan& hp, int d)
         auto mask = [&](int32_t sl) { return (int)bm[Lp.slot_box[sl] - j0]; };
         // the block's slots by parent cone, then (unless mode 0) child mask,
         // in slot order among equals
-        std::vector<SlotKey> sk((size_t)nsb);
-        parallel_for(nsb, [&](int64_t i) {
-            const int32_t sl = s0 + (int32_t)i;
-            sk[i] = SlotKey{((uint64_t)(uint32_t)Lp.slot_cone[sl] << 8) | (uint64_t)(mode != 0 ? mask(sl) : 0), sl};
-        }, 4096);
-        parallel_stable_sort(sk, [](const SlotKey& x, const SlotKey& y) { return x.k != y.k ? x.k < y.k : x.s < y.s; });
         std::vector<int32_t> v((size_t)nsb);
+        const int64_t ncone = (int64_t)Lp.ncell * Lp.ns;
+        const int nch = host_threads();
+        if (ncone * nch <= ((int64_t)1 << 24)) {
+            // two stable counting sorts over nch chunks (a histogram per
+            // chunk): by child mask (unless mode 0), then by cone
+            std::vector<int64_t> hist((size_t)(nch * std::max<int64_t>(ncone, 256)));
+            auto csort = [&](const int32_t* src, int32_t* dst, int64_t nkey, auto&& key) {
+                std::fill(hist.begin(), hist.begin() + nch * nkey, 0);
+                parallel_for(nch, [&](int64_t c) {
+                    int64_t* hc = &hist[(size_t)(c * nkey)];
+                    for (int64_t i = nsb * c / nch; i < nsb * (c + 1) / nch; ++i) hc[key(src[i])]++;
+                });
+                int64_t off = 0;
+                for (int64_t q = 0; q < nkey; ++q)
+                    for (int c = 0; c < nch; ++c) {
+                        const int64_t t = hist[(size_t)(c * nkey + q)];
+                        hist[(size_t)(c * nkey + q)] = off;
+                        off += t;
+                    }
+                parallel_for(nch, [&](int64_t c) {
+                    int64_t* hc = &hist[(size_t)(c * nkey)];
+                    for (int64_t i = nsb * c / nch; i < nsb * (c + 1) / nch; ++i) dst[hc[key(src[i])]++] = src[i];
+                });
+            };
+            std::vector<int32_t> w((size_t)nsb);
+            std::iota(w.begin(), w.end(), s0);
+            if (mode != 0) {
+                csort(w.data(), v.data(), 256, [&](int32_t sl) { return mask(sl); });
+                w.swap(v);
+            }
+            csort(w.data(), v.data(), ncone, [&](int32_t sl) { return (int64_t)Lp.slot_cone[sl]; });
+        } else {
+            std::vector<SlotKey> sk((size_t)nsb);
+            parallel_for(nsb, [&](int64_t i) {
+                const int32_t sl = s0 + (int32_t)i;
+                sk[i] = SlotKey{((uint64_t)(uint32_t)Lp.slot_cone[sl] << 8) | (uint64_t)(mode != 0 ? mask(sl) : 0), sl};
+            }, 4096);
+            parallel_stable_sort(sk, [](const SlotKey& x, const SlotKey& y) { return x.k != y.k ? x.k < y.k : x.s < y.s; });
+            parallel_for(nsb, [&](int64_t k) { v[k] = sk[k].s; }, 4096);
+        }
         std::vector<int> mk((size_t)nsb);
-        parallel_for(nsb, [&](int64_t k) {
-            v[k] = sk[k].s;
-            mk[k] = mask(sk[k].s);
-        }, 4096);
+        parallel_for(nsb, [&](int64_t k) { mk[k] = mask(v[k]); }, 4096);
         // runs of one parent cone
         std::vector<size_t> run{0};
         for (size_t k = 1; k < v.size(); ++k)
